@@ -1,0 +1,161 @@
+/*
+ * mess.h — C ABI of the MI355X (gfx950) Gaussian-basis Hartree-Fock hot path.
+ *
+ * The library computes what section 3 of the MESS paper ("Electronic
+ * Structure Theory in a Nutshell") states as the problem: given atoms
+ * (atomic numbers and positions) and a basis of contracted Gaussian atomic
+ * orbitals on them (eq. 1), build the overlap matrix (eq. 3) and the other
+ * closed-form Gaussian integrals, the Coulomb/exchange matrices J and K from
+ * a density matrix, and iterate the Roothaan equation (eq. 2) to
+ * self-consistency, returning energies (electronic + nuclear, as in the
+ * paper's examples of section 5).
+ *
+ * Conventions (all entry points):
+ *  - Units: bohr and hartree.
+ *  - Basis: contracted Cartesian shells with l in {0,1,2}.  Components of a
+ *    shell are ordered x-major lexicographically (p: x,y,z; d: xx,xy,xz,yy,
+ *    yz,zz) and every Cartesian function is normalised to unit
+ *    self-overlap.  Contraction coefficients multiply normalised
+ *    primitives; the contracted function is then renormalised.
+ *  - Basis functions are numbered shell by shell in the order given.
+ *  - Matrices are N x N, row-major, contiguous, FP64, in DEVICE memory
+ *    (hipMalloc'd or torch CUDA tensors).  Atom and shell arrays are HOST
+ *    memory and are copied at create time.
+ *  - D is the total closed-shell density, D = 2 C_occ C_occ^T (symmetric).
+ *  - J_ij = sum_kl (ij|kl) D_kl,   K_ij = sum_kl (ik|jl) D_kl.
+ *  - Every call returns a status code.  On error nothing is written to
+ *    outputs that were not already written, handles stay valid and usable,
+ *    and mess_last_error() returns a message (thread-local).
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = null stream).
+ *    Calls that return host scalars (mess_basis_info, mess_scf_step)
+ *    synchronise that stream; the others do not.
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef MESS_H
+#define MESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mess_basis mess_basis;
+typedef struct mess_scf mess_scf;
+typedef void *mess_stream;
+
+enum {
+    MESS_OK = 0,
+    MESS_E_ARG = 1,          /* NULL pointer, out-of-range index, non-positive or non-finite value */
+    MESS_E_UNSUPPORTED = 2,  /* l > 2, odd electron count, unknown mode */
+    MESS_E_NOMEM = 3,        /* device allocation failed */
+    MESS_E_DEVICE = 4,       /* HIP runtime error */
+    MESS_E_NUMERIC = 5,      /* ill-conditioned overlap, NaN in a result */
+    MESS_E_SIZE = 6          /* output buffer too small */
+};
+
+enum { MESS_FP64 = 0, MESS_FP32 = 1 };                       /* arithmetic of the ERI path */
+enum { MESS_ERI_DENSE = 0, MESS_ERI_BLOCKS = 1 };            /* mess_eri output layout */
+enum { MESS_JK_DIRECT = 0, MESS_JK_STORED = 1 };             /* mess_jk source of integrals */
+enum { MESS_XC_HF = 0, MESS_XC_LDA_X = 1 };                  /* exchange in the Fock matrix */
+
+typedef struct mess_scf_opts {
+    double schwarz_tol;  /* skip quartet iff Q_ab Q_cd < tol; <= 0 keeps every quartet */
+    double conv_tol;     /* converged when |E_k - E_{k-1}| < conv_tol */
+    int32_t max_iter;    /* informational for callers driving mess_scf_step */
+    int32_t diis_size;   /* Pulay DIIS history length; 0 = plain Roothaan iteration */
+    int32_t prec;        /* MESS_FP64 or MESS_FP32 */
+    int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
+    int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X */
+    int32_t reserved;
+} mess_scf_opts;
+
+/* Build a basis on a molecule (section 3, eq. 1: each atomic orbital sits
+ * on one atom with centre R and atomic number Z).
+ *   n_atoms, Z[n_atoms], xyz_bohr[3*n_atoms]          host arrays
+ *   n_shells, shell_atom/shell_l/shell_nprim[n_shells] host arrays
+ *   exps[sum nprim] > 0, coefs[sum nprim] (raw contraction coefficients)
+ *   charge: molecular charge (electrons = sum Z - charge)
+ * Normalises the basis, builds primitive-pair tables, Schwarz factors of
+ * every shell pair and nuclear repulsion, on the device.
+ * Errors: MESS_E_ARG (NULL, index out of range, exponent <= 0 or not
+ * finite, nprim < 1 or > 16), MESS_E_UNSUPPORTED (l > 2), MESS_E_NOMEM. */
+int mess_basis_create(int32_t n_atoms, const int32_t *Z, const double *xyz_bohr,
+                      int32_t n_shells, const int32_t *shell_atom, const int32_t *shell_l,
+                      const int32_t *shell_nprim, const double *exps, const double *coefs,
+                      int32_t charge, mess_basis **out);
+
+/* Frees every device allocation of the handle.  NULL is a no-op. */
+void mess_basis_destroy(mess_basis *basis);
+
+/* Number of basis functions, occupied orbitals (electrons/2, rounded
+ * down) and nuclear repulsion sum_{A<B} Z_A Z_B / R_AB.  Any output may be
+ * NULL.  Synchronous. */
+int mess_basis_info(const mess_basis *basis, int32_t *nbf, int32_t *n_occ, double *e_nuc);
+
+/* One-electron matrices (section 3, eq. 3 for S; kinetic T and nuclear
+ * attraction V for the core Hamiltonian H = T + V).  Each output is a
+ * device N x N buffer or NULL to skip. */
+int mess_one_electron(const mess_basis *basis, double *S, double *T, double *V, mess_stream stream);
+
+/* Electron-repulsion integrals (mu nu|lambda sigma) over the basis.
+ *   layout MESS_ERI_DENSE: out is a device N^4 FP64 tensor (i slowest);
+ *     every element is written (screened quartets are zero).
+ *     out_bytes must be >= 8 N^4.
+ *   prec: MESS_FP64 (FP32 accepted: integrals computed in FP32, stored
+ *     widened to FP64).
+ *   schwarz_tol: skip quartet iff Q_ab Q_cd < tol (<= 0 keeps all).
+ * Errors: MESS_E_SIZE, MESS_E_UNSUPPORTED (layout), MESS_E_ARG. */
+int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwarz_tol,
+             void *out, size_t out_bytes, mess_stream stream);
+
+/* Coulomb and exchange matrices from a symmetric density D (device N x N):
+ *   J_ij = sum_kl (ij|kl) D_kl,  K_ij = sum_kl (ik|jl) D_kl.
+ * J or K may be NULL to skip.  mode MESS_JK_DIRECT recomputes integrals
+ * over unique shell quartets (8-fold permutational symmetry) with Schwarz
+ * screening and digests them in registers; MESS_JK_STORED computes the
+ * unique blocks once per (basis, prec, tol) and streams them from device
+ * memory on later calls.  prec selects FP64 or FP32 integral arithmetic
+ * (J, K are always returned in FP64). */
+int mess_jk(const mess_basis *basis, const double *D, double *J, double *K,
+            int32_t mode, int32_t prec, double schwarz_tol, mess_stream stream);
+
+/* SCF state for the Roothaan equation (section 3, eq. 2) solved by
+ * fixed-point iteration.  D0: device N x N initial density, or NULL for
+ * the core-Hamiltonian guess.  Errors: MESS_E_UNSUPPORTED (odd electron
+ * count), MESS_E_NUMERIC (overlap too ill-conditioned: lambda_min(S)
+ * below about 1e-7). */
+int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const double *D0,
+                    mess_scf **out);
+
+/* One SCF iteration at the current density D_k:
+ *   J, K <- D_k;  F_k = H + J - K/2;  E_k = 1/2 Tr[D_k (H + F_k)] + E_nuc;
+ *   converged = (k > 0 and |E_k - E_{k-1}| < conv_tol);
+ *   unless converged: DIIS-extrapolated F (if diis_size > 0, once two
+ *   Fock matrices are stored, error X^T (F D S - S D F) X), then
+ *   D_{k+1} = projector onto the n_occ lowest eigenvectors of F in the
+ *   metric S (times 2) becomes the current density.
+ * Outputs (host, any may be NULL): energy E_k, delta_e = E_k - E_{k-1}
+ * (0 at k = 0), resid = max |X^T (F D S - S D F) X|, converged flag.
+ * Synchronises the stream.  Non-convergence is not an error. */
+int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid,
+                  int32_t *converged, mess_stream stream);
+
+/* Copy the current density (device N x N) into D. */
+int mess_scf_density(const mess_scf *scf, double *D, mess_stream stream);
+
+/* Copy the Fock matrix of the last step (device N x N) into F. */
+int mess_scf_fock(const mess_scf *scf, double *F, mess_stream stream);
+
+/* NULL is a no-op. */
+void mess_scf_destroy(mess_scf *scf);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *mess_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESS_H */

@@ -12,24 +12,42 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mess_oracle.c")
-_LIB = os.path.join(_HERE, "libmess_oracle.so")
-_lib = None
+# FP64 oracle, and the same source in x87 extended precision (long double,
+# 64-bit mantissa) used only to arbitrate rounding-level disagreements.
+_LIBS = {"fp64": (os.path.join(_HERE, "libmess_oracle.so"), []),
+         "ext": (os.path.join(_HERE, "libmess_oracle_ext.so"), ["-DOR_REAL=long double"])}
+_lib = {}
+_ext = False
+
+
+class extended_precision:
+    """Context manager: oracle calls inside use the long-double build."""
+
+    def __enter__(self):
+        global _ext
+        self._old, _ext = _ext, True
+
+    def __exit__(self, *a):
+        global _ext
+        _ext = self._old
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the C oracle with gcc (OpenMP), FP64 and extended variants."""
+    for path, defs in _LIBS.values():
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared"] + defs +
+                                  ["-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
+    return _LIBS["fp64"][0]
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    key = "ext" if _ext else "fp64"
+    if key not in _lib:
         build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIBS[key][0])
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
@@ -47,8 +65,8 @@ def lib():
         L.oracle_jk_unique.argtypes = mol + [f64p, ctypes.c_double, f64p, f64p,
                                              ctypes.POINTER(ctypes.c_longlong)]
         L.oracle_jk_elements.argtypes = mol + [f64p, ctypes.c_int, i32p, i32p, f64p, f64p]
-        _lib = L
-    return _lib
+        _lib[key] = L
+    return _lib[key]
 
 
 def _mol_args(m):

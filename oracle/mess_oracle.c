@@ -32,9 +32,18 @@
  * xx, xy, xz, yy, yz, zz.  Matrices are row-major N x N, ERIs are
  * (i j | k l) with i slowest.  Units are bohr and hartree.
  */
-#include <math.h>
 #include <stdlib.h>
+#include <tgmath.h>
 #include <string.h>
+
+/* Arithmetic type: double by default; the test-suite also builds the same
+ * source with -DOR_REAL="long double" as an extended-precision arbiter of
+ * rounding-level differences. */
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+typedef OR_REAL real;
+#define OR_PI ((real)3.14159265358979323846264338327950288L)
 
 #define OR_LMAX 2          /* s, p, d shells */
 #define OR_EMAX 5          /* E tables: i <= l+2 (kinetic), j <= l+2 */
@@ -43,12 +52,12 @@
 
 /* ------------------------------------------------------------------ Boys */
 
-void oracle_boys(int nmax, double T, double *F)
+static void boys_r(int nmax, real T, real *F)
 {
     if (T <= 20.0) {
-        double eT = exp(-T);
+        real eT = exp(-T);
         for (int n = 0; n <= nmax; ++n) {
-            double term = 1.0 / (2.0 * n + 1.0), sum = term;
+            real term = 1.0 / (2.0 * n + 1.0), sum = term;
             for (int k = 1; k < 1000; ++k) {
                 term *= 2.0 * T / (2.0 * n + 2.0 * k + 1.0);
                 sum += term;
@@ -57,8 +66,8 @@ void oracle_boys(int nmax, double T, double *F)
             F[n] = eT * sum;
         }
     } else {
-        double eT = exp(-T);
-        F[0] = 0.5 * sqrt(M_PI / T) * erf(sqrt(T));
+        real eT = exp(-T);
+        F[0] = 0.5 * sqrt(OR_PI / T) * erf(sqrt(T));
         for (int n = 0; n < nmax; ++n)
             F[n + 1] = ((2.0 * n + 1.0) * F[n] - eT) / (2.0 * T);
     }
@@ -66,9 +75,9 @@ void oracle_boys(int nmax, double T, double *F)
 
 /* ----------------------------------------------------------------- basis */
 
-static double dfact(int n) /* n!! for odd n >= -1 */
+static real dfact(int n) /* n!! for odd n >= -1 */
 {
-    double r = 1.0;
+    real r = 1.0;
     for (int k = n; k > 1; k -= 2) r *= k;
     return r;
 }
@@ -92,7 +101,7 @@ typedef struct {
     int *sh_prim;            /* first primitive of each shell */
     int *sh_bf;              /* first basis function of each shell */
     const double *alpha;     /* exponents */
-    double *d;               /* [prim][6]: full coefficient per component */
+    real *d;               /* [prim][6]: full coefficient per component */
 } obasis;
 
 /* Coefficient of primitive p for Cartesian component (lx,ly,lz) such that
@@ -104,24 +113,24 @@ static void normalise_shell(const obasis *B, int s)
     cart_components(l, comp);
     for (int c = 0; c < ncart(l); ++c) {
         int lx = comp[c][0], ly = comp[c][1], lz = comp[c][2];
-        double nprim[32];
+        real nprim[32];
         for (int p = 0; p < np; ++p) {
-            double a = B->alpha[p0 + p];
-            nprim[p] = pow(2.0 * a / M_PI, 0.75) * pow(4.0 * a, 0.5 * l)
+            real a = B->alpha[p0 + p];
+            nprim[p] = pow(2.0 * a / OR_PI, 0.75) * pow(4.0 * a, 0.5 * l)
                        / sqrt(dfact(2 * lx - 1) * dfact(2 * ly - 1) * dfact(2 * lz - 1));
         }
         /* self-overlap of the un-renormalised contraction */
-        double ss = 0.0;
+        real ss = 0.0;
         for (int p = 0; p < np; ++p)
             for (int q = 0; q < np; ++q) {
-                double g = B->alpha[p0 + p] + B->alpha[p0 + q];
-                double ov = pow(M_PI / g, 1.5)
+                real g = B->alpha[p0 + p] + B->alpha[p0 + q];
+                real ov = pow(OR_PI / g, 1.5)
                             * dfact(2 * lx - 1) / pow(2.0 * g, lx)
                             * dfact(2 * ly - 1) / pow(2.0 * g, ly)
                             * dfact(2 * lz - 1) / pow(2.0 * g, lz);
                 ss += B->d[(p0 + p) * 6 + c] * B->d[(p0 + q) * 6 + c] * nprim[p] * nprim[q] * ov;
             }
-        double nc = 1.0 / sqrt(ss);
+        real nc = 1.0 / sqrt(ss);
         for (int p = 0; p < np; ++p) B->d[(p0 + p) * 6 + c] *= nprim[p] * nc;
     }
 }
@@ -141,7 +150,7 @@ static int basis_build(obasis *B, int nat, const int *Z, const double *xyz, int 
         np += sh_np[s]; nbf += ncart(sh_l[s]);
     }
     B->sh_prim[nsh] = np; B->sh_bf[nsh] = nbf; B->nbf = nbf;
-    B->d = (double *)malloc(sizeof(double) * 6 * (np > 0 ? np : 1));
+    B->d = (real *)malloc(sizeof(real) * 6 * (np > 0 ? np : 1));
     for (int p = 0; p < np; ++p)
         for (int c = 0; c < 6; ++c) B->d[p * 6 + c] = coefs[p];
     for (int s = 0; s < nsh; ++s) normalise_shell(B, s);
@@ -157,20 +166,20 @@ static const double *centre(const obasis *B, int s) { return B->xyz + 3 * B->sh_
 
 /* ------------------------------------------------------- Hermite tables */
 
-typedef double Etab[OR_EMAX][OR_EMAX][OR_TMAX];
+typedef real Etab[OR_EMAX][OR_EMAX][OR_TMAX];
 
 /* One Cartesian direction; a on A, b on B, Xab = A - B. */
-static void hermite_E(int imax, int jmax, double a, double b, double Xab, Etab E)
+static void hermite_E(int imax, int jmax, real a, real b, real Xab, Etab E)
 {
-    double p = a + b, mu = a * b / p;
-    double Xpa = -b / p * Xab, Xpb = a / p * Xab;
+    real p = a + b, mu = a * b / p;
+    real Xpa = -b / p * Xab, Xpb = a / p * Xab;
     memset(E, 0, sizeof(Etab));
     E[0][0][0] = exp(-mu * Xab * Xab);
     for (int i = 0; i <= imax; ++i)
         for (int j = 0; j <= jmax; ++j) {
             if (i == 0 && j == 0) continue;
             for (int t = 0; t <= i + j; ++t) {
-                double lo, mid, hi, shift;
+                real lo, mid, hi, shift;
                 if (j == 0) {
                     lo = t > 0 ? E[i - 1][0][t - 1] : 0.0;
                     mid = E[i - 1][0][t];
@@ -187,14 +196,14 @@ static void hermite_E(int imax, int jmax, double a, double b, double Xab, Etab E
         }
 }
 
-typedef double Rtab[OR_RL][OR_RL][OR_RL][OR_RL];   /* [n][t][u][v] */
+typedef real Rtab[OR_RL][OR_RL][OR_RL][OR_RL];   /* [n][t][u][v] */
 
-static void hermite_R(int L, double a, double X, double Y, double Zc, Rtab R)
+static void hermite_R(int L, real a, real X, real Y, real Zc, Rtab R)
 {
-    double T = a * (X * X + Y * Y + Zc * Zc);
-    double F[OR_RL + 1];
-    oracle_boys(L, T, F);
-    double f = 1.0;
+    real T = a * (X * X + Y * Y + Zc * Zc);
+    real F[OR_RL + 1];
+    boys_r(L, T, F);
+    real f = 1.0;
     for (int n = 0; n <= L; ++n) {
         R[n][0][0][0] = f * F[n];
         f *= -2.0 * a;
@@ -204,7 +213,7 @@ static void hermite_R(int L, double a, double X, double Y, double Zc, Rtab R)
             for (int u = 0; u <= L - n - t; ++u)
                 for (int v = 0; v <= L - n - t - u; ++v) {
                     if (t + u + v == 0) continue;
-                    double val;
+                    real val;
                     if (t > 0)
                         val = (t > 1 ? (t - 1) * R[n + 1][t - 2][u][v] : 0.0) + X * R[n + 1][t - 1][u][v];
                     else if (u > 0)
@@ -218,7 +227,7 @@ static void hermite_R(int L, double a, double X, double Y, double Zc, Rtab R)
 /* ------------------------------------------------------ one-electron */
 
 /* S, T, V block of shells (sa, sb): out arrays [na*nb] row-major. */
-static void one_electron_block(const obasis *B, int sa, int sb, double *S, double *Tk, double *V)
+static void one_electron_block(const obasis *B, int sa, int sb, real *S, real *Tk, real *V)
 {
     int la = B->sh_l[sa], lb = B->sh_l[sb];
     int na = ncart(la), nb = ncart(lb);
@@ -231,22 +240,22 @@ static void one_electron_block(const obasis *B, int sa, int sb, double *S, doubl
     for (int p = 0; p < B->sh_np[sa]; ++p)
         for (int q = 0; q < B->sh_np[sb]; ++q) {
             int ip = B->sh_prim[sa] + p, iq = B->sh_prim[sb] + q;
-            double a = B->alpha[ip], b = B->alpha[iq], pp = a + b;
-            double P[3];
+            real a = B->alpha[ip], b = B->alpha[iq], pp = a + b;
+            real P[3];
             for (int x = 0; x < 3; ++x) {
                 hermite_E(la, lb + 2, a, b, A[x] - Bc[x], E[x]);
                 P[x] = (a * A[x] + b * Bc[x]) / pp;
             }
-            double s1 = sqrt(M_PI / pp);
+            real s1 = sqrt(OR_PI / pp);
             for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nb; ++j) {
-                    double cc = B->d[ip * 6 + i] * B->d[iq * 6 + j];
-                    double sd[3], td[3];
+                    real cc = B->d[ip * 6 + i] * B->d[iq * 6 + j];
+                    real sd[3], td[3];
                     for (int x = 0; x < 3; ++x) {
                         int li = ca[i][x], lj = cb[j][x];
                         sd[x] = E[x][li][lj][0] * s1;
-                        double tp2 = E[x][li][lj + 2][0] * s1;
-                        double tm2 = lj >= 2 ? E[x][li][lj - 2][0] * s1 : 0.0;
+                        real tp2 = E[x][li][lj + 2][0] * s1;
+                        real tm2 = lj >= 2 ? E[x][li][lj - 2][0] * s1 : 0.0;
                         td[x] = -2.0 * b * b * tp2 + b * (2 * lj + 1) * sd[x] - 0.5 * lj * (lj - 1) * tm2;
                     }
                     S[i * nb + j] += cc * sd[0] * sd[1] * sd[2];
@@ -255,12 +264,12 @@ static void one_electron_block(const obasis *B, int sa, int sb, double *S, doubl
             for (int C = 0; C < B->nat; ++C) {
                 const double *Cc = B->xyz + 3 * C;
                 hermite_R(la + lb, pp, P[0] - Cc[0], P[1] - Cc[1], P[2] - Cc[2], *R);
-                double pref = -B->Z[C] * 2.0 * M_PI / pp;
+                real pref = -B->Z[C] * 2.0 * OR_PI / pp;
                 for (int i = 0; i < na; ++i)
                     for (int j = 0; j < nb; ++j) {
-                        double cc = B->d[ip * 6 + i] * B->d[iq * 6 + j];
+                        real cc = B->d[ip * 6 + i] * B->d[iq * 6 + j];
                         int lx = ca[i][0] + cb[j][0], ly = ca[i][1] + cb[j][1], lz = ca[i][2] + cb[j][2];
-                        double sum = 0.0;
+                        real sum = 0.0;
                         for (int t = 0; t <= lx; ++t)
                             for (int u = 0; u <= ly; ++u)
                                 for (int v = 0; v <= lz; ++v)
@@ -276,7 +285,7 @@ static void one_electron_block(const obasis *B, int sa, int sb, double *S, doubl
 /* --------------------------------------------------------------- ERIs */
 
 /* Contracted block (sa sb | sc sd), out[na*nb*nc*nd] with a slowest. */
-static void eri_block(const obasis *B, int sa, int sb, int sc, int sd, double *out)
+static void eri_block(const obasis *B, int sa, int sb, int sc, int sd, real *out)
 {
     int l[4] = {B->sh_l[sa], B->sh_l[sb], B->sh_l[sc], B->sh_l[sd]};
     int sh[4] = {sa, sb, sc, sd};
@@ -292,7 +301,7 @@ static void eri_block(const obasis *B, int sa, int sb, int sc, int sd, double *o
     for (int pa = 0; pa < B->sh_np[sa]; ++pa)
     for (int pb = 0; pb < B->sh_np[sb]; ++pb) {
         int ia = B->sh_prim[sa] + pa, ib = B->sh_prim[sb] + pb;
-        double a = B->alpha[ia], b = B->alpha[ib], p = a + b, P[3];
+        real a = B->alpha[ia], b = B->alpha[ib], p = a + b, P[3];
         for (int x = 0; x < 3; ++x) {
             hermite_E(l[0], l[1], a, b, A[x] - Bc[x], Eab[x]);
             P[x] = (a * A[x] + b * Bc[x]) / p;
@@ -300,42 +309,49 @@ static void eri_block(const obasis *B, int sa, int sb, int sc, int sd, double *o
         for (int pc = 0; pc < B->sh_np[sc]; ++pc)
         for (int pd = 0; pd < B->sh_np[sd]; ++pd) {
             int ic = B->sh_prim[sc] + pc, id = B->sh_prim[sd] + pd;
-            double c = B->alpha[ic], d = B->alpha[id], q = c + d, Q[3];
+            real c = B->alpha[ic], d = B->alpha[id], q = c + d, Q[3];
             for (int x = 0; x < 3; ++x) {
                 hermite_E(l[2], l[3], c, d, C[x] - D[x], Ecd[x]);
                 Q[x] = (c * C[x] + d * D[x]) / q;
             }
-            double rho = p * q / (p + q);
+            real rho = p * q / (p + q);
             hermite_R(L, rho, P[0] - Q[0], P[1] - Q[1], P[2] - Q[2], *R);
-            double pref = 2.0 * pow(M_PI, 2.5) / (p * q * sqrt(p + q));
+            real pref = 2.0 * pow(OR_PI, 2.5) / (p * q * sqrt(p + q));
             int k = 0;
             for (int i = 0; i < n[0]; ++i)
             for (int j = 0; j < n[1]; ++j)
             for (int kk = 0; kk < n[2]; ++kk)
             for (int ll = 0; ll < n[3]; ++ll, ++k) {
                 const int *ci = comp[0][i], *cj = comp[1][j], *ck = comp[2][kk], *cl = comp[3][ll];
-                double sum = 0.0;
+                real sum = 0.0;
                 for (int t = 0; t <= ci[0] + cj[0]; ++t)
                 for (int u = 0; u <= ci[1] + cj[1]; ++u)
                 for (int v = 0; v <= ci[2] + cj[2]; ++v) {
-                    double eb = Eab[0][ci[0]][cj[0]][t] * Eab[1][ci[1]][cj[1]][u] * Eab[2][ci[2]][cj[2]][v];
-                    double inner = 0.0;
+                    real eb = Eab[0][ci[0]][cj[0]][t] * Eab[1][ci[1]][cj[1]][u] * Eab[2][ci[2]][cj[2]][v];
+                    real inner = 0.0;
                     for (int tau = 0; tau <= ck[0] + cl[0]; ++tau)
                     for (int nu = 0; nu <= ck[1] + cl[1]; ++nu)
                     for (int phi = 0; phi <= ck[2] + cl[2]; ++phi) {
-                        double ek = Ecd[0][ck[0]][cl[0]][tau] * Ecd[1][ck[1]][cl[1]][nu] * Ecd[2][ck[2]][cl[2]][phi];
-                        double sgn = ((tau + nu + phi) & 1) ? -1.0 : 1.0;
+                        real ek = Ecd[0][ck[0]][cl[0]][tau] * Ecd[1][ck[1]][cl[1]][nu] * Ecd[2][ck[2]][cl[2]][phi];
+                        real sgn = ((tau + nu + phi) & 1) ? -1.0 : 1.0;
                         inner += sgn * ek * (*R)[0][t + tau][u + nu][v + phi];
                     }
                     sum += eb * inner;
                 }
-                double cc = B->d[ia * 6 + i] * B->d[ib * 6 + j] * B->d[ic * 6 + kk] * B->d[id * 6 + ll];
+                real cc = B->d[ia * 6 + i] * B->d[ib * 6 + j] * B->d[ic * 6 + kk] * B->d[id * 6 + ll];
                 out[k] += cc * pref * sum;
             }
         }
     }
     free(Eab); free(Ecd); free(R);
     (void)sh;
+}
+
+void oracle_boys(int nmax, double T, double *F)
+{
+    real Fr[64];
+    boys_r(nmax, (real)T, Fr);
+    for (int n = 0; n <= nmax; ++n) F[n] = (double)Fr[n];
 }
 
 /* ------------------------------------------------------------ exports */
@@ -368,7 +384,7 @@ int oracle_coefficients(MOL_ARGS, double *out)
 {
     obasis B;
     if (basis_build(&B, MOL_PASS)) { basis_free(&B); return -1; }
-    memcpy(out, B.d, sizeof(double) * 6 * B.sh_prim[nsh]);
+    for (int k = 0; k < 6 * B.sh_prim[nsh]; ++k) out[k] = (double)B.d[k];
     basis_free(&B);
     return 0;
 }
@@ -380,14 +396,14 @@ int oracle_one_electron(MOL_ARGS, double *S, double *T, double *V)
     int N = B.nbf;
     #pragma omp parallel for schedule(dynamic)
     for (int sa = 0; sa < nsh; ++sa) {
-        double s[36], t[36], v[36];
+        real s[36], t[36], v[36];
         for (int sb = 0; sb < nsh; ++sb) {
             one_electron_block(&B, sa, sb, s, t, v);
             int na = ncart(sh_l[sa]), nb = ncart(sh_l[sb]);
             for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nb; ++j) {
                     long idx = (long)(B.sh_bf[sa] + i) * N + B.sh_bf[sb] + j;
-                    S[idx] = s[i * nb + j]; T[idx] = t[i * nb + j]; V[idx] = v[i * nb + j];
+                    S[idx] = (double)s[i * nb + j]; T[idx] = (double)t[i * nb + j]; V[idx] = (double)v[i * nb + j];
                 }
         }
     }
@@ -399,7 +415,10 @@ int oracle_eri_shell_quartet(MOL_ARGS, int a, int b, int c, int d, double *out)
 {
     obasis B;
     if (basis_build(&B, MOL_PASS)) { basis_free(&B); return -1; }
-    eri_block(&B, a, b, c, d, out);
+    real blk[1296];
+    eri_block(&B, a, b, c, d, blk);
+    int n = ncart(sh_l[a]) * ncart(sh_l[b]) * ncart(sh_l[c]) * ncart(sh_l[d]);
+    for (int k = 0; k < n; ++k) out[k] = (double)blk[k];
     basis_free(&B);
     return 0;
 }
@@ -411,9 +430,13 @@ int oracle_eri_quartet_list(MOL_ARGS, long nq, const int *quartets, const long *
     obasis B;
     if (basis_build(&B, MOL_PASS)) { basis_free(&B); return -1; }
     #pragma omp parallel for schedule(dynamic)
-    for (long q = 0; q < nq; ++q)
-        eri_block(&B, quartets[4 * q], quartets[4 * q + 1], quartets[4 * q + 2], quartets[4 * q + 3],
-                  out + out_offsets[q]);
+    for (long q = 0; q < nq; ++q) {
+        real blk[1296];
+        const int *qq = quartets + 4 * q;
+        eri_block(&B, qq[0], qq[1], qq[2], qq[3], blk);
+        int n = ncart(sh_l[qq[0]]) * ncart(sh_l[qq[1]]) * ncart(sh_l[qq[2]]) * ncart(sh_l[qq[3]]);
+        for (int k = 0; k < n; ++k) out[out_offsets[q] + k] = (double)blk[k];
+    }
     basis_free(&B);
     return 0;
 }
@@ -428,7 +451,7 @@ int oracle_eri_dense(MOL_ARGS, double *out)
     #pragma omp parallel for schedule(dynamic)
     for (int ab = 0; ab < nsh * nsh; ++ab) {
         int sa = ab / nsh, sb = ab % nsh;
-        double *blk = (double *)malloc(sizeof(double) * 1296);
+        real *blk = (real *)malloc(sizeof(real) * 1296);
         for (int sc = 0; sc < nsh; ++sc)
             for (int sd = 0; sd < nsh; ++sd) {
                 eri_block(&B, sa, sb, sc, sd, blk);
@@ -438,8 +461,8 @@ int oracle_eri_dense(MOL_ARGS, double *out)
                     for (int j = 0; j < nb; ++j)
                         for (int kk = 0; kk < nc; ++kk)
                             for (int ll = 0; ll < nd; ++ll, ++k) {
-                                long I = B.sh_bf[sa] + i, J = B.sh_bf[sb] + j, K = B.sh_bf[sc] + kk, L = B.sh_bf[sd] + ll;
-                                out[((I * N + J) * N + K) * N + L] = blk[k];
+                                long i0 = B.sh_bf[sa] + i, j0 = B.sh_bf[sb] + j, k0 = B.sh_bf[sc] + kk, l0 = B.sh_bf[sd] + ll;
+                                out[((i0 * N + j0) * N + k0) * N + l0] = (double)blk[k];
                             }
             }
         free(blk);
@@ -456,15 +479,15 @@ int oracle_schwarz(MOL_ARGS, double *Q)
     #pragma omp parallel for schedule(dynamic)
     for (int ab = 0; ab < nsh * nsh; ++ab) {
         int sa = ab / nsh, sb = ab % nsh;
-        double *blk = (double *)malloc(sizeof(double) * 1296);
+        real *blk = (real *)malloc(sizeof(real) * 1296);
         eri_block(&B, sa, sb, sa, sb, blk);
         int na = ncart(sh_l[sa]), nb = ncart(sh_l[sb]);
-        double m = 0.0;
+        real m = 0.0;
         for (int i = 0; i < na * nb; ++i) {
-            double v = fabs(blk[i * na * nb + i]);
+            real v = fabs(blk[i * na * nb + i]);
             if (v > m) m = v;
         }
-        Q[ab] = sqrt(m);
+        Q[ab] = (double)sqrt(m);
         free(blk);
     }
     basis_free(&B);
@@ -492,9 +515,9 @@ int oracle_jk_unique(MOL_ARGS, const double *Dm, double tau, double *J, double *
     long long count = 0;
     #pragma omp parallel reduction(+:count)
     {
-        double *Jl = (double *)calloc(N * N, sizeof(double));
-        double *Kl = (double *)calloc(N * N, sizeof(double));
-        double *blk = (double *)malloc(sizeof(double) * 1296);
+        real *Jl = (real *)calloc(N * N, sizeof(real));
+        real *Kl = (real *)calloc(N * N, sizeof(real));
+        real *blk = (real *)malloc(sizeof(real) * 1296);
         #pragma omp for schedule(dynamic)
         for (int ab = npair - 1; ab >= 0; --ab) {
             int a = pa[ab], b = pb[ab];
@@ -503,7 +526,7 @@ int oracle_jk_unique(MOL_ARGS, const double *Dm, double tau, double *J, double *
                 if (tau > 0.0 && Q[a * nsh + b] * Q[c * nsh + d] < tau) continue;
                 ++count;
                 eri_block(&B, a, b, c, d, blk);
-                double f = 1.0 / ((a == b ? 2.0 : 1.0) * (c == d ? 2.0 : 1.0) * (ab == cd ? 2.0 : 1.0));
+                real f = 1.0 / ((a == b ? 2.0 : 1.0) * (c == d ? 2.0 : 1.0) * (ab == cd ? 2.0 : 1.0));
                 int na = ncart(sh_l[a]), nb = ncart(sh_l[b]), nc = ncart(sh_l[c]), nd = ncart(sh_l[d]);
                 int k = 0;
                 for (int ii = 0; ii < na; ++ii)
@@ -511,7 +534,7 @@ int oracle_jk_unique(MOL_ARGS, const double *Dm, double tau, double *J, double *
                 for (int kk = 0; kk < nc; ++kk)
                 for (int ll = 0; ll < nd; ++ll, ++k) {
                     long i = B.sh_bf[a] + ii, j = B.sh_bf[b] + jj, kx = B.sh_bf[c] + kk, l = B.sh_bf[d] + ll;
-                    double v = f * blk[k];
+                    real v = f * blk[k];
                     /* (ij|kl) (ji|kl) (ij|lk) (ji|lk) (kl|ij) (lk|ij) (kl|ji) (lk|ji) */
                     Jl[i * N + j] += v * Dm[kx * N + l];  Kl[i * N + kx] += v * Dm[j * N + l];
                     Jl[j * N + i] += v * Dm[kx * N + l];  Kl[j * N + kx] += v * Dm[i * N + l];
@@ -526,7 +549,7 @@ int oracle_jk_unique(MOL_ARGS, const double *Dm, double tau, double *J, double *
         }
         #pragma omp critical
         {
-            for (long x = 0; x < N * N; ++x) { J[x] += Jl[x]; K[x] += Kl[x]; }
+            for (long x = 0; x < N * N; ++x) { J[x] += (double)Jl[x]; K[x] += (double)Kl[x]; }
         }
         free(Jl); free(Kl); free(blk);
     }
@@ -551,11 +574,11 @@ int oracle_jk_elements(MOL_ARGS, const double *Dm, int npts, const int *mu, cons
         int m = mu[e], n = nu[e];
         int sm = bf_shell[m], sn = bf_shell[n];
         int im = m - B.sh_bf[sm], in_ = n - B.sh_bf[sn];
-        double jsum = 0.0, ksum = 0.0;
+        real jsum = 0.0, ksum = 0.0;
         #pragma omp parallel for schedule(dynamic) reduction(+:jsum, ksum)
         for (int cd = 0; cd < nsh * nsh; ++cd) {
             int sc = cd / nsh, sd = cd % nsh;
-            double *blk = (double *)malloc(sizeof(double) * 1296);
+            real *blk = (real *)malloc(sizeof(real) * 1296);
             int nm = ncart(sh_l[sm]), nnn = ncart(sh_l[sn]), nc = ncart(sh_l[sc]), nd = ncart(sh_l[sd]);
             /* J: (sm sn | sc sd) */
             eri_block(&B, sm, sn, sc, sd, blk);
@@ -571,7 +594,7 @@ int oracle_jk_elements(MOL_ARGS, const double *Dm, int npts, const int *mu, cons
                             * Dm[(B.sh_bf[sc] + kk) * N + B.sh_bf[sd] + ll];
             free(blk);
         }
-        Jout[e] = jsum; Kout[e] = ksum;
+        Jout[e] = (double)jsum; Kout[e] = (double)ksum;
     }
     free(bf_shell);
     basis_free(&B);

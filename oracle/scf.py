@@ -98,9 +98,10 @@ class RHF:
     def commutator(self, F, D):
         return self.X.T @ (F @ D @ self.S - self.S @ D @ F) @ self.X
 
-    def run(self, D0=None):
+    def run(self, D0=None, record=False):
         D = self.core_guess() if D0 is None else np.array(D0, dtype=np.float64)
         energies, focks, errors = [], [], []
+        densities, fock_hist = [], []
         converged = False
         n_iter = self.fixed_iters if self.fixed_iters is not None else self.max_iter
         F = None
@@ -109,6 +110,9 @@ class RHF:
             F, E = fock_and_energy(self.H, J, K, D, self.e_nuc)
             D_used = D
             energies.append(E)
+            if record:
+                densities.append(D)
+                fock_hist.append(F)
             if self.fixed_iters is None and k > 0 and abs(E - energies[-2]) < self.conv_tol:
                 converged = True
                 break
@@ -126,4 +130,4 @@ class RHF:
             converged = True
         return {"energy": energies[-1], "energies": energies, "D": D_used, "D_next": D, "F": F,
                 "converged": converged, "iterations": len(energies),
-                "e_nuc": self.e_nuc}
+                "e_nuc": self.e_nuc, "densities": densities, "focks": fock_hist}

@@ -1,0 +1,97 @@
+"""Build libmess_hip.so for gfx950 with hipcc (in-tree, parallel).
+
+Usage: python -m paper_2406_03121_amd.build [--force] [--jobs N]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libmess_hip.so")
+ROOT = os.path.dirname(HERE)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics", "-Wno-unused-result",
+    "-I" + os.path.join(ROOT, "include"),
+]
+
+# unique angular classes (bra pair class >= ket pair class), pair classes
+# ss ps pp ds dp dd = 0..5
+CLASSES = [(cb, ck) for cb in range(6) for ck in range(cb + 1)]
+# classes evaluated by the wave-cooperative kernel (coop.hip) instead
+COOP_CLASSES = {(4, 2), (4, 4), (5, 2), (5, 3), (5, 4), (5, 5)}
+UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
+
+
+def _units():
+    units = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        name = os.path.splitext(os.path.basename(src))[0]
+        if name == "eri_class":
+            for cb, ck in UNROLLED_CLASSES:
+                units.append((src, os.path.join(OBJ, f"eri_class_{cb}{ck}.o"),
+                              [f"-DMESS_CB={cb}", f"-DMESS_CK={ck}"]))
+        else:
+            units.append((src, os.path.join(OBJ, name + ".o"), []))
+    # heaviest classes first so the parallel build finishes sooner
+    units.sort(key=lambda u: -sum(int(x[-1]) for x in u[2]) if u[2] else 0)
+    return units
+
+
+def _headers_mtime():
+    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(unit, force):
+    src, obj, defs = unit
+    if not force and os.path.exists(obj):
+        if os.path.getmtime(obj) >= max(os.path.getmtime(src), _headers_mtime()):
+            return obj, 0.0, ""
+    import time
+    t = time.time()
+    cmd = [HIPCC] + FLAGS + defs + ["-c", src, "-o", obj + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(obj + ".tmp", obj)
+    return obj, time.time() - t, r.stderr
+
+
+def build(force: bool = False, jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    units = _units()
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for obj, dt, _err in ex.map(lambda u: _compile(u, force), units):
+            objs.append(obj)
+            if verbose and dt:
+                print(f"  {os.path.basename(obj)}: {dt:.1f}s", flush=True)
+    newest = max(os.path.getmtime(o) for o in objs)
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--force", action="store_true")
+    ap.add_argument("--jobs", type=int, default=None)
+    a = ap.parse_args()
+    print(build(force=a.force, jobs=a.jobs, verbose=True))
+    sys.exit(0)

@@ -1,0 +1,55 @@
+// Per-angular-class launchers.  Each of the 21 unique classes (pair class
+// of the bra >= pair class of the ket) is compiled in its own object file
+// (eri_class.hip built once per class) and reached through ClassOps.
+#pragma once
+
+#include "mess_internal.hpp"
+
+namespace mess {
+
+struct ClassLaunch {
+    const PairInfo *pairs;
+    const PrimPair *pp;
+    const PrimPairF *ppf;
+    const double *tab, *etab;
+    const float *tabf, *etabf;
+    int bra_off, ket_off, nbra, same_class;
+    const int64_t *rowstart;
+    int64_t total;
+    int N;
+    hipStream_t stream;
+};
+
+template <int CB, int CK>
+struct ClassOps {
+    // Q[off + i] for the n pairs of class CB (requires CB == CK).
+    static int schwarz(const ClassLaunch &L, int off, int n, double *Q);
+    // Dense N^4 FP64 store of every quartet in the list.
+    static int dense(const ClassLaunch &L, double *eri, int prec);
+    // Gj, Gk half-matrices (either may be NULL) from density D.
+    static int jk(const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec);
+};
+
+// Calls f(integral_constant<CB>, integral_constant<CK>) for a runtime
+// (cb, ck) with cb >= ck.
+template <typename F>
+int dispatch_class(int cb, int ck, F &&f) {
+    using std::integral_constant;
+#define MESS_CASE(B, K) \
+    case (B) * 6 + (K): return f(integral_constant<int, B>{}, integral_constant<int, K>{});
+    switch (cb * 6 + ck) {
+        MESS_CASE(0, 0)
+        MESS_CASE(1, 0) MESS_CASE(1, 1)
+        MESS_CASE(2, 0) MESS_CASE(2, 1) MESS_CASE(2, 2)
+        MESS_CASE(3, 0) MESS_CASE(3, 1) MESS_CASE(3, 2) MESS_CASE(3, 3)
+        MESS_CASE(4, 0) MESS_CASE(4, 1) MESS_CASE(4, 2) MESS_CASE(4, 3) MESS_CASE(4, 4)
+        MESS_CASE(5, 0) MESS_CASE(5, 1) MESS_CASE(5, 2) MESS_CASE(5, 3) MESS_CASE(5, 4) MESS_CASE(5, 5)
+        default: break;
+    }
+#undef MESS_CASE
+    set_error("internal: bad class (%d,%d)", cb, ck);
+    return MESS_E_ARG;
+}
+
+
+}  // namespace mess

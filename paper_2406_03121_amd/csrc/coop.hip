@@ -1,0 +1,625 @@
+// Wave-cooperative shell-quartet kernel for the high angular classes
+// (bra or ket pair dp/dd with a large ket).  One 64-lane wave evaluates one
+// shell quartet: the Obara-Saika vertical recursion of each primitive quartet
+// runs level by level with every intermediate [e0|f0]^(m) in LDS, the 64
+// lanes sharing the independent recursion steps of a level; contracted
+// intermediates are accumulated in LDS and the Head-Gordon-Pople horizontal
+// recursion runs the same way.  The per-class step lists are generated on
+// the host from the recursions (see eri_hgp.hpp for the formulas) and are
+// the same for every quartet of the class.
+#include <cstring>
+#include <memory>
+#include <mutex>
+
+#include "class_ops.hpp"
+#include "eri_kernels.hpp"
+#include "mess_internal.hpp"
+
+namespace mess {
+
+// Recursion step: v = c[a1] V[s1] + c[a2] V[s2] + k3 (c[a3] V[s3] - c[a4] V[s4]) + k5 c[a5] V[s5]
+// packed as x = dst | s1 << 16, y = s2 | s3 << 16, z = s4 | s5 << 16,
+// w = a1 | a2 << 5 | a3 << 10 | a4 << 15 | a5 << 20 | k3 << 25 | k5 << 28.
+// Coefficient slots (per primitive quartet):
+enum : int {
+    kC0 = 0,                 // 0
+    kPA = 1, kWP = 4,        // PA_xyz, WP_xyz (bra)
+    kQC = 7, kWQ = 10,       // QC_xyz, WQ_xyz (ket)
+    kO2P = 13, kO2PR = 14,   // 1/(2p), rho/(2p^2)
+    kO2Q = 15, kO2QR = 16,   // 1/(2q), rho/(2q^2)
+    kO2PQ = 17,              // 1/(2(p+q))
+    kNCoef = 18
+};
+// Horizontal-recursion coefficients: 0 -> 0, 1 -> 1, 2..4 -> AB, 5..7 -> CD.
+enum : int { kH0 = 0, kH1 = 1, kHAB = 2, kHCD = 5, kNHCoef = 8 };
+
+struct CoopProgram {
+    int cb = 0, ck = 0, LA = 0, LB = 0, LC = 0, LD = 0, L = 0;
+    int nV = 0;       // VRR slots (slot 0 holds 0.0); slots 1..L+1 are [0|0]^(m)
+    int nH = 0;       // HRR slots; slots [0, nacc) are the contracted [e0|f0]
+    int nacc = 0, nout = 0;
+    int nvlev = 0, nhlev = 0;
+    int4 *d_vops = nullptr;
+    int *d_vlev = nullptr;     // nvlev + 1 op offsets
+    unsigned short *d_accsrc = nullptr;  // V slot of accumulator k
+    int4 *d_hops = nullptr;
+    int *d_hlev = nullptr;
+    unsigned short *d_outslot = nullptr;  // H slot of output element
+    double *d_outscale = nullptr;
+    size_t lds_bytes = 0;
+};
+
+namespace {
+
+int4 pack(int dst, int s1, int a1, int s2, int a2, int s3, int a3, int s4, int a4, int s5, int a5, int k3,
+          int k5) {
+    int4 o;
+    o.x = dst | (s1 << 16);
+    o.y = s2 | (s3 << 16);
+    o.z = s4 | (s5 << 16);
+    o.w = a1 | (a2 << 5) | (a3 << 10) | (a4 << 15) | (a5 << 20) | (k3 << 25) | (k5 << 28);
+    return o;
+}
+
+struct Builder {
+    std::map<std::tuple<int, int, int>, int> vslot;  // (f, e, m) -> slot
+    int nV = 1;
+    int V(int f, int e, int m) {
+        auto key = std::make_tuple(f, e, m);
+        auto it = vslot.find(key);
+        if (it != vslot.end()) return it->second;
+        vslot[key] = nV;
+        return nV++;
+    }
+    int Vget(int f, int e, int m) const {
+        auto it = vslot.find(std::make_tuple(f, e, m));
+        return it == vslot.end() ? -1 : it->second;
+    }
+};
+
+std::unique_ptr<CoopProgram> build_program(int cb, int ck) {
+    auto P = std::make_unique<CoopProgram>();
+    P->cb = cb; P->ck = ck;
+    const int LA = pair_class_la(cb), LB = pair_class_lb(cb), LC = pair_class_la(ck), LD = pair_class_lb(ck);
+    P->LA = LA; P->LB = LB; P->LC = LC; P->LD = LD;
+    const int LAB = LA + LB, LCD = LC + LD, L = LAB + LCD;
+    P->L = L;
+    const int NE = cart_off(LAB + 1), NF = cart_off(LCD + 1), E0 = cart_off(LA), F0 = cart_off(LC);
+    Builder b;
+    for (int m = 0; m <= L; ++m) b.V(0, 0, m);  // slots 1..L+1
+    std::vector<std::vector<int4>> levels;
+    // bra VRR, level |e|
+    for (int n = 1; n <= LAB; ++n) {
+        std::vector<int4> lev;
+        for (int e = cart_off(n); e < cart_off(n + 1); ++e) {
+            const Cart c = cart_of(e);
+            const int i = c.dir(), ei = c.get(i), e1 = c.minus(i).idx();
+            for (int m = 0; m <= L - n; ++m) {
+                const int dst = b.V(0, e, m);
+                int s3 = 0, s4 = 0, k3 = 0;
+                if (ei >= 2) {
+                    const int e2 = c.minus(i, 2).idx();
+                    s3 = b.Vget(0, e2, m);
+                    s4 = b.Vget(0, e2, m + 1);
+                    k3 = ei - 1;
+                }
+                lev.push_back(pack(dst, b.Vget(0, e1, m), kPA + i, b.Vget(0, e1, m + 1), kWP + i, s3, kO2P, s4,
+                                   kO2PR, 0, kC0, k3, 0));
+            }
+        }
+        levels.push_back(lev);
+    }
+    // ket VRR, level |f|
+    for (int nf = 1; nf <= LCD; ++nf) {
+        std::vector<int4> lev;
+        const int emin = cart_off(std::max(0, LA - (LCD - nf)));
+        for (int f = cart_off(nf); f < cart_off(nf + 1); ++f) {
+            const Cart cf = cart_of(f);
+            const int j = cf.dir(), fj = cf.get(j), f1 = cf.minus(j).idx();
+            for (int e = emin; e < NE; ++e) {
+                const Cart ce = cart_of(e);
+                const int ej = ce.get(j);
+                for (int m = 0; m <= L - ce.l() - nf; ++m) {
+                    const int dst = b.V(f, e, m);
+                    int s3 = 0, s4 = 0, k3 = 0, s5 = 0, k5 = 0;
+                    if (fj >= 2) {
+                        const int f2 = cf.minus(j, 2).idx();
+                        s3 = b.Vget(f2, e, m);
+                        s4 = b.Vget(f2, e, m + 1);
+                        k3 = fj - 1;
+                    }
+                    if (ej >= 1) {
+                        s5 = b.Vget(f1, ce.minus(j).idx(), m + 1);
+                        k5 = ej;
+                    }
+                    lev.push_back(pack(dst, b.Vget(f1, e, m), kQC + j, b.Vget(f1, e, m + 1), kWQ + j, s3, kO2Q,
+                                       s4, kO2QR, s5, kO2PQ, k3, k5));
+                }
+            }
+        }
+        levels.push_back(lev);
+    }
+    P->nV = b.nV;
+    std::vector<int4> vops;
+    std::vector<int> vlev{0};
+    for (auto &lev : levels) {
+        vops.insert(vops.end(), lev.begin(), lev.end());
+        vlev.push_back((int)vops.size());
+    }
+    P->nvlev = (int)levels.size();
+    // accumulators
+    const int NEA = NE - E0, NFA = NF - F0;
+    P->nacc = NEA * NFA;
+    std::vector<unsigned short> accsrc(P->nacc);
+    for (int f = F0; f < NF; ++f)
+        for (int e = E0; e < NE; ++e) accsrc[(f - F0) * NEA + (e - E0)] = (unsigned short)b.Vget(f, e, 0);
+    // horizontal recursion on H; H[(f-F0)*NEA + (e-E0)] = [e0|f0]
+    int nH = P->nacc;
+    std::vector<std::vector<int4>> hlevels;
+    const int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    // bra: T[b][a] for each f; level |b|
+    std::map<std::tuple<int, int, int>, int> Tb;  // (f, b, a) -> slot
+    for (int f = F0; f < NF; ++f)
+        for (int e = E0; e < NE; ++e) Tb[std::make_tuple(f, 0, e)] = (f - F0) * NEA + (e - E0);
+    for (int k = 1; k <= LB; ++k) {
+        std::vector<int4> lev;
+        for (int f = F0; f < NF; ++f)
+            for (int bb = cart_off(k); bb < cart_off(k + 1); ++bb) {
+                const Cart cb_ = cart_of(bb);
+                const int i = cb_.dir(), b1 = cb_.minus(i).idx();
+                for (int a = E0; a < cart_off(LAB - k + 1); ++a) {
+                    const int a1 = cart_of(a).plus(i).idx();
+                    const int dst = nH++;
+                    Tb[std::make_tuple(f, bb, a)] = dst;
+                    lev.push_back(pack(dst, Tb.at(std::make_tuple(f, b1, a1)), kH1, Tb.at(std::make_tuple(f, b1, a)),
+                                       kHAB + i, 0, kH0, 0, kH0, 0, kH0, 0, 0));
+                }
+            }
+        hlevels.push_back(lev);
+    }
+    // ket: U[d][c] for each (a, b); level |d|
+    std::map<std::tuple<int, int, int>, int> Td;  // (ab, d, c) -> slot
+    for (int a = 0; a < NA; ++a)
+        for (int bb = 0; bb < NB; ++bb)
+            for (int f = F0; f < NF; ++f)
+                Td[std::make_tuple(a * NB + bb, 0, f)] = Tb.at(std::make_tuple(f, cart_off(LB) + bb, E0 + a));
+    for (int k = 1; k <= LD; ++k) {
+        std::vector<int4> lev;
+        for (int ab = 0; ab < NA * NB; ++ab)
+            for (int d = cart_off(k); d < cart_off(k + 1); ++d) {
+                const Cart cd_ = cart_of(d);
+                const int i = cd_.dir(), d1 = cd_.minus(i).idx();
+                for (int c = F0; c < cart_off(LCD - k + 1); ++c) {
+                    const int c1 = cart_of(c).plus(i).idx();
+                    const int dst = nH++;
+                    Td[std::make_tuple(ab, d, c)] = dst;
+                    lev.push_back(pack(dst, Td.at(std::make_tuple(ab, d1, c1)), kH1, Td.at(std::make_tuple(ab, d1, c)),
+                                       kHCD + i, 0, kH0, 0, kH0, 0, kH0, 0, 0));
+                }
+            }
+        hlevels.push_back(lev);
+    }
+    P->nH = nH;
+    std::vector<int4> hops;
+    std::vector<int> hlev{0};
+    for (auto &lev : hlevels) {
+        hops.insert(hops.end(), lev.begin(), lev.end());
+        hlev.push_back((int)hops.size());
+    }
+    P->nhlev = (int)hlevels.size();
+    P->nout = NA * NB * NC * ND;
+    std::vector<unsigned short> outslot(P->nout);
+    std::vector<double> outscale(P->nout);
+    auto scale = [](int l, int local) { return cart_is_mixed_d(cart_of(cart_off(l) + local)) ? kSqrt3 : 1.0; };
+    for (int a = 0; a < NA; ++a)
+        for (int bb = 0; bb < NB; ++bb)
+            for (int c = 0; c < NC; ++c)
+                for (int d = 0; d < ND; ++d) {
+                    const int o = ((a * NB + bb) * NC + c) * ND + d;
+                    outslot[o] = (unsigned short)Td.at(std::make_tuple(a * NB + bb, cart_off(LD) + d, F0 + c));
+                    outscale[o] = scale(LA, a) * scale(LB, bb) * scale(LC, c) * scale(LD, d);
+                }
+    if (P->nV >= 65536 || P->nH >= 65536) return nullptr;
+    // Validate the step tables: every source slot is defined by an earlier
+    // level (or is the zero slot with a zero multiplier), every destination
+    // is in range and written once.
+    {
+        std::vector<int> vdef(P->nV, -1);
+        for (int m = 0; m <= L; ++m) vdef[1 + m] = 0;
+        vdef[0] = 0;
+        for (int lv = 0; lv < P->nvlev; ++lv)
+            for (int o = vlev[lv]; o < vlev[lv + 1]; ++o) {
+                const int4 op = vops[o];
+                const int dst = op.x & 0xffff, s1 = op.x >> 16, s2 = op.y & 0xffff, s3 = op.y >> 16,
+                          s4 = op.z & 0xffff, s5 = op.z >> 16;
+                const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
+                auto ok = [&](int sl, bool used) {
+                    if (sl < 0 || sl >= P->nV) return false;
+                    return !used || (vdef[sl] >= 0 && vdef[sl] <= lv);
+                };
+                if (!ok(s1, true) || !ok(s2, true) || !ok(s3, k3 != 0) || !ok(s4, k3 != 0) || !ok(s5, k5 != 0))
+                    return nullptr;
+                if (dst <= L + 1 || dst >= P->nV || vdef[dst] >= 0) return nullptr;
+                vdef[dst] = lv + 1;
+            }
+        for (int k = 0; k < P->nacc; ++k)
+            if (accsrc[k] >= P->nV || vdef[accsrc[k]] < 0) return nullptr;
+        std::vector<int> hdef(P->nH, -1);
+        for (int k = 0; k < P->nacc; ++k) hdef[k] = 0;
+        for (int lv = 0; lv < P->nhlev; ++lv)
+            for (int o = hlev[lv]; o < hlev[lv + 1]; ++o) {
+                const int4 op = hops[o];
+                const int dst = op.x & 0xffff, s1 = op.x >> 16, s2 = op.y & 0xffff;
+                if (s1 >= P->nH || s2 >= P->nH || hdef[s1] < 0 || hdef[s1] > lv || hdef[s2] < 0 || hdef[s2] > lv)
+                    return nullptr;
+                if (dst < P->nacc || dst >= P->nH || hdef[dst] >= 0) return nullptr;
+                hdef[dst] = lv + 1;
+            }
+        for (int o = 0; o < P->nout; ++o)
+            if (outslot[o] >= P->nH || hdef[outslot[o]] < 0) return nullptr;
+    }
+    // LDS: accumulators [0, nacc), then one region shared by the VRR slots
+    // (during the primitive loop) and the HRR slots >= nacc (after it).
+    P->lds_bytes = sizeof(double) * (size_t)(P->nacc + std::max(P->nV, P->nH - P->nacc) + kNCoef + kNHCoef);
+    // upload
+    auto up = [](auto **dptr, const auto &vec) -> bool {
+        using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+        size_t n = std::max<size_t>(1, vec.size());
+        if (hipMalloc((void **)dptr, sizeof(T) * n) != hipSuccess) return false;
+        if (!vec.empty() && hipMemcpy(*dptr, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return false;
+        return true;
+    };
+    if (!up(&P->d_vops, vops) || !up(&P->d_vlev, vlev) || !up(&P->d_accsrc, accsrc) || !up(&P->d_hops, hops) ||
+        !up(&P->d_hlev, hlev) || !up(&P->d_outslot, outslot) || !up(&P->d_outscale, outscale))
+        return nullptr;
+    return P;
+}
+
+std::mutex g_prog_mutex;
+std::map<std::pair<int, int>, std::unique_ptr<CoopProgram>> g_programs;
+
+}  // namespace
+
+// Classes evaluated by the cooperative kernel (the per-lane unrolled form
+// of these needs far more than the 512 registers a lane can hold).
+bool coop_class(int cb, int ck) {
+    return (cb == 5 && ck >= 2) || (cb == 4 && (ck == 2 || ck == 4));
+}
+
+static const CoopProgram *coop_program(int cb, int ck) {
+    std::lock_guard<std::mutex> lk(g_prog_mutex);
+    auto key = std::make_pair(cb, ck);
+    auto it = g_programs.find(key);
+    if (it != g_programs.end()) return it->second.get();
+    std::unique_ptr<CoopProgram> P;
+    try {
+        P = build_program(cb, ck);
+    } catch (...) {
+        P.reset();
+    }
+    if (!P) return nullptr;
+    const CoopProgram *raw = P.get();
+    g_programs[key] = std::move(P);
+    return raw;
+}
+
+// ------------------------------------------------------------ device
+
+struct CoopArgs {
+    const int4 *vops;
+    const int *vlev;
+    const unsigned short *accsrc;
+    const int4 *hops;
+    const int *hlev;
+    const unsigned short *outslot;
+    const double *outscale;
+    int nV, nH, nacc, nout, nvlev, nhlev, L;
+    int NA, NB, NC, ND;
+};
+
+enum { kModeSchwarz = 0, kModeDense = 1, kModeJK = 2 };
+
+__device__ __forceinline__ double coop_boys(int m, double T, const double *__restrict__ tab) {
+    // F_m(T), m <= 8, directly (no recurrence): Taylor about the nearest grid
+    // point for T < 60, the large-T form (2m-1)!!/(2T)^m sqrt(pi/T)/2 above.
+    if (T < kBoysTmax) {
+        const int k = __double2int_rn(T * kBoysInvStep);
+        const double md = static_cast<double>(k) * (1.0 / kBoysInvStep) - T;
+        const double *row = tab + k * kBoysN + m;
+        double f = row[7];
+        f = row[6] + md * (1.0 / 7.0) * f;
+        f = row[5] + md * (1.0 / 6.0) * f;
+        f = row[4] + md * (1.0 / 5.0) * f;
+        f = row[3] + md * (1.0 / 4.0) * f;
+        f = row[2] + md * (1.0 / 3.0) * f;
+        f = row[1] + md * (1.0 / 2.0) * f;
+        return row[0] + md * f;
+    }
+    const double rT = 1.0 / T;
+    double f = 0.5 * sqrt(M_PI * rT);
+    for (int n = 0; n < m; ++n) f *= (2 * n + 1) * 0.5 * rT;
+    return f;
+}
+
+__device__ __forceinline__ double run_op(const int4 op, const double *__restrict__ V, const double *__restrict__ c) {
+    const int s1 = op.x >> 16, s2 = op.y & 0xffff, s3 = op.y >> 16, s4 = op.z & 0xffff, s5 = op.z >> 16;
+    const int w = op.w;
+    const int a1 = w & 31, a2 = (w >> 5) & 31, a3 = (w >> 10) & 31, a4 = (w >> 15) & 31, a5 = (w >> 20) & 31;
+    const double k3 = (double)((w >> 25) & 7), k5 = (double)((w >> 28) & 7);
+    double v = c[a1] * V[s1] + c[a2] * V[s2];
+    v += k3 * (c[a3] * V[s3] - c[a4] * V[s4]);
+    v += k5 * c[a5] * V[s5];
+    return v;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
+                                             int ket_off, int nbra, int same_class,
+                                             const int64_t *__restrict__ rowstart, int64_t total,
+                                             const PrimPair *__restrict__ pp, const double *__restrict__ tab,
+                                             const double *__restrict__ D, int N, double *__restrict__ out0,
+                                             double *__restrict__ out1) {
+    extern __shared__ double lds[];
+    double *H = lds;                 // HRR slots; [0, nacc) are the accumulators
+    double *V = lds + A.nacc;        // VRR slots, aliasing HRR slots >= nacc
+    double *c = lds + A.nacc + max(A.nV, A.nH - A.nacc);  // kNCoef
+    double *hc = c + kNCoef;                               // kNHCoef
+    const int lane = threadIdx.x;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        if (lane == 0) V[0] = 0.0;
+        int i, j;
+        if (MODE == kModeSchwarz) {
+            i = j = (int)q;
+        } else {
+            i = find_row(rowstart, nbra, q);
+            j = (int)(q - rowstart[i]);
+        }
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
+        const double ACx = bra.Ax - ket.Ax, ACy = bra.Ay - ket.Ay, ACz = bra.Az - ket.Az;
+        for (int s = lane; s < A.nacc; s += 64) H[s] = 0.0;
+        for (int ib = 0; ib < bra.npp; ++ib) {
+            const PrimPair P = pp[bra.pp0 + ib];
+            for (int ik = 0; ik < ket.npp; ++ik) {
+                const PrimPair Q = pp[ket.pp0 + ik];
+                const double p = P.p, qq = Q.p, pq = p + qq, rpq = 1.0 / pq, rho = p * qq * rpq;
+                const double PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
+                const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+                __syncthreads();  // previous primitive quartet fully consumed
+                if (lane <= A.L) {
+                    const double pref = 34.986836655249725 / (p * qq * sqrt(pq)) * P.K * Q.K;
+                    V[1 + lane] = pref * coop_boys(lane, T, tab);
+                }
+                if (lane == 32) {
+                    c[kC0] = 0.0;
+                    c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
+                    c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
+                    c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
+                    c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
+                    c[kO2P] = 0.5 / p; c[kO2PR] = 0.5 / p * rho / p;
+                    c[kO2Q] = 0.5 / qq; c[kO2QR] = 0.5 / qq * rho / qq;
+                    c[kO2PQ] = 0.5 * rpq;
+                }
+                __syncthreads();
+                for (int lv = 0; lv < A.nvlev; ++lv) {
+                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
+                    for (int o = b0 + lane; o < b1; o += 64) {
+                        const int4 op = A.vops[o];
+                        V[op.x & 0xffff] = run_op(op, V, c);
+                    }
+                    __syncthreads();
+                }
+                for (int s = lane; s < A.nacc; s += 64) H[s] += V[A.accsrc[s]];
+            }
+        }
+        if (lane == 0) {
+            hc[kH0] = 0.0; hc[kH1] = 1.0;
+            hc[kHAB + 0] = bra.ABx; hc[kHAB + 1] = bra.ABy; hc[kHAB + 2] = bra.ABz;
+            hc[kHCD + 0] = ket.ABx; hc[kHCD + 1] = ket.ABy; hc[kHCD + 2] = ket.ABz;
+        }
+        __syncthreads();
+        for (int lv = 0; lv < A.nhlev; ++lv) {
+            const int b0 = A.hlev[lv], b1 = A.hlev[lv + 1];
+            for (int o = b0 + lane; o < b1; o += 64) {
+                const int4 op = A.hops[o];
+                H[op.x & 0xffff] = run_op(op, H, hc);
+            }
+            __syncthreads();
+        }
+        // output element o = ((a*NB + b)*NC + c)*ND + d is H[outslot[o]] * outscale[o]
+        const int NB = A.NB, NC = A.NC, ND = A.ND, NA = A.NA;
+        auto O = [&](int a, int b, int cc, int d) {
+            const int o = ((a * NB + b) * NC + cc) * ND + d;
+            return H[A.outslot[o]] * A.outscale[o];
+        };
+        if (MODE == kModeSchwarz) {
+            if (lane == 0) {
+                double m = 0.0;
+                for (int a = 0; a < NA; ++a)
+                    for (int b = 0; b < NB; ++b) m = fmax(m, fabs(O(a, b, a, b)));
+                out0[bra_off + i] = sqrt(m);
+            }
+        } else if (MODE == kModeDense) {
+            const int64_t NN = N;
+            for (int o = lane; o < A.nout; o += 64) {
+                const int d = o % ND, cc = (o / ND) % NC, b = (o / (ND * NC)) % NB, a = o / (ND * NC * NB);
+                const double v = H[A.outslot[o]] * A.outscale[o];
+                const int64_t ia = bra.bfa + a, ib = bra.bfb + b, ic = ket.bfa + cc, id = ket.bfb + d;
+                out0[((ia * NN + ib) * NN + ic) * NN + id] = v;
+                out0[((ib * NN + ia) * NN + ic) * NN + id] = v;
+                out0[((ia * NN + ib) * NN + id) * NN + ic] = v;
+                out0[((ib * NN + ia) * NN + id) * NN + ic] = v;
+                out0[((ic * NN + id) * NN + ia) * NN + ib] = v;
+                out0[((id * NN + ic) * NN + ia) * NN + ib] = v;
+                out0[((ic * NN + id) * NN + ib) * NN + ia] = v;
+                out0[((id * NN + ic) * NN + ib) * NN + ia] = v;
+            }
+        } else {
+            double fac = 1.0;
+            if (bra.sa == bra.sb) fac *= 0.5;
+            if (ket.sa == ket.sb) fac *= 0.5;
+            if (same_class && i == j) fac *= 0.5;
+            const int a0 = bra.bfa, b0 = bra.bfb, c0 = ket.bfa, d0 = ket.bfb;
+            auto Dv = [&](int r, int cidx) { return D[(int64_t)r * N + cidx]; };
+            double *Gj = out0, *Gk = out1;
+            const int nab = NA * NB, ncd = NC * ND;
+            // six target families, lanes over their elements
+            const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
+            const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0,
+                      t_bd = Gk ? NB * ND : 0;
+            const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
+            for (int t = lane; t < ntgt; t += 64) {
+                int r = t;
+                double s = 0.0;
+                if (r < t_ab) {
+                    const int a = r / NB, b = r % NB;
+                    for (int cc = 0; cc < NC; ++cc)
+                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(c0 + cc, d0 + d);
+                    unsafeAtomicAdd(&Gj[(int64_t)(a0 + a) * N + b0 + b], 2.0 * fac * s);
+                    continue;
+                }
+                r -= t_ab;
+                if (r < t_cd) {
+                    const int cc = r / ND, d = r % ND;
+                    for (int a = 0; a < NA; ++a)
+                        for (int b = 0; b < NB; ++b) s += O(a, b, cc, d) * Dv(a0 + a, b0 + b);
+                    unsafeAtomicAdd(&Gj[(int64_t)(c0 + cc) * N + d0 + d], 2.0 * fac * s);
+                    continue;
+                }
+                r -= t_cd;
+                if (r < t_ac) {
+                    const int a = r / NC, cc = r % NC;
+                    for (int b = 0; b < NB; ++b)
+                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(b0 + b, d0 + d);
+                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + c0 + cc], fac * s);
+                    continue;
+                }
+                r -= t_ac;
+                if (r < t_bc) {
+                    const int b = r / NC, cc = r % NC;
+                    for (int a = 0; a < NA; ++a)
+                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(a0 + a, d0 + d);
+                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + c0 + cc], fac * s);
+                    continue;
+                }
+                r -= t_bc;
+                if (r < t_ad) {
+                    const int a = r / ND, d = r % ND;
+                    for (int b = 0; b < NB; ++b)
+                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(b0 + b, c0 + cc);
+                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + d0 + d], fac * s);
+                    continue;
+                }
+                r -= t_ad;
+                {
+                    const int b = r / ND, d = r % ND;
+                    for (int a = 0; a < NA; ++a)
+                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(a0 + a, c0 + cc);
+                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + d0 + d], fac * s);
+                }
+            }
+        }
+        __syncthreads();  // H reused by the next quartet
+    }
+}
+
+static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t total, double *out0, double *out1,
+                       const double *D) {
+    const CoopProgram *P = coop_program(cb, ck);
+    if (!P) {
+        set_error("internal: cooperative program for class (%d,%d) could not be built", cb, ck);
+        return MESS_E_DEVICE;
+    }
+    if (total <= 0) return MESS_OK;
+    CoopArgs A;
+    A.vops = P->d_vops; A.vlev = P->d_vlev; A.accsrc = P->d_accsrc;
+    A.hops = P->d_hops; A.hlev = P->d_hlev; A.outslot = P->d_outslot; A.outscale = P->d_outscale;
+    A.nV = P->nV; A.nH = P->nH; A.nacc = P->nacc; A.nout = P->nout;
+    A.nvlev = P->nvlev; A.nhlev = P->nhlev; A.L = P->L;
+    A.NA = ncart(P->LA); A.NB = ncart(P->LB); A.NC = ncart(P->LC); A.ND = ncart(P->LD);
+    int64_t g = total;
+    if (g > (1 << 20)) g = 1 << 20;
+    const size_t lds = P->lds_bytes;
+    if (lds > 160 * 1024) {
+        set_error("internal: class (%d,%d) needs %zu bytes of LDS", cb, ck, lds);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (lds > 64 * 1024) {
+        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeSchwarz>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeDense>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeJK>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    switch (mode) {
+        case kModeSchwarz:
+            hipLaunchKernelGGL(k_coop<kModeSchwarz>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
+            break;
+        case kModeDense:
+            hipLaunchKernelGGL(k_coop<kModeDense>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
+            break;
+        default:
+            hipLaunchKernelGGL(k_coop<kModeJK>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
+    }
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+int coop_schwarz(int c, const ClassLaunch &L, int off, int n, double *Q) {
+    ClassLaunch L2 = L;
+    L2.bra_off = off;
+    L2.ket_off = off;
+    return coop_launch(kModeSchwarz, c, c, L2, n, Q - 0, nullptr, nullptr);
+}
+
+int coop_dense(int cb, int ck, const ClassLaunch &L, double *eri, int prec) {
+    if (prec != MESS_FP64) {
+        set_error("dense ERI store: only MESS_FP64 arithmetic is built for this layout");
+        return MESS_E_UNSUPPORTED;
+    }
+    return coop_launch(kModeDense, cb, ck, L, L.total, eri, nullptr, nullptr);
+}
+
+int coop_jk(int cb, int ck, const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec) {
+    if (prec != MESS_FP64) {
+        set_error("direct J/K: FP32 arithmetic is not built for class (%d,%d)", cb, ck);
+        return MESS_E_UNSUPPORTED;
+    }
+    return coop_launch(kModeJK, cb, ck, L, L.total, Gj, Gk, D);
+}
+
+}  // namespace mess
+
+// The high classes are reached through the same ClassOps interface as the
+// unrolled ones; eri_class.hip is not compiled for them.
+namespace mess {
+#define MESS_COOP_CLASS(B, K)                                                                          \
+    template <>                                                                                        \
+    int ClassOps<B, K>::schwarz(const ClassLaunch &L, int off, int n, double *Q) {                     \
+        if (B != K) {                                                                                  \
+            set_error("internal: Schwarz launch for a mixed class");                                   \
+            return MESS_E_ARG;                                                                         \
+        }                                                                                              \
+        return coop_schwarz(B, L, off, n, Q);                                                          \
+    }                                                                                                  \
+    template <>                                                                                        \
+    int ClassOps<B, K>::dense(const ClassLaunch &L, double *eri, int prec) {                           \
+        return coop_dense(B, K, L, eri, prec);                                                         \
+    }                                                                                                  \
+    template <>                                                                                        \
+    int ClassOps<B, K>::jk(const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec) {  \
+        return coop_jk(B, K, L, D, Gj, Gk, prec);                                                      \
+    }
+MESS_COOP_CLASS(4, 2)
+MESS_COOP_CLASS(4, 4)
+MESS_COOP_CLASS(5, 2)
+MESS_COOP_CLASS(5, 3)
+MESS_COOP_CLASS(5, 4)
+MESS_COOP_CLASS(5, 5)
+#undef MESS_COOP_CLASS
+}  // namespace mess

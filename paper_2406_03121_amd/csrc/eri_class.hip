@@ -1,0 +1,67 @@
+// One angular class of shell quartets.  This file is compiled once per
+// class with -DMESS_CB=<bra pair class> -DMESS_CK=<ket pair class>, so the
+// 21 fully unrolled class kernels build in parallel.
+#include "class_ops.hpp"
+#include "eri_kernels.hpp"
+
+#ifndef MESS_CB
+#error "compile with -DMESS_CB=<0..5> -DMESS_CK=<0..MESS_CB>"
+#endif
+
+namespace mess {
+
+namespace {
+inline unsigned grid_for(int64_t total, int block) {
+    int64_t g = (total + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (1 << 20)) g = 1 << 20;
+    return static_cast<unsigned>(g);
+}
+}  // namespace
+
+template <>
+int ClassOps<MESS_CB, MESS_CK>::schwarz(const ClassLaunch &L, int off, int n, double *Q) {
+    if constexpr (MESS_CB != MESS_CK) {
+        set_error("internal: Schwarz launch for a mixed class");
+        return MESS_E_ARG;
+    } else {
+        using Dm = ClassOf<MESS_CB, MESS_CK>;
+        if (n <= 0) return MESS_OK;
+        hipLaunchKernelGGL(k_schwarz<Dm>, dim3((n + 63) / 64), dim3(64), 0, L.stream, L.pairs, off, n,
+                           L.pp, L.tab, L.etab, Q);
+        MESS_LAUNCH_CHECK();
+        return MESS_OK;
+    }
+}
+
+template <>
+int ClassOps<MESS_CB, MESS_CK>::dense(const ClassLaunch &L, double *eri, int prec) {
+    using Dm = ClassOf<MESS_CB, MESS_CK>;
+    if (L.total <= 0) return MESS_OK;
+    if (prec != MESS_FP64) {
+        set_error("dense ERI store: only MESS_FP64 arithmetic is built for this layout");
+        return MESS_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(k_eri_dense<Dm>, dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                       L.bra_off, L.ket_off, L.nbra, L.rowstart, L.pp, L.tab, L.etab, (int64_t)L.N, eri);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+template <>
+int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double *Gj, double *Gk,
+                                   int prec) {
+    using Dm = ClassOf<MESS_CB, MESS_CK>;
+    if (L.total <= 0) return MESS_OK;
+    if (prec != MESS_FP64) {
+        set_error("direct J/K: FP32 arithmetic is not built");
+        return MESS_E_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL(k_jk_direct<Dm>, dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                       L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.pp, L.tab, L.etab, D,
+                       L.N, Gj, Gk);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+}  // namespace mess

@@ -1,0 +1,280 @@
+// Device code for contracted electron-repulsion integrals over one shell
+// quartet (ab|cd), l <= 2, by Obara-Saika vertical recursion on primitive
+// quartets followed by Head-Gordon-Pople horizontal recursion on the
+// contracted intermediates.  Every loop is unrolled at compile time for the
+// angular class (LA, LB, LC, LD), so every intermediate has a fixed register
+// slot and no index is computed at run time.
+//
+// The integrals are the closed-form Gaussian integrals of section 3 of the
+// paper (the four-centre Coulomb integrals that the Fock matrix needs).
+#pragma once
+
+#include "mess_internal.hpp"
+
+namespace mess {
+
+// ------------------------------------------------------------------ Boys
+//
+// F_n(T) = int_0^1 t^{2n} exp(-T t^2) dt.
+// T < 60: the highest order needed, F_L, from an 8-term Taylor expansion
+// about the nearest grid point T_k = k/16 (|T - T_k| <= 1/32, truncation
+// below 3e-17 relative) using dF_n/dT = -F_{n+1}; exp(-T) the same way from
+// exp(-T_k); then the downward recurrence F_n = (2T F_{n+1} + e^{-T})/(2n+1),
+// which is stable.  T >= 60: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1 and
+// e^{-T} < 1e-26 relative to every F_n, n <= 8, there) and the upward
+// recurrence F_{n+1} = (2n+1) F_n / (2T).
+
+template <int L>
+__device__ __forceinline__ void boys_f64(double T, const double *__restrict__ tab,
+                                         const double *__restrict__ etab, double (&F)[L + 1]) {
+    if (T < kBoysTmax) {
+        const int k = __double2int_rn(T * kBoysInvStep);
+        const double md = static_cast<double>(k) * (1.0 / kBoysInvStep) - T;  // -(T - T_k), exact
+        const double *row = tab + k * kBoysN + L;
+        double f = row[7];
+        f = row[6] + md * (1.0 / 7.0) * f;
+        f = row[5] + md * (1.0 / 6.0) * f;
+        f = row[4] + md * (1.0 / 5.0) * f;
+        f = row[3] + md * (1.0 / 4.0) * f;
+        f = row[2] + md * (1.0 / 3.0) * f;
+        f = row[1] + md * (1.0 / 2.0) * f;
+        f = row[0] + md * f;
+        F[L] = f;
+        if constexpr (L > 0) {
+            double e = 1.0 + md * (1.0 / 7.0);
+            e = 1.0 + md * (1.0 / 6.0) * e;
+            e = 1.0 + md * (1.0 / 5.0) * e;
+            e = 1.0 + md * (1.0 / 4.0) * e;
+            e = 1.0 + md * (1.0 / 3.0) * e;
+            e = 1.0 + md * (1.0 / 2.0) * e;
+            e = 1.0 + md * e;
+            e *= etab[k];
+            const double t2 = 2.0 * T;
+            static_for<0, L>([&](auto I) {
+                constexpr int m = L - 1 - decltype(I)::value;
+                F[m] = (t2 * F[m + 1] + e) * (1.0 / (2 * m + 1));
+            });
+        }
+    } else {
+        const double rT = 1.0 / T;
+        F[0] = 0.5 * sqrt(M_PI * rT);
+        static_for<0, L>([&](auto I) {
+            constexpr int m = decltype(I)::value;
+            F[m + 1] = F[m] * ((2 * m + 1) * 0.5) * rT;
+        });
+    }
+}
+
+// ------------------------------------------------------------ class dims
+
+template <int LA_, int LB_, int LC_, int LD_>
+struct ClassDims {
+    static constexpr int LA = LA_, LB = LB_, LC = LC_, LD = LD_;
+    static constexpr int LAB = LA + LB, LCD = LC + LD, L = LAB + LCD;
+    static constexpr int NE = cart_off(LAB + 1), NF = cart_off(LCD + 1);
+    static constexpr int E0 = cart_off(LA), F0 = cart_off(LC);
+    static constexpr int NEA = NE - E0, NFA = NF - F0;
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    static constexpr int NAB = NA * NB, NCD = NC * ND;
+    static constexpr int NOUT = NAB * NCD;
+};
+
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// ---------------------------------------------------- primitive quartet
+//
+// Accumulates [e0|f0] for la <= |e| <= la+lb, lc <= |f| <= lc+ld of one
+// primitive quartet into acc[f - F0][e - E0].
+//   bra VRR: [e+1_i|0]^(m) = PA_i [e]^(m) + WP_i [e]^(m+1)
+//                           + e_i/(2p) ([e-1_i]^(m) - rho/p [e-1_i]^(m+1))
+//   ket VRR: [e|f+1_j]^(m) = QC_j [e|f]^(m) + WQ_j [e|f]^(m+1)
+//                           + f_j/(2q) ([e|f-1_j]^(m) - rho/q [e|f-1_j]^(m+1))
+//                           + e_j/(2(p+q)) [e-1_j|f]^(m+1)
+//   base:    [0|0]^(m) = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd F_m(rho |PQ|^2)
+
+// AC = A - C (bra and ket anchor centres); P - Q = AC + PA - QC is exact
+// zero when all four shells share one atom.
+template <class Dm>
+__device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPair &Q,
+                                                 const double (&AC)[3],
+                                                 const double *__restrict__ tab,
+                                                 const double *__restrict__ etab,
+                                                 double (&acc)[Dm::NFA][Dm::NEA]) {
+    constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LCD = Dm::LCD;
+    const double p = P.p, q = Q.p;
+    const double pq = p + q;
+    const double rpq = 1.0 / pq;
+    const double rho = p * q * rpq;
+    const double PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
+    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    // 2 pi^{5/2} = 34.986836655249725
+    const double pref = 34.986836655249725 / (p * q * sqrt(pq)) * P.K * Q.K;
+
+    double F[L + 1];
+    boys_f64<L>(T, tab, etab, F);
+
+    double V[NF][NE][L + 1];
+    static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pref * F[decltype(M)::value]; });
+
+    if constexpr (Dm::LAB > 0) {
+        const double PA[3] = {P.PAx, P.PAy, P.PAz};
+        // W - P = q/(p+q) (Q - P)
+        const double WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
+        const double oo2p = 0.5 / p, rho_p = rho / p;
+        static_for<1, NE>([&](auto EI) {
+            constexpr int e = decltype(EI)::value;
+            constexpr Cart c = cart_of(e);
+            constexpr int i = c.dir();
+            constexpr int ei = c.get(i);
+            constexpr int e1 = c.minus(i).idx();
+            static_for<0, L - c.l() + 1>([&](auto MI) {
+                constexpr int m = decltype(MI)::value;
+                double v = PA[i] * V[0][e1][m] + WP[i] * V[0][e1][m + 1];
+                if constexpr (ei >= 2) {
+                    constexpr int e2 = c.minus(i, 2).idx();
+                    v += (ei - 1) * oo2p * (V[0][e2][m] - rho_p * V[0][e2][m + 1]);
+                }
+                V[0][e][m] = v;
+            });
+        });
+    }
+    if constexpr (LCD > 0) {
+        const double QC[3] = {Q.PAx, Q.PAy, Q.PAz};
+        // W - Q = p/(p+q) (P - Q)
+        const double WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
+        const double oo2q = 0.5 / q, rho_q = rho / q, oo2pq = 0.5 * rpq;
+        static_for<1, NF>([&](auto FI) {
+            constexpr int f = decltype(FI)::value;
+            constexpr Cart cf = cart_of(f);
+            constexpr int nf = cf.l();
+            constexpr int j = cf.dir();
+            constexpr int fj = cf.get(j);
+            constexpr int f1 = cf.minus(j).idx();
+            constexpr int emin = cart_off(cmax(0, LA - (LCD - nf)));
+            static_for<emin, NE>([&](auto EI) {
+                constexpr int e = decltype(EI)::value;
+                constexpr Cart ce = cart_of(e);
+                constexpr int ej = ce.get(j);
+                static_for<0, L - ce.l() - nf + 1>([&](auto MI) {
+                    constexpr int m = decltype(MI)::value;
+                    double v = QC[j] * V[f1][e][m] + WQ[j] * V[f1][e][m + 1];
+                    if constexpr (fj >= 2) {
+                        constexpr int f2 = cf.minus(j, 2).idx();
+                        v += (fj - 1) * oo2q * (V[f2][e][m] - rho_q * V[f2][e][m + 1]);
+                    }
+                    if constexpr (ej >= 1) {
+                        constexpr int e1 = ce.minus(j).idx();
+                        v += ej * oo2pq * V[f1][e1][m + 1];
+                    }
+                    V[f][e][m] = v;
+                });
+            });
+        });
+    }
+    static_for<Dm::F0, NF>([&](auto FI) {
+        constexpr int f = decltype(FI)::value;
+        static_for<Dm::E0, NE>([&](auto EI) {
+            constexpr int e = decltype(EI)::value;
+            acc[f - Dm::F0][e - Dm::E0] += V[f][e][0];
+        });
+    });
+}
+
+// --------------------------------------------------------------- HRR
+//
+// (a, b+1_i| = (a+1_i, b| + AB_i (a, b|, applied to contracted integrals.
+// X[e - off(la)] for la <= |e| <= la+lb  ->  Y[a][b], |a| = la, |b| = lb.
+
+template <int LA, int LB>
+__device__ __forceinline__ void hrr_1(const double (&X)[cart_off(LA + LB + 1) - cart_off(LA)],
+                                      const double AB[3], double (&Y)[ncart(LA) * ncart(LB)]) {
+    constexpr int LAB = LA + LB;
+    constexpr int E0 = cart_off(LA), NE = cart_off(LAB + 1);
+    if constexpr (LB == 0) {
+        static_for<0, ncart(LA)>([&](auto I) { Y[decltype(I)::value] = X[decltype(I)::value]; });
+    } else {
+        double T[cart_off(LB + 1)][NE];
+        static_for<E0, NE>([&](auto EI) {
+            constexpr int e = decltype(EI)::value;
+            T[0][e] = X[e - E0];
+        });
+        static_for<1, cart_off(LB + 1)>([&](auto BI) {
+            constexpr int b = decltype(BI)::value;
+            constexpr Cart cb = cart_of(b);
+            constexpr int k = cb.l();
+            constexpr int i = cb.dir();
+            constexpr int b1 = cb.minus(i).idx();
+            static_for<E0, cart_off(LAB - k + 1)>([&](auto AI) {
+                constexpr int a = decltype(AI)::value;
+                constexpr int a1 = cart_of(a).plus(i).idx();
+                T[b][a] = T[b1][a1] + AB[i] * T[b1][a];
+            });
+        });
+        static_for<0, ncart(LA)>([&](auto AI) {
+            static_for<0, ncart(LB)>([&](auto BI) {
+                constexpr int a = decltype(AI)::value, b = decltype(BI)::value;
+                Y[a * ncart(LB) + b] = T[cart_off(LB) + b][E0 + a];
+            });
+        });
+    }
+}
+
+template <int L>
+__device__ constexpr double comp_scale(int local) {
+    return cart_is_mixed_d(cart_of(cart_off(L) + local)) ? kSqrt3 : 1.0;
+}
+
+// ------------------------------------------------- contracted quartet
+//
+// out[((a*NB + b)*NC + c)*ND + d] = (ab|cd) for normalised Cartesian
+// components a, b, c, d of the bra pair's shells (sa, sb) and the ket
+// pair's shells (sc, sd).
+
+template <class Dm>
+__device__ __forceinline__ void eri_quartet_f64(const PairInfo &bra, const PairInfo &ket,
+                                                const PrimPair *__restrict__ pp,
+                                                const double *__restrict__ tab,
+                                                const double *__restrict__ etab,
+                                                double (&out)[Dm::NOUT]) {
+    double acc[Dm::NFA][Dm::NEA];
+    static_for<0, Dm::NFA>([&](auto F) {
+        static_for<0, Dm::NEA>([&](auto E) { acc[decltype(F)::value][decltype(E)::value] = 0.0; });
+    });
+    const double AC[3] = {bra.Ax - ket.Ax, bra.Ay - ket.Ay, bra.Az - ket.Az};
+    for (int ib = 0; ib < bra.npp; ++ib) {
+        const PrimPair P = pp[bra.pp0 + ib];
+        for (int ik = 0; ik < ket.npp; ++ik) {
+            const PrimPair Q = pp[ket.pp0 + ik];
+            prim_quartet_f64<Dm>(P, Q, AC, tab, etab, acc);
+        }
+    }
+    // bra HRR for every ket index f
+    const double AB[3] = {bra.ABx, bra.ABy, bra.ABz};
+    const double CD[3] = {ket.ABx, ket.ABy, ket.ABz};
+    double Y[Dm::NFA][Dm::NAB];
+    static_for<0, Dm::NFA>([&](auto F) {
+        constexpr int f = decltype(F)::value;
+        hrr_1<Dm::LA, Dm::LB>(acc[f], AB, Y[f]);
+    });
+    // ket HRR for every bra (a, b)
+    static_for<0, Dm::NAB>([&](auto AB_) {
+        constexpr int ab = decltype(AB_)::value;
+        double Xk[Dm::NFA];
+        static_for<0, Dm::NFA>([&](auto F) { Xk[decltype(F)::value] = Y[decltype(F)::value][ab]; });
+        double Yk[Dm::NCD];
+        hrr_1<Dm::LC, Dm::LD>(Xk, CD, Yk);
+        constexpr int a = ab / Dm::NB, b = ab % Dm::NB;
+        constexpr double sab = comp_scale<Dm::LA>(a) * comp_scale<Dm::LB>(b);
+        static_for<0, Dm::NCD>([&](auto CD_) {
+            constexpr int cd = decltype(CD_)::value;
+            constexpr int c = cd / Dm::ND, d = cd % Dm::ND;
+            constexpr double s = sab * comp_scale<Dm::LC>(c) * comp_scale<Dm::LD>(d);
+            if constexpr (s == 1.0)
+                out[ab * Dm::NCD + cd] = Yk[cd];
+            else
+                out[ab * Dm::NCD + cd] = Yk[cd] * s;
+        });
+    });
+}
+
+}  // namespace mess

@@ -1,0 +1,166 @@
+// Shell-quartet kernels: Schwarz factors, dense ERI store, direct J/K.
+// One lane per shell quartet; quartets of one angular class per launch.
+#pragma once
+
+#include "eri_hgp.hpp"
+
+namespace mess {
+
+template <int CB, int CK>
+using ClassOf = ClassDims<pair_class_la(CB), pair_class_lb(CB), pair_class_la(CK), pair_class_lb(CK)>;
+
+// Row of thread t in a ragged work list: largest i with rowstart[i] <= t.
+__device__ __forceinline__ int find_row(const int64_t *__restrict__ rowstart, int nbra, int64_t t) {
+    int lo = 0, hi = nbra;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rowstart[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Q = sqrt(max_{a in sa, b in sb} |(ab|ab)|) for every pair of one class.
+template <class Dm>
+__global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pairs, int off, int n,
+                                                const PrimPair *__restrict__ pp,
+                                                const double *__restrict__ tab,
+                                                const double *__restrict__ etab,
+                                                double *__restrict__ Q) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PairInfo pr = pairs[off + i];
+    double out[Dm::NOUT];
+    eri_quartet_f64<Dm>(pr, pr, pp, tab, etab, out);
+    double m = 0.0;
+    static_for<0, Dm::NAB>([&](auto I) {
+        constexpr int ab = decltype(I)::value;
+        m = fmax(m, fabs(out[ab * Dm::NCD + ab]));
+    });
+    Q[off + i] = sqrt(m);
+}
+
+// Dense N^4 store: every unique quartet writes its block to all eight
+// index permutations.
+template <class Dm>
+__global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ pairs, int bra_off,
+                                                   int ket_off, int nbra,
+                                                   const int64_t *__restrict__ rowstart,
+                                                   const PrimPair *__restrict__ pp,
+                                                   const double *__restrict__ tab,
+                                                   const double *__restrict__ etab, int64_t N,
+                                                   double *__restrict__ eri) {
+    const int64_t total = rowstart[nbra];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = find_row(rowstart, nbra, t);
+        const int j = static_cast<int>(t - rowstart[i]);
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[ket_off + j];
+        double out[Dm::NOUT];
+        eri_quartet_f64<Dm>(bra, ket, pp, tab, etab, out);
+        static_for<0, Dm::NOUT>([&](auto I) {
+            constexpr int k = decltype(I)::value;
+            constexpr int a = k / (Dm::NB * Dm::NCD), b = (k / Dm::NCD) % Dm::NB;
+            constexpr int c = (k / Dm::ND) % Dm::NC, d = k % Dm::ND;
+            const int64_t ia = bra.bfa + a, ib = bra.bfb + b, ic = ket.bfa + c, id = ket.bfb + d;
+            const double v = out[k];
+            eri[((ia * N + ib) * N + ic) * N + id] = v;
+            eri[((ib * N + ia) * N + ic) * N + id] = v;
+            eri[((ia * N + ib) * N + id) * N + ic] = v;
+            eri[((ib * N + ia) * N + id) * N + ic] = v;
+            eri[((ic * N + id) * N + ia) * N + ib] = v;
+            eri[((id * N + ic) * N + ia) * N + ib] = v;
+            eri[((ic * N + id) * N + ib) * N + ia] = v;
+            eri[((id * N + ic) * N + ib) * N + ia] = v;
+        });
+    }
+}
+
+// Digest one unique quartet block into the half-matrices Gj, Gk
+// (J = Gj + Gj^T, K = Gk + Gk^T).  With v' = v / ((1+d_ab)(1+d_cd)(1+d_ab,cd)):
+//   Gj[a,b] += 2 v' D[c,d]      Gj[c,d] += 2 v' D[a,b]
+//   Gk[a,c] += v' D[b,d]        Gk[b,c] += v' D[a,d]
+//   Gk[a,d] += v' D[b,c]        Gk[b,d] += v' D[a,c]
+// which is the sum of the eight permutation updates of (ab|cd).
+template <class Dm>
+__device__ __forceinline__ void digest_jk(const double (&out)[Dm::NOUT], double fac, int a0, int b0,
+                                          int c0, int d0, const double *__restrict__ D, int N,
+                                          double *__restrict__ Gj, double *__restrict__ Gk) {
+    constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND;
+    auto O = [&](int a, int b, int c, int d) -> double { return out[((a * NB + b) * NC + c) * ND + d]; };
+    auto Dv = [&](int r, int c) -> double { return D[(int64_t)r * N + c]; };
+    if (Gj) {
+        double Dcd[NC][ND], Dab[NA][NB];
+        static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+            Dcd[C][Dd] = Dv(c0 + C, d0 + Dd); }); });
+        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+            Dab[A][B] = Dv(a0 + A, b0 + B); }); });
+        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+            double s = 0.0;
+            static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+                s += O(A, B, C, Dd) * Dcd[C][Dd]; }); });
+            unsafeAtomicAdd(&Gj[(int64_t)(a0 + A) * N + b0 + B], 2.0 * fac * s);
+        }); });
+        static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+            double s = 0.0;
+            static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                s += O(A, B, C, Dd) * Dab[A][B]; }); });
+            unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * fac * s);
+        }); });
+    }
+    if (Gk) {
+        double Dbd[NB][ND], Dad[NA][ND], Dbc[NB][NC], Dac[NA][NC];
+        static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { Dbd[B][Dd] = Dv(b0 + B, d0 + Dd); }); });
+        static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { Dad[A][Dd] = Dv(a0 + A, d0 + Dd); }); });
+        static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { Dbc[B][C] = Dv(b0 + B, c0 + C); }); });
+        static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { Dac[A][C] = Dv(a0 + A, c0 + C); }); });
+        static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) {
+            double s = 0.0;
+            static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dbd[B][Dd]; }); });
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + c0 + C], fac * s);
+        }); });
+        static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) {
+            double s = 0.0;
+            static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dad[A][Dd]; }); });
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + c0 + C], fac * s);
+        }); });
+        static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) {
+            double s = 0.0;
+            static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dbc[B][C]; }); });
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + d0 + Dd], fac * s);
+        }); });
+        static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) {
+            double s = 0.0;
+            static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dac[A][C]; }); });
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + d0 + Dd], fac * s);
+        }); });
+    }
+}
+
+template <class Dm>
+__global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ pairs, int bra_off,
+                                                   int ket_off, int nbra, int same_class,
+                                                   const int64_t *__restrict__ rowstart,
+                                                   const PrimPair *__restrict__ pp,
+                                                   const double *__restrict__ tab,
+                                                   const double *__restrict__ etab,
+                                                   const double *__restrict__ D, int N,
+                                                   double *__restrict__ Gj, double *__restrict__ Gk) {
+    const int64_t total = rowstart[nbra];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = find_row(rowstart, nbra, t);
+        const int j = static_cast<int>(t - rowstart[i]);
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[ket_off + j];
+        double out[Dm::NOUT];
+        eri_quartet_f64<Dm>(bra, ket, pp, tab, etab, out);
+        double fac = 1.0;
+        if (bra.sa == bra.sb) fac *= 0.5;
+        if (ket.sa == ket.sb) fac *= 0.5;
+        if (same_class && i == j) fac *= 0.5;
+        digest_jk<Dm>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
+    }
+}
+
+}  // namespace mess

@@ -1,0 +1,135 @@
+// mess_eri and mess_jk: class-by-class launches over the unique
+// shell-quartet work lists, then the symmetrisation J = Gj + Gj^T,
+// K = Gk + Gk^T of the half-matrices the digestion accumulates.
+#include "class_ops.hpp"
+#include "mess_internal.hpp"
+
+namespace mess {
+
+int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out);
+int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, ClassLaunch &L);
+int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+
+__global__ void k_fill_zero(double *__restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// out = G + G^T (N x N).
+__global__ void k_symmetrise(const double *__restrict__ G, int N, double *__restrict__ out) {
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && j < N) out[(int64_t)i * N + j] = G[(int64_t)i * N + j] + G[(int64_t)j * N + i];
+}
+
+int zero_async(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return MESS_OK;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)g), dim3(256), 0, s, p, n);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+int symmetrise_async(const double *G, int N, double *out, hipStream_t s) {
+    dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
+    hipLaunchKernelGGL(k_symmetrise, grd, blk, 0, s, G, N, out);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+// Gj, Gk (device, N x N, may be NULL) <- half-matrices of J and K.
+int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau,
+                   hipStream_t s) {
+    WorkLists *W = nullptr;
+    MESS_TRY(get_work_lists(B, tau, s, &W));
+    const int64_t NN = (int64_t)B->nbf * B->nbf;
+    if (Gj) MESS_TRY(zero_async(Gj, NN, s));
+    if (Gk) MESS_TRY(zero_async(Gk, NN, s));
+    for (const ClassList &cl : W->classes) {
+        if (cl.total == 0) continue;
+        ClassLaunch L;
+        fill_class_launch(B, cl, s, L);
+        MESS_TRY(dispatch_class(cl.cb, cl.ck, [&](auto CB, auto CK) {
+            return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(L, D, Gj, Gk, prec);
+        }));
+    }
+    return MESS_OK;
+}
+
+int jk_full(mess_basis *B, const double *D, double *J, double *K, int mode, int prec, double tau,
+            hipStream_t s) {
+    const int N = B->nbf;
+    double *Gj = J ? static_cast<double *>(B->scratch_jk) : nullptr;
+    double *Gk = K ? static_cast<double *>(B->scratch_jk) + (int64_t)N * N : nullptr;
+    if (mode == MESS_JK_DIRECT)
+        MESS_TRY(jk_direct_half(B, D, Gj, Gk, prec, tau, s));
+    else
+        MESS_TRY(jk_stored(B, D, Gj, Gk, prec, tau, s));
+    if (J) MESS_TRY(symmetrise_async(Gj, N, J, s));
+    if (K) MESS_TRY(symmetrise_async(Gk, N, K, s));
+    return MESS_OK;
+}
+
+}  // namespace mess
+
+using namespace mess;
+
+extern "C" {
+
+int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwarz_tol, void *out,
+             size_t out_bytes, mess_stream stream) {
+    if (!basis || !out) {
+        set_error("mess_eri: NULL basis or output");
+        return MESS_E_ARG;
+    }
+    if (prec != MESS_FP64 && prec != MESS_FP32) {
+        set_error("mess_eri: unknown precision %d", prec);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (layout != MESS_ERI_DENSE) {
+        set_error("mess_eri: layout %d is not supported by this entry point", layout);
+        return MESS_E_UNSUPPORTED;
+    }
+    auto *B = const_cast<mess_basis *>(basis);
+    const int64_t N = B->nbf;
+    const size_t need = sizeof(double) * (size_t)(N * N * N * N);
+    if (out_bytes < need) {
+        set_error("mess_eri: output holds %zu bytes, %zu needed", out_bytes, need);
+        return MESS_E_SIZE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WorkLists *W = nullptr;
+    MESS_TRY(get_work_lists(B, schwarz_tol, s, &W));
+    MESS_TRY(zero_async(static_cast<double *>(out), N * N * N * N, s));
+    for (const ClassList &cl : W->classes) {
+        if (cl.total == 0) continue;
+        ClassLaunch L;
+        fill_class_launch(B, cl, s, L);
+        MESS_TRY(dispatch_class(cl.cb, cl.ck, [&](auto CB, auto CK) {
+            return ClassOps<decltype(CB)::value, decltype(CK)::value>::dense(L, static_cast<double *>(out), prec);
+        }));
+    }
+    return MESS_OK;
+}
+
+int mess_jk(const mess_basis *basis, const double *D, double *J, double *K, int32_t mode, int32_t prec,
+            double schwarz_tol, mess_stream stream) {
+    if (!basis || !D) {
+        set_error("mess_jk: NULL basis or density");
+        return MESS_E_ARG;
+    }
+    if (mode != MESS_JK_DIRECT && mode != MESS_JK_STORED) {
+        set_error("mess_jk: unknown mode %d", mode);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (prec != MESS_FP64 && prec != MESS_FP32) {
+        set_error("mess_jk: unknown precision %d", prec);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (!J && !K) return MESS_OK;
+    return jk_full(const_cast<mess_basis *>(basis), D, J, K, mode, prec, schwarz_tol,
+                   static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Dense FP64 linear algebra for the SCF step: a tiled GEMM, a one-workgroup
+// cyclic Jacobi eigensolver (used once per geometry for the overlap matrix)
+// and elementwise helpers.
+#include <cmath>
+
+#include "linalg.hpp"
+
+namespace mess {
+
+// ------------------------------------------------------------------ GEMM
+//
+// 64 x 64 output tile per 256-thread block, 4 x 4 per thread, K in steps of
+// 16 staged through LDS.  FP64 vector FMA: on gfx950 the FP64 matrix cores
+// have the same peak rate as the vector units, and these products are small
+// (N <= ~1000), so the tile is sized for latency, not for MFMA.
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                              int lda, const double *__restrict__ B, int ldb, double beta,
+                                              double *__restrict__ C, int ldc) {
+    __shared__ double As[kTK][kTM + 1];
+    __shared__ double Bs[kTK][kTN + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += kTK) {
+        for (int t = threadIdx.x; t < kTK * kTM; t += 256) {
+            const int kk = t / kTM, mm = t % kTM;
+            const int gr = row0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gr < M && gk < K) v = TA ? A[(int64_t)gk * lda + gr] : A[(int64_t)gr * lda + gk];
+            As[kk][mm] = v;
+        }
+        for (int t = threadIdx.x; t < kTK * kTN; t += 256) {
+            const int kk = t / kTN, nn = t % kTN;
+            const int gc = col0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gc < N && gk < K) v = TB ? B[(int64_t)gc * ldb + gk] : B[(int64_t)gk * ldb + gc];
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = row0 + ty + 16 * i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = col0 + tx + 16 * j;
+            if (c >= N) continue;
+            double v = alpha * acc[i][j];
+            if (beta != 0.0) v += beta * C[(int64_t)r * ldc + c];
+            C[(int64_t)r * ldc + c] = v;
+        }
+    }
+}
+
+int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
+         const double *B, int ldb, double beta, double *C, int ldc) {
+    if (M <= 0 || N <= 0) return MESS_OK;
+    dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), blk(256);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((k_gemm<false, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((k_gemm<true, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((k_gemm<false, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+        hipLaunchKernelGGL((k_gemm<true, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ X, double b, const double *__restrict__ Y,
+                        double *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a * X[i] + (Y ? b * Y[i] : 0.0);
+}
+
+int axpby(hipStream_t s, int64_t n, double a, const double *X, double b, const double *Y, double *out) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)g), dim3(256), 0, s, n, a, X, b, Y, out);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+// ------------------------------------------------------------- Jacobi
+//
+// Two-sided cyclic Jacobi with the round-robin ("circle") ordering: in each
+// of the m-1 rounds of a sweep (m = n rounded up to even) the indices are
+// split into m/2 disjoint pairs (p, q); each pair's rotation
+//   tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1/sqrt(1 + t^2), s = t c
+// annihilates a_pq; rows then columns of A, and the columns of V, are
+// rotated for all pairs at once.  Sweeps stop when every off-diagonal
+// element is below 1e-14 sqrt(|a_pp a_qq|) (or after 20 sweeps).
+
+__global__ void __launch_bounds__(1024) k_jacobi(int n, double *__restrict__ A, double *__restrict__ V,
+                                                 double *__restrict__ w) {
+    __shared__ double cs[512], sn[512];
+    __shared__ int pp[512], qq[512];
+    __shared__ double red[1024];
+    __shared__ int done;
+    const int tid = threadIdx.x;
+    const int m = n + (n & 1);
+    const int npairs = m / 2;
+    for (int idx = tid; idx < n * n; idx += 1024) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 20; ++sweep) {
+        // convergence test: every |a_pq| <= 1e-14 sqrt(|a_pp a_qq|)
+        double worst = 0.0;
+        for (int idx = tid; idx < n * n; idx += 1024) {
+            const int i = idx / n, j = idx % n;
+            if (i == j) continue;
+            const double d = sqrt(fabs(A[(int64_t)i * n + i] * A[(int64_t)j * n + j]));
+            const double a = fabs(A[idx]);
+            const double ratio = d > 0.0 ? a / d : (a > 0.0 ? 1.0 : 0.0);
+            worst = fmax(worst, ratio);
+        }
+        red[tid] = worst;
+        __syncthreads();
+        for (int st = 512; st > 0; st >>= 1) {
+            if (tid < st) red[tid] = fmax(red[tid], red[tid + st]);
+            __syncthreads();
+        }
+        if (tid == 0) done = red[0] <= 1e-14 ? 1 : 0;
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < m - 1; ++r) {
+            if (tid < npairs) {
+                int p, q;
+                if (tid == 0) {
+                    p = r;
+                    q = m - 1;
+                } else {
+                    p = (r + tid) % (m - 1);
+                    q = (r - tid + (m - 1)) % (m - 1);
+                }
+                if (p > q) { const int t = p; p = q; q = t; }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[(int64_t)p * n + q];
+                    if (apq != 0.0) {
+                        const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int it = tid; it < npairs * n; it += 1024) {
+                const int k = it / n, j = it % n;
+                const int p = pp[k], q = qq[k];
+                if (q >= n) continue;
+                const double c = cs[k], s = sn[k];
+                const double ap = A[(int64_t)p * n + j], aq = A[(int64_t)q * n + j];
+                A[(int64_t)p * n + j] = c * ap - s * aq;
+                A[(int64_t)q * n + j] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int it = tid; it < 2 * npairs * n; it += 1024) {
+                const int which = it / (npairs * n);
+                const int rem = it % (npairs * n);
+                const int k = rem / n, i = rem % n;
+                const int p = pp[k], q = qq[k];
+                if (q >= n) continue;
+                const double c = cs[k], s = sn[k];
+                double *X = which ? V : A;
+                const double xp = X[(int64_t)i * n + p], xq = X[(int64_t)i * n + q];
+                X[(int64_t)i * n + p] = c * xp - s * xq;
+                X[(int64_t)i * n + q] = s * xp + c * xq;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < n; i += 1024) w[i] = A[(int64_t)i * n + i];
+}
+
+// Sort eigenpairs ascending: rank of each eigenvalue (ties by index), then
+// gather the columns of V into Vs.
+__global__ void __launch_bounds__(1024) k_sort_eig(int n, const double *__restrict__ w, const double *__restrict__ V,
+                                                   double *__restrict__ ws, double *__restrict__ Vs) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double wi = w[i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += (w[j] < wi) || (w[j] == wi && j < i);
+        ws[r] = wi;
+        for (int row = 0; row < n; ++row) Vs[(int64_t)row * n + r] = V[(int64_t)row * n + i];
+    }
+}
+
+int jacobi_eigh(hipStream_t s, int n, double *A, double *w, double *V, double *work) {
+    if (n > 1024) {
+        set_error("eigensolver: n = %d exceeds the 1024 supported", n);
+        return MESS_E_UNSUPPORTED;
+    }
+    // work: n*n (unsorted vectors) + n (unsorted values)
+    double *Vu = work, *wu = work + (int64_t)n * n;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, n, A, Vu, wu);
+    MESS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sort_eig, dim3(1), dim3(1024), 0, s, n, wu, Vu, w, V);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+}  // namespace mess

@@ -1,0 +1,199 @@
+// Internal declarations shared by the HIP translation units of libmess_hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mess.h"
+
+namespace mess {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const char *fmt, ...);
+
+struct Status {
+    int code = MESS_OK;
+};
+
+#define MESS_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            ::mess::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e),   \
+                              __FILE__, __LINE__);                                     \
+            return (_e == hipErrorOutOfMemory) ? MESS_E_NOMEM : MESS_E_DEVICE;         \
+        }                                                                              \
+    } while (0)
+
+#define MESS_TRY(expr)                     \
+    do {                                   \
+        int _rc = (expr);                  \
+        if (_rc != MESS_OK) return _rc;    \
+    } while (0)
+
+// Launch check: catches bad launch configurations immediately.
+#define MESS_LAUNCH_CHECK() MESS_HIP(hipGetLastError())
+
+// -------------------------------------------------- compile-time loops
+
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// Calls f(integral_constant<int, i>) for i in [Begin, End).
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (Begin < End) {
+        static_for_impl(
+            [&](auto i) { f(std::integral_constant<int, Begin + decltype(i)::value>{}); },
+            std::make_integer_sequence<int, End - Begin>{});
+    }
+}
+
+// --------------------------------------------- Cartesian component tables
+//
+// Components of angular momentum l are ordered x-major lexicographically:
+// (l,0,0), (l-1,1,0), (l-1,0,1), (l-2,2,0), ...  A "global" index counts
+// the components of all l' < l first, so every component of every
+// angular momentum up to some maximum has one index.
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int cart_off(int l) { return l * (l + 1) * (l + 2) / 6; }
+__host__ __device__ constexpr int cart_idx(int x, int y, int z) {
+    return cart_off(x + y + z) + (y + z) * (y + z + 1) / 2 + z;
+}
+
+struct Cart {
+    int x, y, z;
+    __host__ __device__ constexpr int l() const { return x + y + z; }
+    __host__ __device__ constexpr int get(int d) const { return d == 0 ? x : (d == 1 ? y : z); }
+    // Direction used to lower this component in a recurrence: the first
+    // direction with a non-zero exponent.
+    __host__ __device__ constexpr int dir() const { return x > 0 ? 0 : (y > 0 ? 1 : 2); }
+    __host__ __device__ constexpr Cart minus(int d, int k = 1) const {
+        return Cart{x - (d == 0 ? k : 0), y - (d == 1 ? k : 0), z - (d == 2 ? k : 0)};
+    }
+    __host__ __device__ constexpr Cart plus(int d, int k = 1) const { return minus(d, -k); }
+    __host__ __device__ constexpr int idx() const { return cart_idx(x, y, z); }
+};
+
+__host__ __device__ constexpr Cart cart_of(int idx) {
+    int l = 0;
+    while (cart_off(l + 1) <= idx) ++l;
+    int r = idx - cart_off(l);
+    int k = 0;  // k = l - lx
+    while ((k + 1) * (k + 2) / 2 <= r) ++k;
+    int z = r - k * (k + 1) / 2;
+    return Cart{l - k, k - z, z};
+}
+
+// Ratio N(alpha; lx,ly,lz) / N(alpha; l,0,0) of primitive normalisation
+// constants, i.e. sqrt((2l-1)!! / ((2lx-1)!! (2ly-1)!! (2lz-1)!!)).  For
+// l <= 2 it is sqrt(3) for the mixed d components (xy, xz, yz), else 1.
+__host__ __device__ constexpr bool cart_is_mixed_d(Cart c) {
+    return c.l() == 2 && c.x < 2 && c.y < 2 && c.z < 2;
+}
+constexpr double kSqrt3 = 1.7320508075688772935;
+
+// ------------------------------------------------------------ device data
+
+// One shell pair (a, b) with l_a >= l_b.  A is the centre of shell a,
+// AB = A - B.  Primitive pairs live in pp[pp0 .. pp0 + npp).
+struct PairInfo {
+    double Ax, Ay, Az;
+    double ABx, ABy, ABz;
+    int pp0, npp;
+    int sa, sb;    // shell indices
+    int bfa, bfb;  // first basis function of each shell
+};
+
+// One primitive pair (alpha on A, beta on B): p = alpha + beta,
+// PA = P - A = -(beta/p) AB (computed from AB so it is exactly zero when
+// both shells sit on one atom), K = c_a c_b exp(-alpha beta/p |AB|^2) with
+// c the normalised contraction coefficients of the l,0,0 component.
+// The Gaussian product centre is P = A + PA.
+struct PrimPair {
+    double PAx, PAy, PAz, p;
+    double K, rp, pad0, pad1;  // rp = 1/p
+};
+
+struct PrimPairF {
+    float PAx, PAy, PAz, p;
+    float K, rp, pad0, pad1;
+};
+
+// Boys table: F_n(T_k), n = 0..kBoysN-1, T_k = k / kBoysInvStep, T_k <= kBoysTmax.
+constexpr int kBoysN = 16;
+constexpr double kBoysInvStep = 16.0;
+constexpr double kBoysTmax = 60.0;
+constexpr int kBoysRows = 961;  // kBoysTmax * kBoysInvStep + 1
+
+// Pair classes (l_a, l_b), l_a >= l_b: ss ps pp ds dp dd.
+constexpr int kNumPairClasses = 6;
+__host__ __device__ constexpr int pair_class_la(int c) { return c == 0 ? 0 : (c <= 2 ? 1 : 2); }
+__host__ __device__ constexpr int pair_class_lb(int c) {
+    return c == 0 ? 0 : (c == 1 ? 0 : (c == 2 ? 1 : (c == 3 ? 0 : (c == 4 ? 1 : 2))));
+}
+inline int pair_class_of(int la, int lb) {
+    // la >= lb
+    if (la == 0) return 0;
+    if (la == 1) return lb == 0 ? 1 : 2;
+    return lb == 0 ? 3 : (lb == 1 ? 4 : 5);
+}
+
+// Unique shell-quartet work list of one class: bra pairs of class cb and
+// ket pairs of class ck (cb >= ck), both sorted by Schwarz factor
+// (descending).  Bra row i holds kets [0, count_i); rowstart is the
+// exclusive scan of the counts.
+struct ClassList {
+    int cb, ck;
+    int nbra;
+    int64_t total = 0;
+    int64_t *d_rowstart = nullptr;  // nbra + 1
+};
+
+struct WorkLists {
+    double tau = -1.0;
+    std::vector<ClassList> classes;  // 21 (cb >= ck), in a fixed order
+};
+
+struct StoredEri;  // mess_jk(STORED) cache
+
+}  // namespace mess
+
+struct mess_basis {
+    int nat = 0, nsh = 0, nbf = 0, nelec = 0, nocc = 0;
+    double enuc = 0.0;
+    std::vector<int> Z, sh_atom, sh_l, sh_np, sh_prim0, sh_bf0;
+    std::vector<double> xyz, alpha, ctilde;  // ctilde: normalised coefs (l,0,0)
+    int device = 0;
+
+    // device tables
+    double *d_xyz = nullptr;   // [nat*3]
+    double *d_Zd = nullptr;    // [nat] charges as double
+    double *d_boys = nullptr;  // [kBoysRows * kBoysN]
+    double *d_boys_exp = nullptr;  // [kBoysRows]: exp(-T_k)
+    float *d_boys_f = nullptr;     // FP32 copy of the table
+    float *d_boys_exp_f = nullptr;
+
+    int npair = 0;
+    int pair_class_off[mess::kNumPairClasses + 1] = {0};
+    mess::PairInfo *d_pairs = nullptr;     // sorted by class, then Q descending
+    double *d_pairQ = nullptr;             // Schwarz factor per sorted pair
+    mess::PrimPair *d_pp = nullptr;        // primitive pairs (unsorted)
+    mess::PrimPairF *d_ppf = nullptr;      // FP32 copy
+    int npp = 0;
+    std::vector<double> pairQ_host;        // for diagnostics
+
+    std::map<double, mess::WorkLists *> lists;  // keyed by tau
+    std::map<std::pair<int, double>, mess::StoredEri *> stored;  // (prec, tau)
+    void *scratch_jk = nullptr;   // [2 * nbf * nbf] doubles: Gj, Gk
+};

@@ -1,0 +1,610 @@
+// Self-consistent field iteration for the Roothaan equation F(C) C = S C eps
+// (paper section 3, eq. 2), closed shell, on the device.
+//
+// Per step at density D_k:  J, K <- D_k;  F_k = H + J - K/2;
+// E_k = 1/2 Tr[D_k (H + F_k)] + E_nuc;  commutator e_k = X^T (F D S - S D F) X;
+// then (unless converged) optional Pulay DIIS on F, F' = X^T F X and the new
+// density D_{k+1} = 2 X P X^T where P is the projector onto the n_occ lowest
+// eigenvectors of F'.  X is the canonical orthogonaliser U s^{-1/2} over the
+// eigenpairs of S with s > 1e-7 (eq. 5: C^T S C = 1 for C = X C').
+//
+// P is obtained without an eigensolver by trace-correcting second-order
+// spectral projection: X_0 = (e_max - F') / (e_max - e_min) with Gershgorin
+// bounds, then repeatedly X <- X^2 or X <- 2X - X^2, whichever moves the
+// trace towards n_occ.  The fixed point is the same projector an aufbau
+// occupation of the eigenvectors gives whenever the HOMO-LUMO gap is open.
+#include <cmath>
+#include <vector>
+
+#include "class_ops.hpp"
+#include "linalg.hpp"
+#include "mess_internal.hpp"
+
+namespace mess {
+
+int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+int zero_async(double *p, int64_t n, hipStream_t s);
+
+constexpr int kMaxDiis = 16;
+
+// Device scalars shared by the small kernels of one step.
+struct ScfScalars {
+    double energy, resid;
+    double emin, emax;
+    double trX, trX2;
+    double idem;          // tr(X) - tr(X^2) of the last purification step
+    int sp2_iter, sp2_done, sp2_post;
+    int pad;
+    double diis_c[kMaxDiis + 1];
+};
+
+}  // namespace mess
+
+struct mess_scf {
+    mess_basis *basis = nullptr;
+    mess_scf_opts opts{};
+    int N = 0, M = 0;  // basis functions, orthonormal functions kept
+    int iter = 0;
+    double e_prev = 0.0;
+    hipStream_t create_stream = nullptr;
+    // device buffers
+    double *S = nullptr, *H = nullptr, *X = nullptr, *D = nullptr, *F = nullptr, *Fx = nullptr;
+    double *Gj = nullptr, *Gk = nullptr;
+    double *W1 = nullptr, *W2 = nullptr, *W3 = nullptr;  // N x N work
+    double *P = nullptr, *P2 = nullptr;                  // M x M purification
+    double *Fh = nullptr, *Eh = nullptr;                 // DIIS history [kMaxDiis][N*N], [kMaxDiis][M*M]
+    double *Bm = nullptr;                                // DIIS B matrix kMaxDiis^2
+    mess::ScfScalars *sc = nullptr;
+    double *partial = nullptr;                           // reduction partials
+    std::vector<int> hist;  // history slots, oldest first
+    int next_slot = 0;
+    int sp2_iters_last = 0;
+};
+
+namespace mess {
+
+constexpr int kRedBlocks = 256;
+
+// F = H + (Gj + Gj^T) - 1/2 (Gk + Gk^T), and per-block partial sums of
+// D .* (H + F) (deterministic two-stage reduction).
+__global__ void __launch_bounds__(256) k_fock(int N, const double *__restrict__ H, const double *__restrict__ Gj,
+                                              const double *__restrict__ Gk, const double *__restrict__ D,
+                                              double *__restrict__ F, double *__restrict__ partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < NN; idx += (int64_t)gridDim.x * 256) {
+        const int i = (int)(idx / N), j = (int)(idx % N);
+        const int64_t t = (int64_t)j * N + i;
+        const double f = H[idx] + (Gj[idx] + Gj[t]) - 0.5 * (Gk[idx] + Gk[t]);
+        F[idx] = f;
+        acc += D[idx] * (H[idx] + f);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_finish_energy(int nblk, const double *__restrict__ partial, double enuc,
+                                                       ScfScalars *__restrict__ sc) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += partial[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->energy = 0.5 * red[0] + enuc;
+}
+
+// C = M - M^T
+__global__ void k_antisym(int N, const double *__restrict__ Mx, double *__restrict__ C) {
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / N), j = (int)(idx % N);
+        C[idx] = Mx[idx] - Mx[(int64_t)j * N + i];
+    }
+}
+
+// max |x| over n values -> sc->resid (single block, 1024 threads)
+__global__ void __launch_bounds__(1024) k_maxabs(int64_t n, const double *__restrict__ x, ScfScalars *__restrict__ sc) {
+    __shared__ double red[1024];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, fabs(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->resid = red[0];
+}
+
+// B[slot][k] = B[k][slot] = <E_slot, E_k> for the listed history slots.
+__global__ void __launch_bounds__(256) k_diis_dots(int64_t n, int slot, const int *__restrict__ slots, int nslots,
+                                                   const double *__restrict__ Eh, double *__restrict__ Bm) {
+    __shared__ double red[256];
+    const int k = slots[blockIdx.x];
+    const double *a = Eh + (int64_t)slot * n, *b = Eh + (int64_t)k * n;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += a[i] * b[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Bm[slot * kMaxDiis + k] = red[0];
+        Bm[k * kMaxDiis + slot] = red[0];
+    }
+}
+
+// Solve [[B, -1], [-1^T, 0]] [c; lambda] = [0; -1] by Gaussian elimination
+// with partial pivoting (one thread; m <= kMaxDiis).
+__global__ void k_diis_solve(int m, const int *__restrict__ slots, const double *__restrict__ Bm,
+                             ScfScalars *__restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double A[kMaxDiis + 1][kMaxDiis + 2];
+    const int n = m + 1;
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < m; ++j) A[i][j] = Bm[slots[i] * kMaxDiis + slots[j]];
+        A[i][m] = -1.0;
+        A[i][n] = 0.0;
+    }
+    for (int j = 0; j < m; ++j) A[m][j] = -1.0;
+    A[m][m] = 0.0;
+    A[m][n] = -1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (piv != col)
+            for (int c = 0; c <= n; ++c) {
+                const double t = A[col][c];
+                A[col][c] = A[piv][c];
+                A[piv][c] = t;
+            }
+        const double d = A[col][col];
+        for (int r = col + 1; r < n; ++r) {
+            const double f = d != 0.0 ? A[r][col] / d : 0.0;
+            for (int c = col; c <= n; ++c) A[r][c] -= f * A[col][c];
+        }
+    }
+    double x[kMaxDiis + 1];
+    for (int r = n - 1; r >= 0; --r) {
+        double s = A[r][n];
+        for (int c = r + 1; c < n; ++c) s -= A[r][c] * x[c];
+        x[r] = A[r][r] != 0.0 ? s / A[r][r] : 0.0;
+    }
+    for (int i = 0; i < m; ++i) sc->diis_c[i] = x[i];
+}
+
+// Fx = sum_i c_i Fh[slot_i]
+__global__ void k_diis_combine(int64_t n, int m, const int *__restrict__ slots, const double *__restrict__ Fh,
+                               const ScfScalars *__restrict__ sc, double *__restrict__ Fx) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int i = 0; i < m; ++i) v += sc->diis_c[i] * Fh[(int64_t)slots[i] * n + idx];
+        Fx[idx] = v;
+    }
+}
+
+// Gershgorin bounds of a symmetric M x M matrix (one block).
+__global__ void __launch_bounds__(1024) k_gershgorin(int M, const double *__restrict__ A, ScfScalars *__restrict__ sc) {
+    __shared__ double lo[1024], hi[1024];
+    double l = 1e300, h = -1e300;
+    for (int i = threadIdx.x; i < M; i += 1024) {
+        double r = 0.0;
+        for (int j = 0; j < M; ++j)
+            if (j != i) r += fabs(A[(int64_t)i * M + j]);
+        const double d = A[(int64_t)i * M + i];
+        l = fmin(l, d - r);
+        h = fmax(h, d + r);
+    }
+    lo[threadIdx.x] = l;
+    hi[threadIdx.x] = h;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + st]);
+            hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->emin = lo[0];
+        sc->emax = hi[0] > lo[0] ? hi[0] : lo[0] + 1.0;
+        sc->sp2_iter = 0;
+        sc->sp2_done = 0;
+        sc->sp2_post = 0;
+    }
+}
+
+// X0 = (e_max I - F') / (e_max - e_min)
+__global__ void k_sp2_init(int M, const double *__restrict__ Fp, const ScfScalars *__restrict__ sc,
+                           double *__restrict__ X) {
+    const double emax = sc->emax, inv = 1.0 / (sc->emax - sc->emin);
+    const int64_t MM = (int64_t)M * M;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < MM; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / M), j = (int)(idx % M);
+        X[idx] = ((i == j ? emax : 0.0) - Fp[idx]) * inv;
+    }
+}
+
+// traces of X and X2 (one block)
+__global__ void __launch_bounds__(1024) k_sp2_traces(int M, const double *__restrict__ X, const double *__restrict__ X2,
+                                                     ScfScalars *__restrict__ sc) {
+    __shared__ double a[1024], b[1024];
+    if (sc->sp2_done) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < M; i += 1024) {
+        s1 += X[(int64_t)i * M + i];
+        s2 += X2[(int64_t)i * M + i];
+    }
+    a[threadIdx.x] = s1;
+    b[threadIdx.x] = s2;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            a[threadIdx.x] += a[threadIdx.x + st];
+            b[threadIdx.x] += b[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->trX = a[0];
+        sc->trX2 = b[0];
+        sc->idem = a[0] - b[0];
+    }
+}
+
+// X <- X^2 or 2X - X^2 (trace towards n_occ); convergence bookkeeping.
+__global__ void k_sp2_update(int M, double nocc, double *__restrict__ X, const double *__restrict__ X2,
+                             ScfScalars *__restrict__ sc) {
+    if (sc->sp2_done) return;
+    const double t1 = sc->trX, t2 = sc->trX2;
+    const bool square = fabs(t2 - nocc) < fabs(2.0 * t1 - t2 - nocc);
+    const int64_t MM = (int64_t)M * M;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < MM; idx += (int64_t)gridDim.x * blockDim.x)
+        X[idx] = square ? X2[idx] : 2.0 * X[idx] - X2[idx];
+}
+
+__global__ void k_sp2_bookkeep(ScfScalars *__restrict__ sc) {
+    if (threadIdx.x != 0 || sc->sp2_done) return;
+    sc->sp2_iter += 1;
+    // once idempotent to 1e-10, two more quadratic steps reach rounding level
+    if (sc->sp2_post > 0 || fabs(sc->idem) < 1e-10) sc->sp2_post += 1;
+    if (sc->sp2_post >= 3) sc->sp2_done = 1;
+}
+
+__global__ void k_scale_identity_minus(int M, double a, double b, const double *__restrict__ Z, double *__restrict__ out) {
+    // out = a I + b Z
+    const int64_t MM = (int64_t)M * M;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < MM; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / M), j = (int)(idx % M);
+        out[idx] = (i == j ? a : 0.0) + b * Z[idx];
+    }
+}
+
+// X[:, k] = U[:, drop + k] / sqrt(w[drop + k]), N x M
+__global__ void k_canonical_x(int N, int M, int drop, const double *__restrict__ U, const double *__restrict__ w,
+                              double *__restrict__ X) {
+    const int64_t n = (int64_t)N * M;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / M), k = (int)(idx % M);
+        X[idx] = U[(int64_t)i * N + drop + k] / sqrt(w[drop + k]);
+    }
+}
+
+static unsigned grid1(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 2048) g = 2048;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Projector P (M x M) onto the n_occ lowest eigenvectors of Fp; P and P2
+// are work buffers (result in P).  Returns the number of iterations.
+static int purify(mess_scf *st, const double *Fp, hipStream_t s, int *iters) {
+    const int M = st->M;
+    const double nocc = st->basis->nocc;
+    hipLaunchKernelGGL(k_gershgorin, dim3(1), dim3(1024), 0, s, M, Fp, st->sc);
+    hipLaunchKernelGGL(k_sp2_init, dim3(grid1((int64_t)M * M)), dim3(256), 0, s, M, Fp, st->sc, st->P);
+    MESS_LAUNCH_CHECK();
+    const int chunk = 8, maxit = 200;
+    int done = 0, it = 0;
+    while (!done && it < maxit) {
+        for (int k = 0; k < chunk; ++k) {
+            MESS_TRY(gemm(s, false, false, M, M, M, 1.0, st->P, M, st->P, M, 0.0, st->P2, M));
+            hipLaunchKernelGGL(k_sp2_traces, dim3(1), dim3(1024), 0, s, M, st->P, st->P2, st->sc);
+            hipLaunchKernelGGL(k_sp2_update, dim3(grid1((int64_t)M * M)), dim3(256), 0, s, M, nocc, st->P, st->P2,
+                               st->sc);
+            hipLaunchKernelGGL(k_sp2_bookkeep, dim3(1), dim3(64), 0, s, st->sc);
+        }
+        MESS_LAUNCH_CHECK();
+        it += chunk;
+        MESS_HIP(hipMemcpyAsync(&done, &st->sc->sp2_done, sizeof(int), hipMemcpyDeviceToHost, s));
+        MESS_HIP(hipStreamSynchronize(s));
+    }
+    int n = 0;
+    MESS_HIP(hipMemcpyAsync(&n, &st->sc->sp2_iter, sizeof(int), hipMemcpyDeviceToHost, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    *iters = n;
+    return MESS_OK;
+}
+
+// D = 2 X P X^T from the projector in the orthonormal basis.
+static int density_from_projector(mess_scf *st, hipStream_t s, double *Dout) {
+    const int N = st->N, M = st->M;
+    MESS_TRY(gemm(s, false, false, N, M, M, 1.0, st->X, M, st->P, M, 0.0, st->W1, M));      // W1 = X P  (N x M)
+    MESS_TRY(gemm(s, false, true, N, N, M, 2.0, st->W1, M, st->X, M, 0.0, Dout, N));       // D = 2 W1 X^T
+    return MESS_OK;
+}
+
+// Fp = X^T F X (M x M) into P2's partner buffer W2.
+static int to_orthonormal(mess_scf *st, const double *F, double *Fp, hipStream_t s) {
+    const int N = st->N, M = st->M;
+    MESS_TRY(gemm(s, true, false, M, N, N, 1.0, st->X, M, F, N, 0.0, st->W3, N));   // W3 = X^T F (M x N)
+    MESS_TRY(gemm(s, false, false, M, M, N, 1.0, st->W3, N, st->X, M, 0.0, Fp, M));  // Fp = W3 X
+    return MESS_OK;
+}
+
+static void free_scf(mess_scf *st) {
+    if (!st) return;
+    for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
+                      st->P2, st->Fh, st->Eh, st->Bm, st->partial})
+        hipFree(p);
+    hipFree(st->sc);
+    delete st;
+}
+
+static int scf_create_impl(mess_scf *st, const double *D0) {
+    mess_basis *B = st->basis;
+    const int N = B->nbf;
+    st->N = N;
+    hipStream_t s = nullptr;
+    const size_t nn = (size_t)N * N;
+    for (double **p : {&st->S, &st->H, &st->X, &st->D, &st->F, &st->Fx, &st->Gj, &st->Gk, &st->W1, &st->W2, &st->W3,
+                       &st->P, &st->P2})
+        MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
+    const int nd = std::max(1, std::min(st->opts.diis_size, kMaxDiis));
+    MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * nn * nd));
+    MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * nn * nd));
+    MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kMaxDiis * kMaxDiis));
+    MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
+    MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
+    MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
+    // one-electron: S in S, T in W1, V in W2 -> H
+    MESS_TRY(mess_one_electron(B, st->S, st->W1, st->W2, s));
+    MESS_TRY(axpby(s, (int64_t)nn, 1.0, st->W1, 1.0, st->W2, st->H));
+    // canonical orthogonaliser from the eigenpairs of S
+    MESS_HIP(hipMemcpyAsync(st->W1, st->S, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    double *w = st->partial;  // N <= kRedBlocks? use W3 tail otherwise
+    std::vector<double> wh(N);
+    double *wdev = nullptr;
+    MESS_HIP(hipMalloc(&wdev, sizeof(double) * N));
+    double *work = nullptr;
+    MESS_HIP(hipMalloc(&work, sizeof(double) * (nn + N)));
+    int rc = jacobi_eigh(s, N, st->W1, wdev, st->W2, work);
+    if (rc == MESS_OK && hipMemcpyAsync(wh.data(), wdev, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = MESS_E_DEVICE;
+    if (rc == MESS_OK && hipStreamSynchronize(s) != hipSuccess) rc = MESS_E_DEVICE;
+    (void)w;
+    int drop = 0;
+    if (rc == MESS_OK) {
+        for (int i = 0; i < N; ++i)
+            if (!std::isfinite(wh[i])) {
+                set_error("mess_scf_create: non-finite overlap eigenvalue");
+                rc = MESS_E_NUMERIC;
+                break;
+            }
+        while (rc == MESS_OK && drop < N && wh[drop] <= 1e-7) ++drop;
+    }
+    if (rc == MESS_OK) {
+        st->M = N - drop;
+        if (st->M < B->nocc || st->M <= 0) {
+            set_error("mess_scf_create: only %d linearly independent functions for %d occupied orbitals", st->M,
+                      B->nocc);
+            rc = MESS_E_NUMERIC;
+        }
+    }
+    if (rc == MESS_OK) {
+        hipLaunchKernelGGL(k_canonical_x, dim3(grid1((int64_t)N * st->M)), dim3(256), 0, s, N, st->M, drop, st->W2,
+                           wdev, st->X);
+        if (hipGetLastError() != hipSuccess) rc = MESS_E_DEVICE;
+    }
+    hipStreamSynchronize(s);
+    hipFree(wdev);
+    hipFree(work);
+    if (rc != MESS_OK) {
+        if (rc == MESS_E_DEVICE) set_error("mess_scf_create: device error in the overlap eigensolve");
+        return rc;
+    }
+    const int M = st->M;
+    // two Newton steps X <- X (3 I - X^T S X) / 2 restore X^T S X = I to rounding
+    for (int k = 0; k < 2; ++k) {
+        MESS_TRY(gemm(s, false, false, N, M, N, 1.0, st->S, N, st->X, M, 0.0, st->W1, M));   // W1 = S X
+        MESS_TRY(gemm(s, true, false, M, M, N, 1.0, st->X, M, st->W1, M, 0.0, st->P, M));    // P = X^T S X
+        hipLaunchKernelGGL(k_scale_identity_minus, dim3(grid1((int64_t)M * M)), dim3(256), 0, s, M, 1.5, -0.5, st->P,
+                           st->P2);
+        MESS_TRY(gemm(s, false, false, N, M, M, 1.0, st->X, M, st->P2, M, 0.0, st->W1, M));  // W1 = X (1.5 - 0.5 Z)
+        MESS_HIP(hipMemcpyAsync(st->X, st->W1, sizeof(double) * N * M, hipMemcpyDeviceToDevice, s));
+    }
+    // initial density
+    if (D0) {
+        MESS_HIP(hipMemcpyAsync(st->D, D0, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    } else {
+        MESS_TRY(to_orthonormal(st, st->H, st->W2, s));
+        int it = 0;
+        MESS_TRY(purify(st, st->W2, s, &it));
+        MESS_TRY(density_from_projector(st, s, st->D));
+    }
+    MESS_HIP(hipStreamSynchronize(s));
+    return MESS_OK;
+}
+
+static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *resid, int32_t *converged,
+                         hipStream_t s) {
+    mess_basis *B = st->basis;
+    const int N = st->N, M = st->M;
+    const int64_t nn = (int64_t)N * N, mm = (int64_t)M * M;
+    // J, K half matrices
+    if (st->opts.jk_mode == MESS_JK_DIRECT)
+        MESS_TRY(jk_direct_half(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+    else
+        MESS_TRY(jk_stored(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+    hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, st->D, st->F, st->partial);
+    hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc, st->sc);
+    MESS_LAUNCH_CHECK();
+    // commutator e = X^T (F D S - S D F) X, stored at the next DIIS slot
+    const int nd = std::min(st->opts.diis_size, kMaxDiis);
+    const int slot = nd > 0 ? st->next_slot : 0;
+    double *e = nd > 0 ? st->Eh + (int64_t)slot * mm : st->P2;
+    MESS_TRY(gemm(s, false, false, N, N, N, 1.0, st->F, N, st->D, N, 0.0, st->W1, N));    // W1 = F D
+    MESS_TRY(gemm(s, false, false, N, N, N, 1.0, st->W1, N, st->S, N, 0.0, st->W2, N));   // W2 = F D S
+    hipLaunchKernelGGL(k_antisym, dim3(grid1(nn)), dim3(256), 0, s, N, st->W2, st->W1);  // W1 = W2 - W2^T
+    MESS_TRY(gemm(s, true, false, M, N, N, 1.0, st->X, M, st->W1, N, 0.0, st->W3, N));    // W3 = X^T W1
+    MESS_TRY(gemm(s, false, false, M, M, N, 1.0, st->W3, N, st->X, M, 0.0, e, M));       // e = W3 X
+    hipLaunchKernelGGL(k_maxabs, dim3(1), dim3(1024), 0, s, mm, e, st->sc);
+    MESS_LAUNCH_CHECK();
+    ScfScalars h;
+    MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(h.energy)) {
+        set_error("mess_scf_step: non-finite energy");
+        return MESS_E_NUMERIC;
+    }
+    const double de = st->iter > 0 ? h.energy - st->e_prev : 0.0;
+    const bool conv = st->iter > 0 && std::fabs(de) < st->opts.conv_tol;
+    if (energy) *energy = h.energy;
+    if (delta_e) *delta_e = de;
+    if (resid) *resid = h.resid;
+    if (converged) *converged = conv ? 1 : 0;
+    st->e_prev = h.energy;
+    st->iter += 1;
+    if (conv) return MESS_OK;  // D stays the density that gave E_k
+    // DIIS
+    const double *Fuse = st->F;
+    if (nd > 0) {
+        MESS_HIP(hipMemcpyAsync(st->Fh + (int64_t)slot * nn, st->F, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        st->hist.push_back(slot);
+        if ((int)st->hist.size() > nd) st->hist.erase(st->hist.begin());
+        st->next_slot = (slot + 1) % nd;
+        int *dslots = reinterpret_cast<int *>(st->P2);  // scratch for the slot list
+        (void)dslots;
+        int hs[kMaxDiis];
+        for (size_t i = 0; i < st->hist.size(); ++i) hs[i] = st->hist[i];
+        int *d_hs = nullptr;
+        MESS_HIP(hipMalloc(&d_hs, sizeof(int) * kMaxDiis));
+        int rc = MESS_OK;
+        if (hipMemcpyAsync(d_hs, hs, sizeof(int) * st->hist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = MESS_E_DEVICE;
+        if (rc == MESS_OK) {
+            hipLaunchKernelGGL(k_diis_dots, dim3((unsigned)st->hist.size()), dim3(256), 0, s, mm, slot, d_hs,
+                               (int)st->hist.size(), st->Eh, st->Bm);
+            if (st->hist.size() >= 2) {
+                hipLaunchKernelGGL(k_diis_solve, dim3(1), dim3(64), 0, s, (int)st->hist.size(), d_hs, st->Bm, st->sc);
+                hipLaunchKernelGGL(k_diis_combine, dim3(grid1(nn)), dim3(256), 0, s, nn, (int)st->hist.size(), d_hs,
+                                   st->Fh, st->sc, st->Fx);
+                Fuse = st->Fx;
+            }
+            if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = MESS_E_DEVICE;
+        }
+        hipFree(d_hs);
+        if (rc != MESS_OK) {
+            set_error("mess_scf_step: DIIS kernels failed");
+            return rc;
+        }
+    }
+    MESS_TRY(to_orthonormal(st, Fuse, st->W2, s));
+    int it = 0;
+    MESS_TRY(purify(st, st->W2, s, &it));
+    st->sp2_iters_last = it;
+    MESS_TRY(density_from_projector(st, s, st->D));
+    (void)M;
+    return MESS_OK;
+}
+
+}  // namespace mess
+
+using namespace mess;
+
+extern "C" {
+
+int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const double *D0, mess_scf **out) {
+    if (!basis || !opts || !out) {
+        set_error("mess_scf_create: NULL basis, options or output");
+        return MESS_E_ARG;
+    }
+    *out = nullptr;
+    if (basis->nelec % 2) {
+        set_error("mess_scf_create: %d electrons; only closed-shell (even) systems are supported", basis->nelec);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (opts->jk_mode != MESS_JK_DIRECT && opts->jk_mode != MESS_JK_STORED) {
+        set_error("mess_scf_create: unknown J/K mode %d", opts->jk_mode);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (opts->prec != MESS_FP64 && opts->prec != MESS_FP32) {
+        set_error("mess_scf_create: unknown precision %d", opts->prec);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (opts->xc != MESS_XC_HF) {
+        set_error("mess_scf_create: exchange form %d is not built", opts->xc);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (opts->diis_size < 0 || opts->diis_size > kMaxDiis || !(opts->conv_tol >= 0.0)) {
+        set_error("mess_scf_create: diis_size must be 0..%d and conv_tol >= 0", kMaxDiis);
+        return MESS_E_ARG;
+    }
+    auto *st = new mess_scf();
+    st->basis = const_cast<mess_basis *>(basis);
+    st->opts = *opts;
+    int rc = scf_create_impl(st, D0);
+    if (rc != MESS_OK) {
+        free_scf(st);
+        return rc;
+    }
+    *out = st;
+    return MESS_OK;
+}
+
+int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid, int32_t *converged,
+                  mess_stream stream) {
+    if (!scf) {
+        set_error("mess_scf_step: NULL handle");
+        return MESS_E_ARG;
+    }
+    return scf_step_impl(scf, energy, delta_e, resid, converged, static_cast<hipStream_t>(stream));
+}
+
+int mess_scf_density(const mess_scf *scf, double *D, mess_stream stream) {
+    if (!scf || !D) {
+        set_error("mess_scf_density: NULL argument");
+        return MESS_E_ARG;
+    }
+    MESS_HIP(hipMemcpyAsync(D, scf->D, sizeof(double) * scf->N * scf->N, hipMemcpyDeviceToDevice,
+                            static_cast<hipStream_t>(stream)));
+    return MESS_OK;
+}
+
+int mess_scf_fock(const mess_scf *scf, double *F, mess_stream stream) {
+    if (!scf || !F) {
+        set_error("mess_scf_fock: NULL argument");
+        return MESS_E_ARG;
+    }
+    MESS_HIP(hipMemcpyAsync(F, scf->F, sizeof(double) * scf->N * scf->N, hipMemcpyDeviceToDevice,
+                            static_cast<hipStream_t>(stream)));
+    return MESS_OK;
+}
+
+void mess_scf_destroy(mess_scf *scf) { free_scf(scf); }
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""Thin ctypes binding of libmess_hip.so (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name declared
+in include/mess.h.  Matrices are torch tensors on a HIP device (float64,
+contiguous, row-major); atom and shell arrays are host numpy arrays.  There
+is no fallback: if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmess_hip.so")
+
+MESS_OK, MESS_E_ARG, MESS_E_UNSUPPORTED, MESS_E_NOMEM, MESS_E_DEVICE, MESS_E_NUMERIC, MESS_E_SIZE = range(7)
+MESS_FP64, MESS_FP32 = 0, 1
+MESS_ERI_DENSE, MESS_ERI_BLOCKS = 0, 1
+MESS_JK_DIRECT, MESS_JK_STORED = 0, 1
+MESS_XC_HF, MESS_XC_LDA_X = 0, 1
+
+EXPORTED = [
+    "mess_basis_create", "mess_basis_destroy", "mess_basis_info", "mess_one_electron",
+    "mess_eri", "mess_jk", "mess_scf_create", "mess_scf_step", "mess_scf_density",
+    "mess_scf_fock", "mess_scf_destroy", "mess_last_error",
+]
+
+
+class MessError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__(f"{where} -> status {code}: {msg}")
+        self.code = code
+
+
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("schwarz_tol", ctypes.c_double), ("conv_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("jk_mode", ctypes.c_int32),
+                ("xc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built; run `python -m paper_2406_03121_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        L.mess_basis_create.argtypes = [i32, vp, vp, i32, vp, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]
+        L.mess_basis_destroy.argtypes = [vp]
+        L.mess_basis_destroy.restype = None
+        L.mess_basis_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(f64)]
+        L.mess_one_electron.argtypes = [vp, vp, vp, vp, vp]
+        L.mess_eri.argtypes = [vp, i32, i32, f64, vp, sz, vp]
+        L.mess_jk.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp]
+        if hasattr(L, "mess_scf_create"):
+            L.mess_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, ctypes.POINTER(vp)]
+            L.mess_scf_step.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                        ctypes.POINTER(i32), vp]
+            L.mess_scf_density.argtypes = [vp, vp, vp]
+            L.mess_scf_fock.argtypes = [vp, vp, vp]
+            L.mess_scf_destroy.argtypes = [vp]
+            L.mess_scf_destroy.restype = None
+        L.mess_last_error.argtypes = []
+        L.mess_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def mess_last_error() -> str:
+    return lib().mess_last_error().decode()
+
+
+def _check(rc, where):
+    if rc != MESS_OK:
+        raise MessError(rc, where, mess_last_error())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Basis:
+    """Owning wrapper of a mess_basis handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        nbf, nocc, enuc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().mess_basis_info(handle, ctypes.byref(nbf), ctypes.byref(nocc), ctypes.byref(enuc)),
+               "mess_basis_info")
+        self.nbf, self.n_occ, self.e_nuc = nbf.value, nocc.value, enuc.value
+
+    def close(self):
+        if self.handle:
+            lib().mess_basis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mess_basis_create(Z, xyz, shell_atom, shell_l, shell_nprim, exps, coefs, charge=0) -> Basis:
+    Z, pZ = _host(Z, np.int32)
+    xyz, pX = _host(xyz, np.float64)
+    sa, pA = _host(shell_atom, np.int32)
+    sl, pL = _host(shell_l, np.int32)
+    sn, pN = _host(shell_nprim, np.int32)
+    ex, pE = _host(exps, np.float64)
+    co, pC = _host(coefs, np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().mess_basis_create(len(Z), pZ, pX, len(sl), pA, pL, pN, pE, pC, int(charge), ctypes.byref(h)),
+           "mess_basis_create")
+    return Basis(h)
+
+
+def basis_from_molecule(mol) -> Basis:
+    """Convenience: a mess_inputs.Molecule -> Basis."""
+    return mess_basis_create(mol.Z, mol.xyz, mol.shell_atom, mol.shell_l, mol.shell_nprim, mol.exps,
+                             mol.coefs, mol.charge)
+
+
+def mess_one_electron(basis: Basis, S=None, T=None, V=None, stream=None):
+    _check(lib().mess_one_electron(basis.handle, _ptr(S), _ptr(T), _ptr(V), _stream(stream)),
+           "mess_one_electron")
+
+
+def mess_eri(basis: Basis, out, layout=MESS_ERI_DENSE, prec=MESS_FP64, schwarz_tol=0.0, stream=None):
+    nbytes = out.numel() * out.element_size()
+    _check(lib().mess_eri(basis.handle, int(layout), int(prec), float(schwarz_tol), _ptr(out), nbytes,
+                          _stream(stream)), "mess_eri")
+
+
+def mess_jk(basis: Basis, D, J=None, K=None, mode=MESS_JK_DIRECT, prec=MESS_FP64, schwarz_tol=0.0,
+            stream=None):
+    _check(lib().mess_jk(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(mode), int(prec), float(schwarz_tol),
+                         _stream(stream)), "mess_jk")
+
+
+class Scf:
+    """Owning wrapper of a mess_scf handle."""
+
+    def __init__(self, handle, basis):
+        self.handle, self.basis = handle, basis
+
+    def close(self):
+        if self.handle:
+            lib().mess_scf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mess_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
+                    prec=MESS_FP64, jk_mode=MESS_JK_DIRECT, xc=MESS_XC_HF, D0=None) -> Scf:
+    opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), int(prec),
+                   int(jk_mode), int(xc), 0)
+    h = ctypes.c_void_p()
+    _check(lib().mess_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), ctypes.byref(h)), "mess_scf_create")
+    return Scf(h, basis)
+
+
+def mess_scf_step(scf: Scf, stream=None):
+    """Returns (energy, delta_e, resid, converged)."""
+    e, de, r, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(lib().mess_scf_step(scf.handle, ctypes.byref(e), ctypes.byref(de), ctypes.byref(r), ctypes.byref(c),
+                               _stream(stream)), "mess_scf_step")
+    return e.value, de.value, r.value, bool(c.value)
+
+
+def mess_scf_density(scf: Scf, D, stream=None):
+    _check(lib().mess_scf_density(scf.handle, _ptr(D), _stream(stream)), "mess_scf_density")
+
+
+def mess_scf_fock(scf: Scf, F, stream=None):
+    _check(lib().mess_scf_fock(scf.handle, _ptr(F), _stream(stream)), "mess_scf_fock")
