@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the Hartree-Fock hot path on one MI355X.
+
+One step = one complete closed-shell SCF of the 60-atom water-cluster
+workload (300 Cartesian s/p/d functions, Schwarz threshold 1e-10): basis
+creation (normalisation, primitive pairs, Schwarz factors), unique
+shell-quartet work lists, one-electron integrals, overlap eigensolve and
+orthogonaliser, core-Hamiltonian guess, then Fock builds with direct J/K
+(ERI class kernels), Pulay DIIS and purification until |dE| < 1e-8 Ha.
+
+Prints one JSON line (stdout).  value = shell quartets evaluated per second
+over the timed steps (all Fock builds); the roofline block is for the
+dominant ERI class kernel, from HIP events recorded on the launch stream
+around every class launch inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop/FMA x 2.4 GHz
+CLASS_NAMES = {}
+_PC = ["ss", "ps", "pp", "ds", "dp", "dd"]
+for _cb in range(6):
+    for _ck in range(_cb + 1):
+        CLASS_NAMES[_cb * (_cb + 1) // 2 + _ck] = f"({_PC[_cb]}|{_PC[_ck]})"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name, seed):
+    from mess_inputs import generators as G
+    if name == "water60_spd":
+        return G.water_cluster(seed)
+    if name == "hco6_sp":
+        return G.random_small_molecule(seed)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def scf_once(mess, mol, tau, conv_tol, max_iter=100, verbose=True):
+    B = mess.basis_from_molecule(mol)
+    st = mess.mess_scf_create(B, schwarz_tol=tau, conv_tol=conv_tol, diis_size=8)
+    e, it, conv = 0.0, 0, False
+    for it in range(1, max_iter + 1):
+        e, de, resid, conv = mess.mess_scf_step(st)
+        if verbose:
+            log(f"  iteration {it}: E={e:.10f} dE={de:.2e} resid={resid:.2e}")
+        if conv:
+            break
+    st.close()
+    B.close()
+    return e, it, conv
+
+
+def cpu_baseline(mol, target_seconds):
+    """Oracle ERI throughput on a uniform random sample of unique shell quartets."""
+    from oracle import core
+    ns = mol.n_shells
+    pairs = [(a, b) for a in range(ns) for b in range(a + 1)]
+    rng = np.random.Generator(np.random.PCG64(12345))
+
+    def sample(n):
+        out = []
+        while len(out) < n:
+            i, j = rng.integers(0, len(pairs), 2)
+            if j > i:
+                i, j = j, i
+            out.append(pairs[i] + pairs[j])
+        return np.array(out, dtype=np.int32)
+
+    core.lib()
+    n = 200
+    t = time.perf_counter()
+    core.eri_quartet_list(mol, sample(n))
+    dt = time.perf_counter() - t
+    n2 = int(max(200, min(200000, n * target_seconds / max(dt, 1e-3))))
+    q = sample(n2)
+    t = time.perf_counter()
+    core.eri_quartet_list(mol, q)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n2 / dt, "unit": "shell quartets/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n2} unique shell quartets of {mol.name} drawn uniformly (unscreened), "
+                      f"FP64 McMurchie-Davidson oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water60_spd")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tau", type=float, default=1e-10)
+    ap.add_argument("--conv", type=float, default=1e-8)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
+              "shell-quartet lists is a design note, not a built path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_03121_amd import mess
+    torch.cuda.init()
+    mol = make_workload(a.workload, a.seed)
+    log(f"workload {mol.name}: {mol.n_atoms} atoms, {mol.n_shells} shells, {mol.n_bf} functions")
+    for w in range(a.warmup):
+        e, it, conv = scf_once(mess, mol, a.tau, a.conv)
+        log(f"warmup {w}: E={e:.10f} iterations={it} converged={conv}")
+
+    torch.cuda.synchronize()
+    mess.mess_prof_enable(True)
+    t0 = time.perf_counter()
+    results = []
+    for k in range(a.steps):
+        results.append(scf_once(mess, mol, a.tau, a.conv))
+        log(f"step {k}: E={results[-1][0]:.10f} iterations={results[-1][1]}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    tot = mess.mess_prof_read(-1)
+    per = {}
+    for c in range(21):
+        r = mess.mess_prof_read(c)
+        if r["launches"]:
+            per[c] = r
+    mess.mess_prof_enable(False)
+
+    dom = max(per, key=lambda c: per[c]["ms"])
+    d = per[dom]
+    achieved = d["alg_flops"] / (d["ms"] * 1e-3) / 1e12
+    eri_tf = tot["alg_flops"] / (tot["ms"] * 1e-3) / 1e12
+    value = tot["quartets"] / elapsed
+    energies = [r[0] for r in results]
+    line = {
+        "metric": "shell-quartet ERIs/s + J/K GB/s; SCF molecules/s vs plain FP64 at |ΔE|<1e-6 Ha",
+        "value": value,
+        "unit": "shell quartets/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "seed": a.seed, "n_atoms": mol.n_atoms, "n_bf": mol.n_bf,
+                   "schwarz_tol": a.tau, "conv_tol": a.conv, "jk": "direct", "diis": 8},
+        "molecules_per_s": a.steps / elapsed,
+        "scf_iterations": results[-1][1],
+        "energy_hartree": energies[-1],
+        "energy_spread_hartree": float(np.max(energies) - np.min(energies)),
+        "jk_gbps": None,
+        "primitive_quartets_per_s": tot["prim_quartets"] / elapsed,
+        "eri_kernels": {"ms": tot["ms"], "alg_tflops": eri_tf, "frac_of_fp64_peak": eri_tf / FP64_VALU_PEAK_TFLOPS,
+                        "share_of_step": tot["ms"] * 1e-3 / elapsed},
+        "per_class_ms": {CLASS_NAMES[c]: round(per[c]["ms"], 3) for c in sorted(per)},
+        "roofline": {"kernel": f"ERI/JK class {CLASS_NAMES[dom]}", "bound": "alu",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle on a quartet sample")
+        line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,28 @@ int mess_scf_fock(const mess_scf *scf, double *F, mess_stream stream);
 /* NULL is a no-op. */
 void mess_scf_destroy(mess_scf *scf);
 
+/* ---- Instrumentation (not part of the method; used by benchmarks). ----
+ * Class index cls = cb (cb + 1) / 2 + ck for bra pair class cb >= ket pair
+ * class ck, pair classes ss, ps, pp, ds, dp, dd = 0..5.
+ *
+ * mess_work_stats: for the unique, Schwarz-screened shell-quartet list of
+ * one class: number of shell quartets, of primitive quartets, and the
+ * algorithmic FP64 operation count of one direct J/K pass over it (an FMA
+ * counts 2; Boys function, vertical and horizontal recursion, contraction
+ * and J/K digestion).  Host outputs, any may be NULL.
+ *
+ * mess_prof_enable(1) starts recording a pair of HIP events on the launch
+ * stream around every class launch of mess_jk / mess_scf_step (0 stops;
+ * both discard earlier records).  mess_prof_read sums, for one class (or
+ * all with cls = -1), launches, elapsed milliseconds between the events,
+ * algorithmic operations, shell and primitive quartets.  Synchronises on
+ * the recorded events. */
+int mess_work_stats(const mess_basis *basis, double schwarz_tol, int32_t cls, int64_t *quartets,
+                    int64_t *prim_quartets, double *alg_flops_jk);
+int mess_prof_enable(int32_t on);
+int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops, int64_t *quartets,
+                   int64_t *prim_quartets);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *mess_last_error(void);
 

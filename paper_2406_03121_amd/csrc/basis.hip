@@ -263,14 +263,28 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                                B->pair_class_off[cb], cl.nbra, B->pair_class_off[ck], nket, cb == ck ? 1 : 0,
                                tau, d_counts);
             hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, d_counts, cl.nbra, cl.d_rowstart);
+            cl.h_rowstart.resize(cl.nbra + 1);
             if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(&cl.total, cl.d_rowstart + cl.nbra, sizeof(int64_t), hipMemcpyDeviceToHost,
-                               s) != hipSuccess ||
+                hipMemcpyAsync(cl.h_rowstart.data(), cl.d_rowstart, sizeof(int64_t) * (cl.nbra + 1),
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 hipFree(cl.d_rowstart);
                 set_error("work-list construction failed on the device");
                 rc = MESS_E_DEVICE;
                 break;
+            }
+            cl.total = cl.h_rowstart[cl.nbra];
+            {
+                // primitive quartets: sum_i npp(bra_i) * sum_{j < count_i} npp(ket_j)
+                const int boff = B->pair_class_off[cb], koff = B->pair_class_off[ck];
+                std::vector<int64_t> kpre(nket + 1, 0);
+                for (int j = 0; j < nket; ++j) kpre[j + 1] = kpre[j] + B->pairs_host[koff + j].npp;
+                int64_t tot = 0;
+                for (int i = 0; i < cl.nbra; ++i) {
+                    const int64_t cnt = cl.h_rowstart[i + 1] - cl.h_rowstart[i];
+                    tot += (int64_t)B->pairs_host[boff + i].npp * kpre[cnt];
+                }
+                cl.prim_quartets = tot;
             }
             W->classes.push_back(cl);
         }
@@ -515,6 +529,8 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     MESS_HIPC(hipGetLastError());
     B->pairQ_host.resize(np_);
     MESS_HIPC(hipMemcpy(B->pairQ_host.data(), B->d_pairQ, sizeof(double) * np_, hipMemcpyDeviceToHost));
+    B->pairs_host.resize(np_);
+    MESS_HIPC(hipMemcpy(B->pairs_host.data(), B->d_pairs, sizeof(PairInfo) * np_, hipMemcpyDeviceToHost));
     for (int i = 0; i < np_; ++i)
         if (!std::isfinite(B->pairQ_host[i])) {
             set_error("mess_basis_create: non-finite Schwarz factor (pair %d)", i);
@@ -567,6 +583,29 @@ int mess_basis_create(int32_t n_atoms, const int32_t *Z, const double *xyz_bohr,
 }
 
 void mess_basis_destroy(mess_basis *basis) { free_basis(basis); }
+
+int mess_work_stats(const mess_basis *basis, double schwarz_tol, int32_t cls, int64_t *quartets,
+                    int64_t *prim_quartets, double *alg_flops_jk) {
+    if (!basis || cls < 0 || cls > 20) {
+        set_error("mess_work_stats: NULL basis or class index outside 0..20");
+        return MESS_E_ARG;
+    }
+    WorkLists *W = nullptr;
+    MESS_TRY(get_work_lists(const_cast<mess_basis *>(basis), schwarz_tol, nullptr, &W));
+    for (const ClassList &cl : W->classes)
+        if (class_index(cl.cb, cl.ck) == cls) {
+            double fp = 0.0, fq = 0.0;
+            class_flops(cl.cb, cl.ck, &fp, &fq);
+            if (quartets) *quartets = cl.total;
+            if (prim_quartets) *prim_quartets = cl.prim_quartets;
+            if (alg_flops_jk) *alg_flops_jk = fp * (double)cl.prim_quartets + fq * (double)cl.total;
+            return MESS_OK;
+        }
+    if (quartets) *quartets = 0;
+    if (prim_quartets) *prim_quartets = 0;
+    if (alg_flops_jk) *alg_flops_jk = 0.0;
+    return MESS_OK;
+}
 
 int mess_basis_info(const mess_basis *B, int32_t *nbf, int32_t *n_occ, double *e_nuc) {
     if (!B) {

@@ -77,7 +77,14 @@ struct Builder {
     }
 };
 
-std::unique_ptr<CoopProgram> build_program(int cb, int ck) {
+struct CoopTables {
+    std::vector<int4> vops, hops;
+    std::vector<int> vlev, hlev;
+    std::vector<unsigned short> accsrc, outslot;
+    std::vector<double> outscale;
+};
+
+std::unique_ptr<CoopProgram> build_tables(int cb, int ck, CoopTables &tables) {
     auto P = std::make_unique<CoopProgram>();
     P->cb = cb; P->ck = ck;
     const int LA = pair_class_la(cb), LB = pair_class_lb(cb), LC = pair_class_la(ck), LD = pair_class_lb(ck);
@@ -261,6 +268,20 @@ std::unique_ptr<CoopProgram> build_program(int cb, int ck) {
     // LDS: accumulators [0, nacc), then one region shared by the VRR slots
     // (during the primitive loop) and the HRR slots >= nacc (after it).
     P->lds_bytes = sizeof(double) * (size_t)(P->nacc + std::max(P->nV, P->nH - P->nacc) + kNCoef + kNHCoef);
+    tables.vops = std::move(vops);
+    tables.hops = std::move(hops);
+    tables.vlev = std::move(vlev);
+    tables.hlev = std::move(hlev);
+    tables.accsrc = std::move(accsrc);
+    tables.outslot = std::move(outslot);
+    tables.outscale = std::move(outscale);
+    return P;
+}
+
+std::unique_ptr<CoopProgram> build_program(int cb, int ck) {
+    CoopTables T;
+    auto P = build_tables(cb, ck, T);
+    if (!P) return nullptr;
     // upload
     auto up = [](auto **dptr, const auto &vec) -> bool {
         using T = typename std::remove_reference<decltype(vec)>::type::value_type;
@@ -270,16 +291,53 @@ std::unique_ptr<CoopProgram> build_program(int cb, int ck) {
             return false;
         return true;
     };
-    if (!up(&P->d_vops, vops) || !up(&P->d_vlev, vlev) || !up(&P->d_accsrc, accsrc) || !up(&P->d_hops, hops) ||
-        !up(&P->d_hlev, hlev) || !up(&P->d_outslot, outslot) || !up(&P->d_outscale, outscale))
+    if (!up(&P->d_vops, T.vops) || !up(&P->d_vlev, T.vlev) || !up(&P->d_accsrc, T.accsrc) ||
+        !up(&P->d_hops, T.hops) || !up(&P->d_hlev, T.hlev) || !up(&P->d_outslot, T.outslot) ||
+        !up(&P->d_outscale, T.outscale))
         return nullptr;
     return P;
 }
 
 std::mutex g_prog_mutex;
+std::mutex g_flop_mutex;
+std::map<std::pair<int, int>, std::pair<double, double>> g_flops;
 std::map<std::pair<int, int>, std::unique_ptr<CoopProgram>> g_programs;
 
 }  // namespace
+
+// Algorithmic operation count of the recursion (FMA = 2): per primitive
+// quartet the setup of Boys arguments and prefactors with the Taylor
+// evaluation and downward recurrence of the Boys function (80 + 4L), each
+// vertical step (3 for the two leading terms, 4 for the f_i/2p term, 2 for
+// the e_j/2(p+q) term) and one add per contracted intermediate; per shell
+// quartet each horizontal step (2) and the J/K digestion (six families of
+// one FMA per integral: 12 per integral).
+void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk) {
+    std::lock_guard<std::mutex> lk(g_flop_mutex);
+    auto key = std::make_pair(cb, ck);
+    auto it = g_flops.find(key);
+    if (it == g_flops.end()) {
+        CoopTables T;
+        double fp = 0.0, fq = 0.0;
+        std::unique_ptr<CoopProgram> P;
+        try {
+            P = build_tables(cb, ck, T);
+        } catch (...) {
+            P.reset();
+        }
+        if (P) {
+            fp = 80.0 + 4.0 * P->L + P->nacc;
+            for (const int4 &op : T.vops) {
+                const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
+                fp += 3.0 + (k3 ? 4.0 : 0.0) + (k5 ? 2.0 : 0.0);
+            }
+            fq = 2.0 * (double)T.hops.size() + 12.0 * P->nout;
+        }
+        it = g_flops.emplace(key, std::make_pair(fp, fq)).first;
+    }
+    *per_prim = it->second.first;
+    *per_quartet_jk = it->second.second;
+}
 
 // Classes evaluated by the cooperative kernel (the per-lane unrolled form
 // of these needs far more than the 512 registers a lane can hold).

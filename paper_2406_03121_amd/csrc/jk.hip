@@ -46,13 +46,21 @@ int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int p
     const int64_t NN = (int64_t)B->nbf * B->nbf;
     if (Gj) MESS_TRY(zero_async(Gj, NN, s));
     if (Gk) MESS_TRY(zero_async(Gk, NN, s));
+    const bool prof = prof_on();
     for (const ClassList &cl : W->classes) {
         if (cl.total == 0) continue;
         ClassLaunch L;
         fill_class_launch(B, cl, s, L);
+        if (prof) {
+            double fp = 0.0, fq = 0.0;
+            class_flops(cl.cb, cl.ck, &fp, &fq);
+            prof_record(s, class_index(cl.cb, cl.ck), true, cl.total, cl.prim_quartets,
+                        fp * (double)cl.prim_quartets + fq * (double)cl.total);
+        }
         MESS_TRY(dispatch_class(cl.cb, cl.ck, [&](auto CB, auto CK) {
             return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(L, D, Gj, Gk, prec);
         }));
+        if (prof) prof_record(s, 0, false, 0, 0, 0.0);
     }
     return MESS_OK;
 }

@@ -156,9 +156,23 @@ inline int pair_class_of(int la, int lb) {
 struct ClassList {
     int cb, ck;
     int nbra;
-    int64_t total = 0;
-    int64_t *d_rowstart = nullptr;  // nbra + 1
+    int64_t total = 0;               // shell quartets
+    int64_t prim_quartets = 0;       // sum over quartets of (bra prim pairs) x (ket prim pairs)
+    int64_t *d_rowstart = nullptr;   // nbra + 1
+    std::vector<int64_t> h_rowstart;  // host copy
 };
+
+// Index 0..20 of the class (cb >= ck).
+inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
+
+// Algorithmic FP64 operation counts of the recursion for one class (an FMA
+// counts 2): per primitive quartet (Boys, vertical recursion, contraction)
+// and per shell quartet (horizontal recursion + J/K digestion).
+void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk);
+
+// Profiling of class launches (HIP events on the launch stream).
+bool prof_on();
+void prof_record(hipStream_t s, int cls, bool begin, int64_t quartets, int64_t prims, double flops);
 
 struct WorkLists {
     double tau = -1.0;
@@ -192,6 +206,7 @@ struct mess_basis {
     mess::PrimPairF *d_ppf = nullptr;      // FP32 copy
     int npp = 0;
     std::vector<double> pairQ_host;        // for diagnostics
+    std::vector<mess::PairInfo> pairs_host;  // sorted pairs (host copy)
 
     std::map<double, mess::WorkLists *> lists;  // keyed by tau
     std::map<std::pair<int, double>, mess::StoredEri *> stored;  // (prec, tau)

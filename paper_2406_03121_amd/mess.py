@@ -25,6 +25,7 @@ EXPORTED = [
     "mess_basis_create", "mess_basis_destroy", "mess_basis_info", "mess_one_electron",
     "mess_eri", "mess_jk", "mess_scf_create", "mess_scf_step", "mess_scf_density",
     "mess_scf_fock", "mess_scf_destroy", "mess_last_error",
+    "mess_work_stats", "mess_prof_enable", "mess_prof_read",
 ]
 
 
@@ -67,6 +68,11 @@ def lib():
             L.mess_scf_fock.argtypes = [vp, vp, vp]
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
+        i64 = ctypes.c_int64
+        L.mess_work_stats.argtypes = [vp, f64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(f64)]
+        L.mess_prof_enable.argtypes = [i32]
+        L.mess_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                     ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mess_last_error.argtypes = []
         L.mess_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -203,3 +209,29 @@ def mess_scf_density(scf: Scf, D, stream=None):
 
 def mess_scf_fock(scf: Scf, F, stream=None):
     _check(lib().mess_scf_fock(scf.handle, _ptr(F), _stream(stream)), "mess_scf_fock")
+
+
+def class_index(cb, ck):
+    return cb * (cb + 1) // 2 + ck
+
+
+def mess_work_stats(basis: Basis, schwarz_tol, cls):
+    """(shell quartets, primitive quartets, algorithmic FP64 ops of one J/K pass) of class cls."""
+    q, p, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().mess_work_stats(basis.handle, float(schwarz_tol), int(cls), ctypes.byref(q), ctypes.byref(p),
+                                 ctypes.byref(f)), "mess_work_stats")
+    return q.value, p.value, f.value
+
+
+def mess_prof_enable(on=True):
+    _check(lib().mess_prof_enable(1 if on else 0), "mess_prof_enable")
+
+
+def mess_prof_read(cls=-1):
+    """dict(launches, ms, alg_flops, quartets, prim_quartets) for class cls (-1: all)."""
+    n, q, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    ms, f = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mess_prof_read(int(cls), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(f), ctypes.byref(q),
+                                ctypes.byref(p)), "mess_prof_read")
+    return {"launches": n.value, "ms": ms.value, "alg_flops": f.value, "quartets": q.value,
+            "prim_quartets": p.value}
