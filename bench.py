@@ -167,7 +167,10 @@ def main():
         "primitive_quartets_per_s": tot["prim_quartets"] / elapsed,
         "eri_kernels": {"ms": tot["ms"], "alg_tflops": eri_tf, "frac_of_fp64_peak": eri_tf / FP64_VALU_PEAK_TFLOPS,
                         "share_of_step": tot["ms"] * 1e-3 / elapsed},
-        "per_class_ms": {CLASS_NAMES[c]: round(per[c]["ms"], 3) for c in sorted(per)},
+        "per_class": {CLASS_NAMES[c]: {"ms": round(per[c]["ms"], 3), "quartets": per[c]["quartets"],
+                                       "prim_quartets": per[c]["prim_quartets"],
+                                       "tflops": round(per[c]["alg_flops"] / (per[c]["ms"] * 1e-3) / 1e12, 3)}
+                      for c in sorted(per)},
         "roofline": {"kernel": f"ERI/JK class {CLASS_NAMES[dom]}", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None},

@@ -46,7 +46,6 @@ struct CoopProgram {
     int *d_hlev = nullptr;
     unsigned short *d_outslot = nullptr;  // H slot of output element
     double *d_outscale = nullptr;
-    size_t lds_bytes = 0;
 };
 
 namespace {
@@ -267,7 +266,6 @@ std::unique_ptr<CoopProgram> build_tables(int cb, int ck, CoopTables &tables) {
     }
     // LDS: accumulators [0, nacc), then one region shared by the VRR slots
     // (during the primitive loop) and the HRR slots >= nacc (after it).
-    P->lds_bytes = sizeof(double) * (size_t)(P->nacc + std::max(P->nV, P->nH - P->nacc) + kNCoef + kNHCoef);
     tables.vops = std::move(vops);
     tables.hops = std::move(hops);
     tables.vlev = std::move(vlev);
@@ -411,66 +409,14 @@ __device__ __forceinline__ double run_op(const int4 op, const double *__restrict
     return v;
 }
 
+// Horizontal recursion of the accumulated [e0|f0] (in H[0, nacc)) and the
+// per-mode output of one quartet, shared by the wave.
 template <int MODE>
-__global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
-                                             int ket_off, int nbra, int same_class,
-                                             const int64_t *__restrict__ rowstart, int64_t total,
-                                             const PrimPair *__restrict__ pp, const double *__restrict__ tab,
-                                             const double *__restrict__ D, int N, double *__restrict__ out0,
-                                             double *__restrict__ out1) {
-    extern __shared__ double lds[];
-    double *H = lds;                 // HRR slots; [0, nacc) are the accumulators
-    double *V = lds + A.nacc;        // VRR slots, aliasing HRR slots >= nacc
-    double *c = lds + A.nacc + max(A.nV, A.nH - A.nacc);  // kNCoef
-    double *hc = c + kNCoef;                               // kNHCoef
-    const int lane = threadIdx.x;
-    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-        if (lane == 0) V[0] = 0.0;
-        int i, j;
-        if (MODE == kModeSchwarz) {
-            i = j = (int)q;
-        } else {
-            i = find_row(rowstart, nbra, q);
-            j = (int)(q - rowstart[i]);
-        }
-        const PairInfo bra = pairs[bra_off + i];
-        const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
-        const double ACx = bra.Ax - ket.Ax, ACy = bra.Ay - ket.Ay, ACz = bra.Az - ket.Az;
-        for (int s = lane; s < A.nacc; s += 64) H[s] = 0.0;
-        for (int ib = 0; ib < bra.npp; ++ib) {
-            const PrimPair P = pp[bra.pp0 + ib];
-            for (int ik = 0; ik < ket.npp; ++ik) {
-                const PrimPair Q = pp[ket.pp0 + ik];
-                const double p = P.p, qq = Q.p, pq = p + qq, rpq = 1.0 / pq, rho = p * qq * rpq;
-                const double PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
-                const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-                __syncthreads();  // previous primitive quartet fully consumed
-                if (lane <= A.L) {
-                    const double pref = 34.986836655249725 / (p * qq * sqrt(pq)) * P.K * Q.K;
-                    V[1 + lane] = pref * coop_boys(lane, T, tab);
-                }
-                if (lane == 32) {
-                    c[kC0] = 0.0;
-                    c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
-                    c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
-                    c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
-                    c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
-                    c[kO2P] = 0.5 / p; c[kO2PR] = 0.5 / p * rho / p;
-                    c[kO2Q] = 0.5 / qq; c[kO2QR] = 0.5 / qq * rho / qq;
-                    c[kO2PQ] = 0.5 * rpq;
-                }
-                __syncthreads();
-                for (int lv = 0; lv < A.nvlev; ++lv) {
-                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
-                    for (int o = b0 + lane; o < b1; o += 64) {
-                        const int4 op = A.vops[o];
-                        V[op.x & 0xffff] = run_op(op, V, c);
-                    }
-                    __syncthreads();
-                }
-                for (int s = lane; s < A.nacc; s += 64) H[s] += V[A.accsrc[s]];
-            }
-        }
+__device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restrict__ H, double *__restrict__ hc,
+                                            const int lane, const PairInfo &bra, const PairInfo &ket, const int i,
+                                            const int j, const int bra_off, const int same_class,
+                                            const double *__restrict__ D, const int N, double *__restrict__ out0,
+                                            double *__restrict__ out1) {
         if (lane == 0) {
             hc[kH0] = 0.0; hc[kH1] = 1.0;
             hc[kHAB + 0] = bra.ABx; hc[kHAB + 1] = bra.ABy; hc[kHAB + 2] = bra.ABz;
@@ -578,8 +524,199 @@ __global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restr
                 }
             }
         }
+}
+
+template <int MODE, int G>
+__global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
+                                             int ket_off, int nbra, int same_class,
+                                             const int64_t *__restrict__ rowstart, int64_t total,
+                                             const PrimPair *__restrict__ pp, const double *__restrict__ tab,
+                                             const double *__restrict__ D, int N, double *__restrict__ out0,
+                                             double *__restrict__ out1) {
+    // G primitive quartets of the same shell quartet are in flight at once,
+    // each with its own VRR slots and coefficient set.
+    extern __shared__ double lds[];
+    double *H = lds;                 // HRR slots; [0, nacc) are the accumulators
+    double *V0 = lds + A.nacc;       // G x nV VRR slots, aliasing HRR slots >= nacc
+    double *c0 = lds + A.nacc + max(G * A.nV, A.nH - A.nacc);  // G x kNCoef
+    double *hc = c0 + G * kNCoef;                              // kNHCoef
+    const int lane = threadIdx.x;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        if (lane < G) V0[lane * A.nV] = 0.0;
+        int i, j;
+        if (MODE == kModeSchwarz) {
+            i = j = (int)q;
+        } else {
+            i = find_row(rowstart, nbra, q);
+            j = (int)(q - rowstart[i]);
+        }
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
+        const double ACx = bra.Ax - ket.Ax, ACy = bra.Ay - ket.Ay, ACz = bra.Az - ket.Az;
+        for (int s = lane; s < A.nacc; s += 64) H[s] = 0.0;
+        const int nprim = bra.npp * ket.npp;
+        for (int base = 0; base < nprim; base += G) {
+            __syncthreads();  // previous primitive quartets fully consumed
+            // set-up: Boys values (lanes g*(L+1) .. ) and coefficients (lanes 48 + g)
+            {
+                const int g = lane / (A.L + 1), m = lane % (A.L + 1);
+                const bool boys_lane = g < G;
+                const int gc = lane - 48;
+                const bool coef_lane = gc >= 0 && gc < G;
+                if (boys_lane || coef_lane) {
+                    const int gg = boys_lane ? g : gc;
+                    const int pi = base + gg;
+                    const bool live = pi < nprim;
+                    const PrimPair P = pp[bra.pp0 + (live ? pi / ket.npp : 0)];
+                    const PrimPair Q = pp[ket.pp0 + (live ? pi % ket.npp : 0)];
+                    const double p = P.p, qq = Q.p, pq = p + qq, rpq = 1.0 / pq, rho = p * qq * rpq;
+                    const double PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy),
+                                 PQz = ACz + (P.PAz - Q.PAz);
+                    if (boys_lane) {
+                        const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+                        const double pref = live ? 34.986836655249725 / (p * qq * sqrt(pq)) * P.K * Q.K : 0.0;
+                        V0[gg * A.nV + 1 + m] = pref * coop_boys(m, T, tab);
+                    } else {
+                        double *c = c0 + gg * kNCoef;
+                        c[kC0] = 0.0;
+                        c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
+                        c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
+                        c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
+                        c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
+                        c[kO2P] = 0.5 / p; c[kO2PR] = 0.5 / p * rho / p;
+                        c[kO2Q] = 0.5 / qq; c[kO2QR] = 0.5 / qq * rho / qq;
+                        c[kO2PQ] = 0.5 * rpq;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int lv = 0; lv < A.nvlev; ++lv) {
+                const int b0 = A.vlev[lv], nops = A.vlev[lv + 1] - b0;
+                for (int t = lane; t < nops * G; t += 64) {
+                    const int g = t % G;
+                    const int4 op = A.vops[b0 + t / G];
+                    double *V = V0 + g * A.nV;
+                    V[op.x & 0xffff] = run_op(op, V, c0 + g * kNCoef);
+                }
+                __syncthreads();
+            }
+            for (int s = lane; s < A.nacc; s += 64) {
+                const int src = A.accsrc[s];
+                double acc = H[s];
+#pragma unroll
+                for (int g = 0; g < G; ++g) acc += V0[g * A.nV + src];
+                H[s] = acc;
+            }
+        }
+        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
         __syncthreads();  // H reused by the next quartet
     }
+}
+
+
+// --------------------------------------------------- primitive lanes
+//
+// Alternative mapping for classes whose unrolled recursion fits in one
+// lane's registers but whose contracted intermediates do not: one wave per
+// shell quartet, lane k evaluating primitive quartet k (then k + 64, ...)
+// with the fully unrolled recursion; after each round of 64 the wave sums
+// the intermediates with a butterfly reduce-scatter (six exchange steps,
+// each lane keeping half of what it holds), so lane l ends with the sums of
+// intermediates [l*NPER, (l+1)*NPER).  The horizontal recursion and output
+// then run table-driven as in k_coop.
+
+template <int NP, int C, int O>
+__device__ __forceinline__ void rs_step(double (&v)[NP], const int lane) {
+    const bool up = (lane & O) != 0;
+    static_for<0, C / 2>([&](auto I) {
+        constexpr int k = decltype(I)::value;
+        const double lo = v[k], hi = v[k + C / 2];
+        const double send = up ? lo : hi;
+        const double keep = up ? hi : lo;
+        v[k] = keep + __shfl_xor(send, O, 64);
+    });
+}
+
+template <class Dm, int MODE>
+__global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
+                                              int ket_off, int nbra, int same_class,
+                                              const int64_t *__restrict__ rowstart, int64_t total,
+                                              const PrimPair *__restrict__ pp, const double *__restrict__ tab,
+                                              const double *__restrict__ etab, const double *__restrict__ D, int N,
+                                              double *__restrict__ out0, double *__restrict__ out1) {
+    constexpr int NACC = Dm::NFA * Dm::NEA;
+    constexpr int NP = ((NACC + 63) / 64) * 64, NPER = NP / 64;
+    extern __shared__ double lds[];
+    double *H = lds;
+    double *hc = lds + A.nH;
+    const int lane = threadIdx.x;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        int i, j;
+        if (MODE == kModeSchwarz) {
+            i = j = (int)q;
+        } else {
+            i = find_row(rowstart, nbra, q);
+            j = (int)(q - rowstart[i]);
+        }
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
+        const double AC[3] = {bra.Ax - ket.Ax, bra.Ay - ket.Ay, bra.Az - ket.Az};
+        double part[NPER];
+        static_for<0, NPER>([&](auto I) { part[I] = 0.0; });
+        const int nprim = bra.npp * ket.npp;
+        for (int k0 = 0; k0 < nprim; k0 += 64) {
+            const int k = k0 + lane;
+            double a[Dm::NFA][Dm::NEA];
+            static_for<0, Dm::NFA>([&](auto F) {
+                static_for<0, Dm::NEA>([&](auto E) { a[decltype(F)::value][decltype(E)::value] = 0.0; });
+            });
+            if (k < nprim) {
+                const PrimPair P = pp[bra.pp0 + k / ket.npp];
+                const PrimPair Q = pp[ket.pp0 + k % ket.npp];
+                prim_quartet_f64<Dm>(P, Q, AC, tab, etab, a);
+            }
+            double v[NP];
+            static_for<0, NP>([&](auto I) {
+                constexpr int x = decltype(I)::value;
+                if constexpr (x < NACC) v[x] = a[x / Dm::NEA][x % Dm::NEA];
+                else v[x] = 0.0;
+            });
+            rs_step<NP, NP, 32>(v, lane);
+            rs_step<NP, NP / 2, 16>(v, lane);
+            rs_step<NP, NP / 4, 8>(v, lane);
+            rs_step<NP, NP / 8, 4>(v, lane);
+            rs_step<NP, NP / 16, 2>(v, lane);
+            rs_step<NP, NP / 32, 1>(v, lane);
+            static_for<0, NPER>([&](auto I) { part[I] += v[I]; });
+        }
+        static_for<0, NPER>([&](auto I) {
+            const int idx = lane * NPER + decltype(I)::value;
+            if (idx < NACC) H[idx] = part[I];
+        });
+        __syncthreads();
+        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
+        __syncthreads();
+    }
+}
+
+// Classes run with the primitive-lane mapping (measured faster than the
+// table-driven kernel; for (dd|dp) and (dd|dd) the unrolled recursion
+// spills too much and the table-driven kernel wins).
+static bool plane_class(int cb, int ck) { return (cb == 5 && (ck == 2 || ck == 3)) || (cb == 4 && (ck == 2 || ck == 4)); }
+
+template <int MODE>
+static void launch_plane(int cb, int ck, const CoopArgs &A, const ClassLaunch &L, int64_t total, unsigned g,
+                         size_t lds, const double *D, double *out0, double *out1) {
+#define MESS_PLANE(B, K)                                                                                          \
+    if (cb == B && ck == K)                                                                                       \
+        hipLaunchKernelGGL((k_plane<ClassOf<B, K>, MODE>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,  \
+                           L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, L.etab, D, L.N, out0,  \
+                           out1);
+    MESS_PLANE(5, 3)
+    MESS_PLANE(5, 2)
+    MESS_PLANE(4, 4)
+    MESS_PLANE(4, 2)
+#undef MESS_PLANE
 }
 
 static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t total, double *out0, double *out1,
@@ -598,32 +735,44 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     A.NA = ncart(P->LA); A.NB = ncart(P->LB); A.NC = ncart(P->LC); A.ND = ncart(P->LD);
     int64_t g = total;
     if (g > (1 << 20)) g = 1 << 20;
-    const size_t lds = P->lds_bytes;
-    if (lds > 160 * 1024) {
+    if (plane_class(cb, ck)) {
+        const size_t lds = sizeof(double) * (size_t)(P->nH + kNHCoef);
+        switch (mode) {
+            case kModeSchwarz: launch_plane<kModeSchwarz>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1); break;
+            case kModeDense: launch_plane<kModeDense>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1); break;
+            default: launch_plane<kModeJK>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1);
+        }
+        MESS_LAUNCH_CHECK();
+        return MESS_OK;
+    }
+    // primitive quartets in flight per wave: more while the block stays
+    // small enough in LDS for several waves per CU
+    int G = 4;
+    auto lds_for = [&](int g) {
+        return sizeof(double) * (size_t)(P->nacc + std::max(g * P->nV, P->nH - P->nacc) + g * kNCoef + kNHCoef);
+    };
+    while (G > 1 && lds_for(G) > 20 * 1024) G /= 2;
+    const size_t lds = lds_for(G);
+    if (lds > 64 * 1024) {
         set_error("internal: class (%d,%d) needs %zu bytes of LDS", cb, ck, lds);
         return MESS_E_UNSUPPORTED;
     }
-    if (lds > 64 * 1024) {
-        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeSchwarz>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeDense>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        MESS_HIP(hipFuncSetAttribute((const void *)k_coop<kModeJK>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
+#define MESS_COOP_GO(MODE, GG)                                                                                  \
+    hipLaunchKernelGGL((k_coop<MODE, GG>), dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,  \
+                       L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1)
+#define MESS_COOP_G(MODE)                   \
+    do {                                    \
+        if (G == 4) MESS_COOP_GO(MODE, 4);  \
+        else if (G == 2) MESS_COOP_GO(MODE, 2); \
+        else MESS_COOP_GO(MODE, 1);         \
+    } while (0)
     switch (mode) {
-        case kModeSchwarz:
-            hipLaunchKernelGGL(k_coop<kModeSchwarz>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
-            break;
-        case kModeDense:
-            hipLaunchKernelGGL(k_coop<kModeDense>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
-            break;
-        default:
-            hipLaunchKernelGGL(k_coop<kModeJK>, dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1);
+        case kModeSchwarz: MESS_COOP_G(kModeSchwarz); break;
+        case kModeDense: MESS_COOP_G(kModeDense); break;
+        default: MESS_COOP_G(kModeJK);
     }
+#undef MESS_COOP_G
+#undef MESS_COOP_GO
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }

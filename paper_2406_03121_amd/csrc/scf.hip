@@ -304,6 +304,47 @@ __global__ void k_canonical_x(int N, int M, int drop, const double *__restrict__
     }
 }
 
+// r = max |A - I| (single block)
+__global__ void __launch_bounds__(1024) k_maxabs_minus_identity(int N, const double *__restrict__ A,
+                                                                ScfScalars *__restrict__ sc) {
+    __shared__ double red[1024];
+    double m = 0.0;
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t i = threadIdx.x; i < NN; i += 1024) m = fmax(m, fabs(A[i] - ((i / N == i % N) ? 1.0 : 0.0)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->resid = red[0];
+}
+
+// max row sum of |A| (infinity norm, single block) -> sc->trX
+__global__ void __launch_bounds__(1024) k_norm_inf(int N, const double *__restrict__ A, ScfScalars *__restrict__ sc) {
+    __shared__ double red[1024];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < N; i += 1024) {
+        double r = 0.0;
+        for (int j = 0; j < N; ++j) r += fabs(A[(int64_t)i * N + j]);
+        m = fmax(m, r);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->trX = red[0];
+}
+
+__global__ void k_identity_scaled(int N, double a, const double *__restrict__ src, double *__restrict__ out) {
+    // out = a * src (src != NULL) or the identity (src == NULL)
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN; idx += (int64_t)gridDim.x * blockDim.x)
+        out[idx] = src ? a * src[idx] : ((idx / N == idx % N) ? 1.0 : 0.0);
+}
+
 static unsigned grid1(int64_t n) {
     int64_t g = (n + 255) / 256;
     if (g > 2048) g = 2048;
@@ -356,6 +397,57 @@ static int to_orthonormal(mess_scf *st, const double *F, double *Fp, hipStream_t
     return MESS_OK;
 }
 
+// Loewdin orthogonaliser X = S^{-1/2} by the coupled Newton-Schulz
+// iteration on A = S / c (c >= lambda_max(S) by Gershgorin, so the spectrum
+// of A lies in (0, 1]):  T = (3 I - Z Y)/2,  Y <- Y T,  Z <- T Z, from
+// Y = A, Z = I; Z -> A^{-1/2}.  *ok is false if it did not converge or if
+// lambda_min(S) >= 1 / ||S^{-1}||_inf cannot be shown to exceed 1e-6 (then
+// the caller uses the eigensolver and canonical dropping instead).
+static int lowdin_newton_schulz(mess_scf *st, hipStream_t s, bool *ok) {
+    const int N = st->N;
+    const int64_t nn = (int64_t)N * N;
+    *ok = false;
+    hipLaunchKernelGGL(k_gershgorin, dim3(1), dim3(1024), 0, s, N, st->S, st->sc);
+    ScfScalars h;
+    MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    const double c = h.emax;
+    if (!(c > 0.0) || !std::isfinite(c)) return MESS_OK;
+    double *Y = st->Gj, *Z = st->Gk, *T = st->F, *tmp = st->Fx;
+    hipLaunchKernelGGL(k_identity_scaled, dim3(grid1(nn)), dim3(256), 0, s, N, 1.0 / c, st->S, Y);
+    hipLaunchKernelGGL(k_identity_scaled, dim3(grid1(nn)), dim3(256), 0, s, N, 0.0, nullptr, Z);
+    MESS_LAUNCH_CHECK();
+    bool conv = false;
+    for (int it = 0; it < 80 && !conv; ++it) {
+        MESS_TRY(gemm(s, false, false, N, N, N, 1.0, Z, N, Y, N, 0.0, tmp, N));  // tmp = Z Y
+        if (it % 4 == 3) {
+            hipLaunchKernelGGL(k_maxabs_minus_identity, dim3(1), dim3(1024), 0, s, N, tmp, st->sc);
+            MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
+            MESS_HIP(hipStreamSynchronize(s));
+            if (!std::isfinite(h.resid)) return MESS_OK;
+            if (h.resid < 1e-14) conv = true;
+        }
+        hipLaunchKernelGGL(k_scale_identity_minus, dim3(grid1(nn)), dim3(256), 0, s, N, 1.5, -0.5, tmp, T);
+        MESS_TRY(gemm(s, false, false, N, N, N, 1.0, Y, N, T, N, 0.0, tmp, N));  // Y T
+        std::swap(Y, tmp);
+        MESS_TRY(gemm(s, false, false, N, N, N, 1.0, T, N, Z, N, 0.0, tmp, N));  // T Z
+        std::swap(Z, tmp);
+    }
+    if (!conv) return MESS_OK;
+    // X = Z / sqrt(c); bound lambda_min(S) >= 1/||X X||_inf
+    hipLaunchKernelGGL(k_identity_scaled, dim3(grid1(nn)), dim3(256), 0, s, N, 1.0 / std::sqrt(c), Z, st->X);
+    MESS_LAUNCH_CHECK();
+    MESS_TRY(gemm(s, false, false, N, N, N, 1.0, st->X, N, st->X, N, 0.0, tmp, N));
+    hipLaunchKernelGGL(k_norm_inf, dim3(1), dim3(1024), 0, s, N, tmp, st->sc);
+    MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    if (std::isfinite(h.trX) && h.trX > 0.0 && 1.0 / h.trX > 1e-6) {
+        st->M = N;
+        *ok = true;
+    }
+    return MESS_OK;
+}
+
 static void free_scf(mess_scf *st) {
     if (!st) return;
     for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
@@ -365,28 +457,13 @@ static void free_scf(mess_scf *st) {
     delete st;
 }
 
-static int scf_create_impl(mess_scf *st, const double *D0) {
+// Canonical orthogonaliser X = U s^{-1/2} over the eigenpairs of S with
+// s > 1e-7, from the one-workgroup Jacobi eigensolver.
+static int canonical_orthogonaliser(mess_scf *st, hipStream_t s) {
     mess_basis *B = st->basis;
-    const int N = B->nbf;
-    st->N = N;
-    hipStream_t s = nullptr;
+    const int N = st->N;
     const size_t nn = (size_t)N * N;
-    for (double **p : {&st->S, &st->H, &st->X, &st->D, &st->F, &st->Fx, &st->Gj, &st->Gk, &st->W1, &st->W2, &st->W3,
-                       &st->P, &st->P2})
-        MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
-    const int nd = std::max(1, std::min(st->opts.diis_size, kMaxDiis));
-    MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * nn * nd));
-    MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * nn * nd));
-    MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kMaxDiis * kMaxDiis));
-    MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
-    MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
-    MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
-    // one-electron: S in S, T in W1, V in W2 -> H
-    MESS_TRY(mess_one_electron(B, st->S, st->W1, st->W2, s));
-    MESS_TRY(axpby(s, (int64_t)nn, 1.0, st->W1, 1.0, st->W2, st->H));
-    // canonical orthogonaliser from the eigenpairs of S
     MESS_HIP(hipMemcpyAsync(st->W1, st->S, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    double *w = st->partial;  // N <= kRedBlocks? use W3 tail otherwise
     std::vector<double> wh(N);
     double *wdev = nullptr;
     MESS_HIP(hipMalloc(&wdev, sizeof(double) * N));
@@ -396,7 +473,6 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     if (rc == MESS_OK && hipMemcpyAsync(wh.data(), wdev, sizeof(double) * N, hipMemcpyDeviceToHost, s) != hipSuccess)
         rc = MESS_E_DEVICE;
     if (rc == MESS_OK && hipStreamSynchronize(s) != hipSuccess) rc = MESS_E_DEVICE;
-    (void)w;
     int drop = 0;
     if (rc == MESS_OK) {
         for (int i = 0; i < N; ++i)
@@ -427,6 +503,33 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
         if (rc == MESS_E_DEVICE) set_error("mess_scf_create: device error in the overlap eigensolve");
         return rc;
     }
+    return MESS_OK;
+}
+
+static int scf_create_impl(mess_scf *st, const double *D0) {
+    mess_basis *B = st->basis;
+    const int N = B->nbf;
+    st->N = N;
+    hipStream_t s = nullptr;
+    const size_t nn = (size_t)N * N;
+    for (double **p : {&st->S, &st->H, &st->X, &st->D, &st->F, &st->Fx, &st->Gj, &st->Gk, &st->W1, &st->W2, &st->W3,
+                       &st->P, &st->P2})
+        MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
+    const int nd = std::max(1, std::min(st->opts.diis_size, kMaxDiis));
+    MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * nn * nd));
+    MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * nn * nd));
+    MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kMaxDiis * kMaxDiis));
+    MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
+    MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
+    MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
+    // one-electron: S in S, T in W1, V in W2 -> H
+    MESS_TRY(mess_one_electron(B, st->S, st->W1, st->W2, s));
+    MESS_TRY(axpby(s, (int64_t)nn, 1.0, st->W1, 1.0, st->W2, st->H));
+    // Loewdin orthogonaliser by Newton-Schulz; eigensolver + canonical
+    // dropping only when S may be near-singular
+    bool lowdin = false;
+    MESS_TRY(lowdin_newton_schulz(st, s, &lowdin));
+    if (!lowdin) MESS_TRY(canonical_orthogonaliser(st, s));
     const int M = st->M;
     // two Newton steps X <- X (3 I - X^T S X) / 2 restore X^T S X = I to rounding
     for (int k = 0; k < 2; ++k) {
