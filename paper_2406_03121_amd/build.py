@@ -31,6 +31,8 @@ CLASSES = [(cb, ck) for cb in range(6) for ck in range(cb + 1)]
 # classes evaluated by the wave-cooperative kernel (coop.hip) instead
 COOP_CLASSES = {(4, 2), (4, 4), (5, 2), (5, 3), (5, 4), (5, 5)}
 UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
+# primitive-lane kernels (plane.hip), one object per class and precision
+PLANE_CLASSES = [(5, 3), (5, 2), (4, 4), (4, 2)]
 
 
 def _units():
@@ -41,16 +43,34 @@ def _units():
             for cb, ck in UNROLLED_CLASSES:
                 units.append((src, os.path.join(OBJ, f"eri_class_{cb}{ck}.o"),
                               [f"-DMESS_CB={cb}", f"-DMESS_CK={ck}"]))
+        elif name == "plane":
+            for cb, ck in PLANE_CLASSES:
+                for real in ("double", "float"):
+                    units.append((src, os.path.join(OBJ, f"plane_{cb}{ck}_{real}.o"),
+                                  [f"-DMESS_PCB={cb}", f"-DMESS_PCK={ck}", f"-DMESS_PREAL={real}"]))
         else:
             units.append((src, os.path.join(OBJ, name + ".o"), []))
     # heaviest classes first so the parallel build finishes sooner
-    units.sort(key=lambda u: -sum(int(x[-1]) for x in u[2]) if u[2] else 0)
+    def weight(u):
+        w = 0
+        for d in u[2]:
+            if d.startswith("-DMESS_CB=") or d.startswith("-DMESS_CK=") or d.startswith("-DMESS_PC"):
+                w += int(d.split("=")[1])
+        return -w - (10 if "plane" in u[1] else 0)
+    units.sort(key=weight)
     return units
 
 
 def _headers_mtime():
     hs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
     return max(os.path.getmtime(h) for h in hs)
+
+
+def _clean_stale(units):
+    keep = {u[1] for u in units}
+    for o in glob.glob(os.path.join(OBJ, "*.o")):
+        if o not in keep:
+            os.remove(o)
 
 
 def _compile(unit, force):
@@ -71,6 +91,7 @@ def _compile(unit, force):
 def build(force: bool = False, jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     units = _units()
+    _clean_stale(units)
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -11,28 +11,13 @@
 #include <memory>
 #include <mutex>
 
-#include "class_ops.hpp"
-#include "eri_kernels.hpp"
-#include "mess_internal.hpp"
+#include "coop.hpp"
 
 namespace mess {
 
 // Recursion step: v = c[a1] V[s1] + c[a2] V[s2] + k3 (c[a3] V[s3] - c[a4] V[s4]) + k5 c[a5] V[s5]
 // packed as x = dst | s1 << 16, y = s2 | s3 << 16, z = s4 | s5 << 16,
 // w = a1 | a2 << 5 | a3 << 10 | a4 << 15 | a5 << 20 | k3 << 25 | k5 << 28.
-// Coefficient slots (per primitive quartet):
-enum : int {
-    kC0 = 0,                 // 0
-    kPA = 1, kWP = 4,        // PA_xyz, WP_xyz (bra)
-    kQC = 7, kWQ = 10,       // QC_xyz, WQ_xyz (ket)
-    kO2P = 13, kO2PR = 14,   // 1/(2p), rho/(2p^2)
-    kO2Q = 15, kO2QR = 16,   // 1/(2q), rho/(2q^2)
-    kO2PQ = 17,              // 1/(2(p+q))
-    kNCoef = 18
-};
-// Horizontal-recursion coefficients: 0 -> 0, 1 -> 1, 2..4 -> AB, 5..7 -> CD.
-enum : int { kH0 = 0, kH1 = 1, kHAB = 2, kHCD = 5, kNHCoef = 8 };
-
 struct CoopProgram {
     int cb = 0, ck = 0, LA = 0, LB = 0, LC = 0, LD = 0, L = 0;
     int nV = 0;       // VRR slots (slot 0 holds 0.0); slots 1..L+1 are [0|0]^(m)
@@ -362,187 +347,56 @@ static const CoopProgram *coop_program(int cb, int ck) {
 
 // ------------------------------------------------------------ device
 
-struct CoopArgs {
-    const int4 *vops;
-    const int *vlev;
-    const unsigned short *accsrc;
-    const int4 *hops;
-    const int *hlev;
-    const unsigned short *outslot;
-    const double *outscale;
-    int nV, nH, nacc, nout, nvlev, nhlev, L;
-    int NA, NB, NC, ND;
-};
-
-enum { kModeSchwarz = 0, kModeDense = 1, kModeJK = 2 };
-
-__device__ __forceinline__ double coop_boys(int m, double T, const double *__restrict__ tab) {
-    // F_m(T), m <= 8, directly (no recurrence): Taylor about the nearest grid
-    // point for T < 60, the large-T form (2m-1)!!/(2T)^m sqrt(pi/T)/2 above.
-    if (T < kBoysTmax) {
-        const int k = __double2int_rn(T * kBoysInvStep);
-        const double md = static_cast<double>(k) * (1.0 / kBoysInvStep) - T;
-        const double *row = tab + k * kBoysN + m;
-        double f = row[7];
-        f = row[6] + md * (1.0 / 7.0) * f;
-        f = row[5] + md * (1.0 / 6.0) * f;
-        f = row[4] + md * (1.0 / 5.0) * f;
-        f = row[3] + md * (1.0 / 4.0) * f;
-        f = row[2] + md * (1.0 / 3.0) * f;
-        f = row[1] + md * (1.0 / 2.0) * f;
-        return row[0] + md * f;
-    }
-    const double rT = 1.0 / T;
-    double f = 0.5 * sqrt(M_PI * rT);
-    for (int n = 0; n < m; ++n) f *= (2 * n + 1) * 0.5 * rT;
-    return f;
-}
-
-__device__ __forceinline__ double run_op(const int4 op, const double *__restrict__ V, const double *__restrict__ c) {
+template <typename Real>
+__device__ __forceinline__ Real run_op_r(const int4 op, const Real *__restrict__ V, const Real *__restrict__ c) {
     const int s1 = op.x >> 16, s2 = op.y & 0xffff, s3 = op.y >> 16, s4 = op.z & 0xffff, s5 = op.z >> 16;
     const int w = op.w;
     const int a1 = w & 31, a2 = (w >> 5) & 31, a3 = (w >> 10) & 31, a4 = (w >> 15) & 31, a5 = (w >> 20) & 31;
-    const double k3 = (double)((w >> 25) & 7), k5 = (double)((w >> 28) & 7);
-    double v = c[a1] * V[s1] + c[a2] * V[s2];
+    const Real k3 = (Real)((w >> 25) & 7), k5 = (Real)((w >> 28) & 7);
+    Real v = c[a1] * V[s1] + c[a2] * V[s2];
     v += k3 * (c[a3] * V[s3] - c[a4] * V[s4]);
     v += k5 * c[a5] * V[s5];
     return v;
 }
 
-// Horizontal recursion of the accumulated [e0|f0] (in H[0, nacc)) and the
-// per-mode output of one quartet, shared by the wave.
-template <int MODE>
-__device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restrict__ H, double *__restrict__ hc,
-                                            const int lane, const PairInfo &bra, const PairInfo &ket, const int i,
-                                            const int j, const int bra_off, const int same_class,
-                                            const double *__restrict__ D, const int N, double *__restrict__ out0,
-                                            double *__restrict__ out1) {
-        if (lane == 0) {
-            hc[kH0] = 0.0; hc[kH1] = 1.0;
-            hc[kHAB + 0] = bra.ABx; hc[kHAB + 1] = bra.ABy; hc[kHAB + 2] = bra.ABz;
-            hc[kHCD + 0] = ket.ABx; hc[kHCD + 1] = ket.ABy; hc[kHCD + 2] = ket.ABz;
-        }
-        __syncthreads();
-        for (int lv = 0; lv < A.nhlev; ++lv) {
-            const int b0 = A.hlev[lv], b1 = A.hlev[lv + 1];
-            for (int o = b0 + lane; o < b1; o += 64) {
-                const int4 op = A.hops[o];
-                H[op.x & 0xffff] = run_op(op, H, hc);
-            }
-            __syncthreads();
-        }
-        // output element o = ((a*NB + b)*NC + c)*ND + d is H[outslot[o]] * outscale[o]
-        const int NB = A.NB, NC = A.NC, ND = A.ND, NA = A.NA;
-        auto O = [&](int a, int b, int cc, int d) {
-            const int o = ((a * NB + b) * NC + cc) * ND + d;
-            return H[A.outslot[o]] * A.outscale[o];
-        };
-        if (MODE == kModeSchwarz) {
-            if (lane == 0) {
-                double m = 0.0;
-                for (int a = 0; a < NA; ++a)
-                    for (int b = 0; b < NB; ++b) m = fmax(m, fabs(O(a, b, a, b)));
-                out0[bra_off + i] = sqrt(m);
-            }
-        } else if (MODE == kModeDense) {
-            const int64_t NN = N;
-            for (int o = lane; o < A.nout; o += 64) {
-                const int d = o % ND, cc = (o / ND) % NC, b = (o / (ND * NC)) % NB, a = o / (ND * NC * NB);
-                const double v = H[A.outslot[o]] * A.outscale[o];
-                const int64_t ia = bra.bfa + a, ib = bra.bfb + b, ic = ket.bfa + cc, id = ket.bfb + d;
-                out0[((ia * NN + ib) * NN + ic) * NN + id] = v;
-                out0[((ib * NN + ia) * NN + ic) * NN + id] = v;
-                out0[((ia * NN + ib) * NN + id) * NN + ic] = v;
-                out0[((ib * NN + ia) * NN + id) * NN + ic] = v;
-                out0[((ic * NN + id) * NN + ia) * NN + ib] = v;
-                out0[((id * NN + ic) * NN + ia) * NN + ib] = v;
-                out0[((ic * NN + id) * NN + ib) * NN + ia] = v;
-                out0[((id * NN + ic) * NN + ib) * NN + ia] = v;
-            }
-        } else {
-            double fac = 1.0;
-            if (bra.sa == bra.sb) fac *= 0.5;
-            if (ket.sa == ket.sb) fac *= 0.5;
-            if (same_class && i == j) fac *= 0.5;
-            const int a0 = bra.bfa, b0 = bra.bfb, c0 = ket.bfa, d0 = ket.bfb;
-            auto Dv = [&](int r, int cidx) { return D[(int64_t)r * N + cidx]; };
-            double *Gj = out0, *Gk = out1;
-            const int nab = NA * NB, ncd = NC * ND;
-            // six target families, lanes over their elements
-            const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
-            const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0,
-                      t_bd = Gk ? NB * ND : 0;
-            const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
-            for (int t = lane; t < ntgt; t += 64) {
-                int r = t;
-                double s = 0.0;
-                if (r < t_ab) {
-                    const int a = r / NB, b = r % NB;
-                    for (int cc = 0; cc < NC; ++cc)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(c0 + cc, d0 + d);
-                    unsafeAtomicAdd(&Gj[(int64_t)(a0 + a) * N + b0 + b], 2.0 * fac * s);
-                    continue;
-                }
-                r -= t_ab;
-                if (r < t_cd) {
-                    const int cc = r / ND, d = r % ND;
-                    for (int a = 0; a < NA; ++a)
-                        for (int b = 0; b < NB; ++b) s += O(a, b, cc, d) * Dv(a0 + a, b0 + b);
-                    unsafeAtomicAdd(&Gj[(int64_t)(c0 + cc) * N + d0 + d], 2.0 * fac * s);
-                    continue;
-                }
-                r -= t_cd;
-                if (r < t_ac) {
-                    const int a = r / NC, cc = r % NC;
-                    for (int b = 0; b < NB; ++b)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(b0 + b, d0 + d);
-                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + c0 + cc], fac * s);
-                    continue;
-                }
-                r -= t_ac;
-                if (r < t_bc) {
-                    const int b = r / NC, cc = r % NC;
-                    for (int a = 0; a < NA; ++a)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(a0 + a, d0 + d);
-                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + c0 + cc], fac * s);
-                    continue;
-                }
-                r -= t_bc;
-                if (r < t_ad) {
-                    const int a = r / ND, d = r % ND;
-                    for (int b = 0; b < NB; ++b)
-                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(b0 + b, c0 + cc);
-                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + d0 + d], fac * s);
-                    continue;
-                }
-                r -= t_ad;
-                {
-                    const int b = r / ND, d = r % ND;
-                    for (int a = 0; a < NA; ++a)
-                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(a0 + a, c0 + cc);
-                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + d0 + d], fac * s);
-                }
-            }
-        }
+// F_m(T) in the kernel's arithmetic: FP64 form above, or FP32 Taylor for
+// 1e-3 <= T <= 30 with the FP64 form rounded to FP32 outside.
+template <typename Real>
+__device__ __forceinline__ Real coop_boys_r(int m, Real T, const BoysTabs &bt) {
+    if constexpr (sizeof(Real) == 8) {
+        return coop_boys(m, T, bt.tab);
+    } else {
+        if (T < 1e-3f || T > 30.0f) return (float)coop_boys(m, (double)T, bt.tab);
+        const int k = __float2int_rn(T * (float)kBoysInvStep);
+        const float md = (float)k * (float)(1.0 / kBoysInvStep) - T;
+        const float *row = bt.tabf + k * kBoysN + m;
+        float f = row[5];
+        f = row[4] + md * (1.0f / 5.0f) * f;
+        f = row[3] + md * (1.0f / 4.0f) * f;
+        f = row[2] + md * (1.0f / 3.0f) * f;
+        f = row[1] + md * (1.0f / 2.0f) * f;
+        return row[0] + md * f;
+    }
 }
 
-template <int MODE, int G>
-__global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
+template <int MODE, typename Real>
+__global__ void __launch_bounds__(64) k_coop(CoopArgs A, int region, const PairInfo *__restrict__ pairs, int bra_off,
                                              int ket_off, int nbra, int same_class,
                                              const int64_t *__restrict__ rowstart, int64_t total,
-                                             const PrimPair *__restrict__ pp, const double *__restrict__ tab,
+                                             const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                              const double *__restrict__ D, int N, double *__restrict__ out0,
                                              double *__restrict__ out1) {
-    // G primitive quartets of the same shell quartet are in flight at once,
-    // each with its own VRR slots and coefficient set.
+    // LDS: accumulators H[0, nacc) (FP64), then `region` doubles shared by the
+    // VRR slots (Real, during the primitive loop) and the HRR slots >= nacc
+    // (after it), then the VRR coefficients (Real) and the HRR coefficients.
     extern __shared__ double lds[];
-    double *H = lds;                 // HRR slots; [0, nacc) are the accumulators
-    double *V0 = lds + A.nacc;       // G x nV VRR slots, aliasing HRR slots >= nacc
-    double *c0 = lds + A.nacc + max(G * A.nV, A.nH - A.nacc);  // G x kNCoef
-    double *hc = c0 + G * kNCoef;                              // kNHCoef
+    double *H = lds;
+    Real *V = reinterpret_cast<Real *>(lds + A.nacc);
+    Real *c = reinterpret_cast<Real *>(lds + A.nacc + region);
+    double *hc = lds + A.nacc + region + (kNCoef * sizeof(Real) + 7) / 8;
     const int lane = threadIdx.x;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-        if (lane < G) V0[lane * A.nV] = 0.0;
+        if (lane == 0) V[0] = Real(0);
         int i, j;
         if (MODE == kModeSchwarz) {
             i = j = (int)q;
@@ -552,175 +406,70 @@ __global__ void __launch_bounds__(64) k_coop(CoopArgs A, const PairInfo *__restr
         }
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
-        const double ACx = bra.Ax - ket.Ax, ACy = bra.Ay - ket.Ay, ACz = bra.Az - ket.Az;
+        const Real ACx = Real(bra.Ax - ket.Ax), ACy = Real(bra.Ay - ket.Ay), ACz = Real(bra.Az - ket.Az);
         for (int s = lane; s < A.nacc; s += 64) H[s] = 0.0;
-        const int nprim = bra.npp * ket.npp;
-        for (int base = 0; base < nprim; base += G) {
-            __syncthreads();  // previous primitive quartets fully consumed
-            // set-up: Boys values (lanes g*(L+1) .. ) and coefficients (lanes 48 + g)
-            {
-                const int g = lane / (A.L + 1), m = lane % (A.L + 1);
-                const bool boys_lane = g < G;
-                const int gc = lane - 48;
-                const bool coef_lane = gc >= 0 && gc < G;
-                if (boys_lane || coef_lane) {
-                    const int gg = boys_lane ? g : gc;
-                    const int pi = base + gg;
-                    const bool live = pi < nprim;
-                    const PrimPair P = pp[bra.pp0 + (live ? pi / ket.npp : 0)];
-                    const PrimPair Q = pp[ket.pp0 + (live ? pi % ket.npp : 0)];
-                    const double p = P.p, qq = Q.p, pq = p + qq, rpq = 1.0 / pq, rho = p * qq * rpq;
-                    const double PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy),
-                                 PQz = ACz + (P.PAz - Q.PAz);
-                    if (boys_lane) {
-                        const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-                        const double pref = live ? 34.986836655249725 / (p * qq * sqrt(pq)) * P.K * Q.K : 0.0;
-                        V0[gg * A.nV + 1 + m] = pref * coop_boys(m, T, tab);
-                    } else {
-                        double *c = c0 + gg * kNCoef;
-                        c[kC0] = 0.0;
-                        c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
-                        c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
-                        c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
-                        c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
-                        c[kO2P] = 0.5 / p; c[kO2PR] = 0.5 / p * rho / p;
-                        c[kO2Q] = 0.5 / qq; c[kO2QR] = 0.5 / qq * rho / qq;
-                        c[kO2PQ] = 0.5 * rpq;
-                    }
+        for (int ib = 0; ib < bra.npp; ++ib) {
+            const PrimPairT<Real> P = pp[bra.pp0 + ib];
+            for (int ik = 0; ik < ket.npp; ++ik) {
+                const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+                const Real p = P.p, qq = Q.p, pq = p + qq, rpq = Real(1) / pq, rho = p * qq * rpq;
+                const Real PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
+                const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+                __syncthreads();  // previous primitive quartet fully consumed
+                if (lane <= A.L) {
+                    const Real pref = Real(34.986836655249725) / (p * qq * sqrt(pq)) * P.K * Q.K;
+                    V[1 + lane] = pref * coop_boys_r<Real>(lane, T, bt);
                 }
-            }
-            __syncthreads();
-            for (int lv = 0; lv < A.nvlev; ++lv) {
-                const int b0 = A.vlev[lv], nops = A.vlev[lv + 1] - b0;
-                for (int t = lane; t < nops * G; t += 64) {
-                    const int g = t % G;
-                    const int4 op = A.vops[b0 + t / G];
-                    double *V = V0 + g * A.nV;
-                    V[op.x & 0xffff] = run_op(op, V, c0 + g * kNCoef);
+                if (lane == 32) {
+                    c[kC0] = Real(0);
+                    c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
+                    c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
+                    c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
+                    c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
+                    c[kO2P] = Real(0.5) / p; c[kO2PR] = Real(0.5) / p * rho / p;
+                    c[kO2Q] = Real(0.5) / qq; c[kO2QR] = Real(0.5) / qq * rho / qq;
+                    c[kO2PQ] = Real(0.5) * rpq;
                 }
                 __syncthreads();
-            }
-            for (int s = lane; s < A.nacc; s += 64) {
-                const int src = A.accsrc[s];
-                double acc = H[s];
-#pragma unroll
-                for (int g = 0; g < G; ++g) acc += V0[g * A.nV + src];
-                H[s] = acc;
+                for (int lv = 0; lv < A.nvlev; ++lv) {
+                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
+                    for (int o = b0 + lane; o < b1; o += 64) {
+                        const int4 op = A.vops[o];
+                        V[op.x & 0xffff] = run_op_r<Real>(op, V, c);
+                    }
+                    __syncthreads();
+                }
+                for (int s = lane; s < A.nacc; s += 64) H[s] += (double)V[A.accsrc[s]];
             }
         }
+        __syncthreads();
         coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
         __syncthreads();  // H reused by the next quartet
     }
 }
 
-
-// --------------------------------------------------- primitive lanes
-//
-// Alternative mapping for classes whose unrolled recursion fits in one
-// lane's registers but whose contracted intermediates do not: one wave per
-// shell quartet, lane k evaluating primitive quartet k (then k + 64, ...)
-// with the fully unrolled recursion; after each round of 64 the wave sums
-// the intermediates with a butterfly reduce-scatter (six exchange steps,
-// each lane keeping half of what it holds), so lane l ends with the sums of
-// intermediates [l*NPER, (l+1)*NPER).  The horizontal recursion and output
-// then run table-driven as in k_coop.
-
-template <int NP, int C, int O>
-__device__ __forceinline__ void rs_step(double (&v)[NP], const int lane) {
-    const bool up = (lane & O) != 0;
-    static_for<0, C / 2>([&](auto I) {
-        constexpr int k = decltype(I)::value;
-        const double lo = v[k], hi = v[k + C / 2];
-        const double send = up ? lo : hi;
-        const double keep = up ? hi : lo;
-        v[k] = keep + __shfl_xor(send, O, 64);
-    });
-}
-
-template <class Dm, int MODE>
-__global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
-                                              int ket_off, int nbra, int same_class,
-                                              const int64_t *__restrict__ rowstart, int64_t total,
-                                              const PrimPair *__restrict__ pp, const double *__restrict__ tab,
-                                              const double *__restrict__ etab, const double *__restrict__ D, int N,
-                                              double *__restrict__ out0, double *__restrict__ out1) {
-    constexpr int NACC = Dm::NFA * Dm::NEA;
-    constexpr int NP = ((NACC + 63) / 64) * 64, NPER = NP / 64;
-    extern __shared__ double lds[];
-    double *H = lds;
-    double *hc = lds + A.nH;
-    const int lane = threadIdx.x;
-    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-        int i, j;
-        if (MODE == kModeSchwarz) {
-            i = j = (int)q;
-        } else {
-            i = find_row(rowstart, nbra, q);
-            j = (int)(q - rowstart[i]);
-        }
-        const PairInfo bra = pairs[bra_off + i];
-        const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
-        const double AC[3] = {bra.Ax - ket.Ax, bra.Ay - ket.Ay, bra.Az - ket.Az};
-        double part[NPER];
-        static_for<0, NPER>([&](auto I) { part[I] = 0.0; });
-        const int nprim = bra.npp * ket.npp;
-        for (int k0 = 0; k0 < nprim; k0 += 64) {
-            const int k = k0 + lane;
-            double a[Dm::NFA][Dm::NEA];
-            static_for<0, Dm::NFA>([&](auto F) {
-                static_for<0, Dm::NEA>([&](auto E) { a[decltype(F)::value][decltype(E)::value] = 0.0; });
-            });
-            if (k < nprim) {
-                const PrimPair P = pp[bra.pp0 + k / ket.npp];
-                const PrimPair Q = pp[ket.pp0 + k % ket.npp];
-                prim_quartet_f64<Dm>(P, Q, AC, tab, etab, a);
-            }
-            double v[NP];
-            static_for<0, NP>([&](auto I) {
-                constexpr int x = decltype(I)::value;
-                if constexpr (x < NACC) v[x] = a[x / Dm::NEA][x % Dm::NEA];
-                else v[x] = 0.0;
-            });
-            rs_step<NP, NP, 32>(v, lane);
-            rs_step<NP, NP / 2, 16>(v, lane);
-            rs_step<NP, NP / 4, 8>(v, lane);
-            rs_step<NP, NP / 8, 4>(v, lane);
-            rs_step<NP, NP / 16, 2>(v, lane);
-            rs_step<NP, NP / 32, 1>(v, lane);
-            static_for<0, NPER>([&](auto I) { part[I] += v[I]; });
-        }
-        static_for<0, NPER>([&](auto I) {
-            const int idx = lane * NPER + decltype(I)::value;
-            if (idx < NACC) H[idx] = part[I];
-        });
-        __syncthreads();
-        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
-        __syncthreads();
-    }
-}
-
-// Classes run with the primitive-lane mapping (measured faster than the
-// table-driven kernel; for (dd|dp) and (dd|dd) the unrolled recursion
-// spills too much and the table-driven kernel wins).
+// Classes run with the primitive-lane mapping in FP64 (measured faster than
+// the table-driven kernel; for (dd|dp) and (dd|dd) the unrolled recursion
+// spills too much and the table-driven kernel wins).  In FP32 the
+// primitive-lane mapping serves every high class except (dd|dp), (dd|dd).
 static bool plane_class(int cb, int ck) { return (cb == 5 && (ck == 2 || ck == 3)) || (cb == 4 && (ck == 2 || ck == 4)); }
 
-template <int MODE>
-static void launch_plane(int cb, int ck, const CoopArgs &A, const ClassLaunch &L, int64_t total, unsigned g,
-                         size_t lds, const double *D, double *out0, double *out1) {
-#define MESS_PLANE(B, K)                                                                                          \
-    if (cb == B && ck == K)                                                                                       \
-        hipLaunchKernelGGL((k_plane<ClassOf<B, K>, MODE>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,  \
-                           L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, L.etab, D, L.N, out0,  \
-                           out1);
-    MESS_PLANE(5, 3)
-    MESS_PLANE(5, 2)
-    MESS_PLANE(4, 4)
-    MESS_PLANE(4, 2)
-#undef MESS_PLANE
+static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, const ClassLaunch &L, int64_t total,
+                         unsigned g, size_t lds, const double *D, double *out0, double *out1) {
+#define MESS_PL(B, K)                                                                                  \
+    if (cb == B && ck == K) {                                                                          \
+        if (prec == MESS_FP32) PlaneOps<B, K, float>::launch(mode, A, L, total, g, lds, D, out0, out1);  \
+        else PlaneOps<B, K, double>::launch(mode, A, L, total, g, lds, D, out0, out1);                   \
+    }
+    MESS_PL(5, 3)
+    MESS_PL(5, 2)
+    MESS_PL(4, 4)
+    MESS_PL(4, 2)
+#undef MESS_PL
 }
 
 static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t total, double *out0, double *out1,
-                       const double *D) {
+                       const double *D, int prec = MESS_FP64) {
     const CoopProgram *P = coop_program(cb, ck);
     if (!P) {
         set_error("internal: cooperative program for class (%d,%d) could not be built", cb, ck);
@@ -737,41 +486,32 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     if (g > (1 << 20)) g = 1 << 20;
     if (plane_class(cb, ck)) {
         const size_t lds = sizeof(double) * (size_t)(P->nH + kNHCoef);
-        switch (mode) {
-            case kModeSchwarz: launch_plane<kModeSchwarz>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1); break;
-            case kModeDense: launch_plane<kModeDense>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1); break;
-            default: launch_plane<kModeJK>(cb, ck, A, L, total, (unsigned)g, lds, D, out0, out1);
-        }
+        launch_plane(mode, cb, ck, prec, A, L, total, (unsigned)g, lds, D, out0, out1);
         MESS_LAUNCH_CHECK();
         return MESS_OK;
     }
-    // primitive quartets in flight per wave: more while the block stays
-    // small enough in LDS for several waves per CU
-    int G = 4;
-    auto lds_for = [&](int g) {
-        return sizeof(double) * (size_t)(P->nacc + std::max(g * P->nV, P->nH - P->nacc) + g * kNCoef + kNHCoef);
-    };
-    while (G > 1 && lds_for(G) > 20 * 1024) G /= 2;
-    const size_t lds = lds_for(G);
+    const size_t rsz = prec == MESS_FP32 ? sizeof(float) : sizeof(double);
+    const int region = (int)std::max<size_t>((P->nV * rsz + 7) / 8, (size_t)(P->nH - P->nacc));
+    const size_t lds = sizeof(double) * ((size_t)P->nacc + region + (kNCoef * rsz + 7) / 8 + kNHCoef);
     if (lds > 64 * 1024) {
         set_error("internal: class (%d,%d) needs %zu bytes of LDS", cb, ck, lds);
         return MESS_E_UNSUPPORTED;
     }
-#define MESS_COOP_GO(MODE, GG)                                                                                  \
-    hipLaunchKernelGGL((k_coop<MODE, GG>), dim3((unsigned)g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,  \
-                       L.ket_off, L.nbra, L.same_class, L.rowstart, total, L.pp, L.tab, D, L.N, out0, out1)
-#define MESS_COOP_G(MODE)                   \
-    do {                                    \
-        if (G == 4) MESS_COOP_GO(MODE, 4);  \
-        else if (G == 2) MESS_COOP_GO(MODE, 2); \
-        else MESS_COOP_GO(MODE, 1);         \
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+#define MESS_COOP_GO(MODE, R, PP)                                                                                 \
+    hipLaunchKernelGGL((k_coop<MODE, R>), dim3((unsigned)g), dim3(64), lds, L.stream, A, region, L.pairs,        \
+                       L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, total, PP, bt, D, L.N, out0, out1)
+#define MESS_COOP_M(MODE)                                            \
+    do {                                                             \
+        if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf);     \
+        else MESS_COOP_GO(MODE, double, L.pp);                       \
     } while (0)
     switch (mode) {
-        case kModeSchwarz: MESS_COOP_G(kModeSchwarz); break;
-        case kModeDense: MESS_COOP_G(kModeDense); break;
-        default: MESS_COOP_G(kModeJK);
+        case kModeSchwarz: MESS_COOP_M(kModeSchwarz); break;
+        case kModeDense: MESS_COOP_M(kModeDense); break;
+        default: MESS_COOP_M(kModeJK);
     }
-#undef MESS_COOP_G
+#undef MESS_COOP_M
 #undef MESS_COOP_GO
     MESS_LAUNCH_CHECK();
     return MESS_OK;
@@ -785,19 +525,11 @@ int coop_schwarz(int c, const ClassLaunch &L, int off, int n, double *Q) {
 }
 
 int coop_dense(int cb, int ck, const ClassLaunch &L, double *eri, int prec) {
-    if (prec != MESS_FP64) {
-        set_error("dense ERI store: only MESS_FP64 arithmetic is built for this layout");
-        return MESS_E_UNSUPPORTED;
-    }
-    return coop_launch(kModeDense, cb, ck, L, L.total, eri, nullptr, nullptr);
+    return coop_launch(kModeDense, cb, ck, L, L.total, eri, nullptr, nullptr, prec);
 }
 
 int coop_jk(int cb, int ck, const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec) {
-    if (prec != MESS_FP64) {
-        set_error("direct J/K: FP32 arithmetic is not built for class (%d,%d)", cb, ck);
-        return MESS_E_UNSUPPORTED;
-    }
-    return coop_launch(kModeJK, cb, ck, L, L.total, Gj, Gk, D);
+    return coop_launch(kModeJK, cb, ck, L, L.total, Gj, Gk, D, prec);
 }
 
 }  // namespace mess

@@ -38,12 +38,13 @@ template <>
 int ClassOps<MESS_CB, MESS_CK>::dense(const ClassLaunch &L, double *eri, int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
-    if (prec != MESS_FP64) {
-        set_error("dense ERI store: only MESS_FP64 arithmetic is built for this layout");
-        return MESS_E_UNSUPPORTED;
-    }
-    hipLaunchKernelGGL(k_eri_dense<Dm>, dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                       L.bra_off, L.ket_off, L.nbra, L.rowstart, L.pp, L.tab, L.etab, (int64_t)L.N, eri);
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL((k_eri_dense<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.ppf, bt, (int64_t)L.N, eri);
+    else
+        hipLaunchKernelGGL((k_eri_dense<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.pp, bt, (int64_t)L.N, eri);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
@@ -53,13 +54,15 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
                                    int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
-    if (prec != MESS_FP64) {
-        set_error("direct J/K: FP32 arithmetic is not built");
-        return MESS_E_UNSUPPORTED;
-    }
-    hipLaunchKernelGGL(k_jk_direct<Dm>, dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                       L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.pp, L.tab, L.etab, D,
-                       L.N, Gj, Gk);
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL((k_jk_direct<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.ppf, bt, D, L.N, Gj,
+                           Gk);
+    else
+        hipLaunchKernelGGL((k_jk_direct<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.pp, bt, D, L.N, Gj,
+                           Gk);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }

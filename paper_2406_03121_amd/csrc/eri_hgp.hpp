@@ -65,6 +65,61 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
     }
 }
 
+// FP32 Boys function (mixed-precision path): FP32 Taylor expansion about the
+// grid point (6 terms, |T - T_k| <= 1/32, truncation 1.3e-12 relative) and
+// FP32 downward recurrence for 1e-3 <= T <= 30; the FP64 evaluation above,
+// rounded to FP32, for T < 1e-3 and T > 30.
+struct BoysTabs {
+    const double *tab, *etab;
+    const float *tabf, *etabf;
+};
+
+template <int L>
+__device__ __forceinline__ void boys_f32(float T, const BoysTabs &bt, float (&F)[L + 1]) {
+    if (T < 1e-3f || T > 30.0f) {
+        double Fd[L + 1];
+        boys_f64<L>((double)T, bt.tab, bt.etab, Fd);
+        static_for<0, L + 1>([&](auto M) { F[M] = (float)Fd[M]; });
+        return;
+    }
+    const int k = __float2int_rn(T * (float)kBoysInvStep);
+    const float md = (float)k * (float)(1.0 / kBoysInvStep) - T;
+    const float *row = bt.tabf + k * kBoysN + L;
+    float f = row[5];
+    f = row[4] + md * (1.0f / 5.0f) * f;
+    f = row[3] + md * (1.0f / 4.0f) * f;
+    f = row[2] + md * (1.0f / 3.0f) * f;
+    f = row[1] + md * (1.0f / 2.0f) * f;
+    f = row[0] + md * f;
+    F[L] = f;
+    if constexpr (L > 0) {
+        float e = 1.0f + md * (1.0f / 5.0f);
+        e = 1.0f + md * (1.0f / 4.0f) * e;
+        e = 1.0f + md * (1.0f / 3.0f) * e;
+        e = 1.0f + md * (1.0f / 2.0f) * e;
+        e = 1.0f + md * e;
+        e *= bt.etabf[k];
+        const float t2 = 2.0f * T;
+        static_for<0, L>([&](auto I) {
+            constexpr int m = L - 1 - decltype(I)::value;
+            F[m] = (t2 * F[m + 1] + e) * (1.0f / (2 * m + 1));
+        });
+    }
+}
+
+template <int L, typename Real>
+__device__ __forceinline__ void boys_eval(Real T, const BoysTabs &bt, Real (&F)[L + 1]) {
+    if constexpr (sizeof(Real) == 8)
+        boys_f64<L>(T, bt.tab, bt.etab, F);
+    else
+        boys_f32<L>(T, bt, F);
+}
+
+template <typename Real> struct PrimPairOf;
+template <> struct PrimPairOf<double> { using type = PrimPair; };
+template <> struct PrimPairOf<float> { using type = PrimPairF; };
+template <typename Real> using PrimPairT = typename PrimPairOf<Real>::type;
+
 // ------------------------------------------------------------ class dims
 
 template <int LA_, int LB_, int LC_, int LD_>
@@ -94,33 +149,31 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // AC = A - C (bra and ket anchor centres); P - Q = AC + PA - QC is exact
 // zero when all four shells share one atom.
-template <class Dm>
-__device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPair &Q,
-                                                 const double (&AC)[3],
-                                                 const double *__restrict__ tab,
-                                                 const double *__restrict__ etab,
-                                                 double (&acc)[Dm::NFA][Dm::NEA]) {
+template <class Dm, typename Real>
+__device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
+                                             const Real (&AC)[3], const BoysTabs &bt,
+                                             Real (&acc)[Dm::NFA][Dm::NEA]) {
     constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LCD = Dm::LCD;
-    const double p = P.p, q = Q.p;
-    const double pq = p + q;
-    const double rpq = 1.0 / pq;
-    const double rho = p * q * rpq;
-    const double PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
-    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const Real p = P.p, q = Q.p;
+    const Real pq = p + q;
+    const Real rpq = Real(1) / pq;
+    const Real rho = p * q * rpq;
+    const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
+    const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
     // 2 pi^{5/2} = 34.986836655249725
-    const double pref = 34.986836655249725 / (p * q * sqrt(pq)) * P.K * Q.K;
+    const Real pref = Real(34.986836655249725) / (p * q * sqrt(pq)) * P.K * Q.K;
 
-    double F[L + 1];
-    boys_f64<L>(T, tab, etab, F);
+    Real F[L + 1];
+    boys_eval<L, Real>(T, bt, F);
 
-    double V[NF][NE][L + 1];
+    Real V[NF][NE][L + 1];
     static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pref * F[decltype(M)::value]; });
 
     if constexpr (Dm::LAB > 0) {
-        const double PA[3] = {P.PAx, P.PAy, P.PAz};
+        const Real PA[3] = {P.PAx, P.PAy, P.PAz};
         // W - P = q/(p+q) (Q - P)
-        const double WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
-        const double oo2p = 0.5 / p, rho_p = rho / p;
+        const Real WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
+        const Real oo2p = Real(0.5) / p, rho_p = rho / p;
         static_for<1, NE>([&](auto EI) {
             constexpr int e = decltype(EI)::value;
             constexpr Cart c = cart_of(e);
@@ -129,20 +182,20 @@ __device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPa
             constexpr int e1 = c.minus(i).idx();
             static_for<0, L - c.l() + 1>([&](auto MI) {
                 constexpr int m = decltype(MI)::value;
-                double v = PA[i] * V[0][e1][m] + WP[i] * V[0][e1][m + 1];
+                Real v = PA[i] * V[0][e1][m] + WP[i] * V[0][e1][m + 1];
                 if constexpr (ei >= 2) {
                     constexpr int e2 = c.minus(i, 2).idx();
-                    v += (ei - 1) * oo2p * (V[0][e2][m] - rho_p * V[0][e2][m + 1]);
+                    v += Real(ei - 1) * oo2p * (V[0][e2][m] - rho_p * V[0][e2][m + 1]);
                 }
                 V[0][e][m] = v;
             });
         });
     }
     if constexpr (LCD > 0) {
-        const double QC[3] = {Q.PAx, Q.PAy, Q.PAz};
+        const Real QC[3] = {Q.PAx, Q.PAy, Q.PAz};
         // W - Q = p/(p+q) (P - Q)
-        const double WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
-        const double oo2q = 0.5 / q, rho_q = rho / q, oo2pq = 0.5 * rpq;
+        const Real WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
+        const Real oo2q = Real(0.5) / q, rho_q = rho / q, oo2pq = Real(0.5) * rpq;
         static_for<1, NF>([&](auto FI) {
             constexpr int f = decltype(FI)::value;
             constexpr Cart cf = cart_of(f);
@@ -157,14 +210,14 @@ __device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPa
                 constexpr int ej = ce.get(j);
                 static_for<0, L - ce.l() - nf + 1>([&](auto MI) {
                     constexpr int m = decltype(MI)::value;
-                    double v = QC[j] * V[f1][e][m] + WQ[j] * V[f1][e][m + 1];
+                    Real v = QC[j] * V[f1][e][m] + WQ[j] * V[f1][e][m + 1];
                     if constexpr (fj >= 2) {
                         constexpr int f2 = cf.minus(j, 2).idx();
-                        v += (fj - 1) * oo2q * (V[f2][e][m] - rho_q * V[f2][e][m + 1]);
+                        v += Real(fj - 1) * oo2q * (V[f2][e][m] - rho_q * V[f2][e][m + 1]);
                     }
                     if constexpr (ej >= 1) {
                         constexpr int e1 = ce.minus(j).idx();
-                        v += ej * oo2pq * V[f1][e1][m + 1];
+                        v += Real(ej) * oo2pq * V[f1][e1][m + 1];
                     }
                     V[f][e][m] = v;
                 });
@@ -180,20 +233,29 @@ __device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPa
     });
 }
 
+// FP64 form used by the existing call sites.
+template <class Dm>
+__device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPair &Q, const double (&AC)[3],
+                                                 const double *__restrict__ tab, const double *__restrict__ etab,
+                                                 double (&acc)[Dm::NFA][Dm::NEA]) {
+    const BoysTabs bt{tab, etab, nullptr, nullptr};
+    prim_quartet<Dm, double>(P, Q, AC, bt, acc);
+}
+
 // --------------------------------------------------------------- HRR
 //
 // (a, b+1_i| = (a+1_i, b| + AB_i (a, b|, applied to contracted integrals.
 // X[e - off(la)] for la <= |e| <= la+lb  ->  Y[a][b], |a| = la, |b| = lb.
 
-template <int LA, int LB>
-__device__ __forceinline__ void hrr_1(const double (&X)[cart_off(LA + LB + 1) - cart_off(LA)],
-                                      const double AB[3], double (&Y)[ncart(LA) * ncart(LB)]) {
+template <int LA, int LB, typename Real>
+__device__ __forceinline__ void hrr_1(const Real (&X)[cart_off(LA + LB + 1) - cart_off(LA)],
+                                      const Real AB[3], Real (&Y)[ncart(LA) * ncart(LB)]) {
     constexpr int LAB = LA + LB;
     constexpr int E0 = cart_off(LA), NE = cart_off(LAB + 1);
     if constexpr (LB == 0) {
         static_for<0, ncart(LA)>([&](auto I) { Y[decltype(I)::value] = X[decltype(I)::value]; });
     } else {
-        double T[cart_off(LB + 1)][NE];
+        Real T[cart_off(LB + 1)][NE];
         static_for<E0, NE>([&](auto EI) {
             constexpr int e = decltype(EI)::value;
             T[0][e] = X[e - E0];
@@ -230,39 +292,37 @@ __device__ constexpr double comp_scale(int local) {
 // components a, b, c, d of the bra pair's shells (sa, sb) and the ket
 // pair's shells (sc, sd).
 
-template <class Dm>
-__device__ __forceinline__ void eri_quartet_f64(const PairInfo &bra, const PairInfo &ket,
-                                                const PrimPair *__restrict__ pp,
-                                                const double *__restrict__ tab,
-                                                const double *__restrict__ etab,
-                                                double (&out)[Dm::NOUT]) {
-    double acc[Dm::NFA][Dm::NEA];
+template <class Dm, typename Real>
+__device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo &ket,
+                                            const PrimPairT<Real> *__restrict__ pp, const BoysTabs &bt,
+                                            Real (&out)[Dm::NOUT]) {
+    Real acc[Dm::NFA][Dm::NEA];
     static_for<0, Dm::NFA>([&](auto F) {
-        static_for<0, Dm::NEA>([&](auto E) { acc[decltype(F)::value][decltype(E)::value] = 0.0; });
+        static_for<0, Dm::NEA>([&](auto E) { acc[decltype(F)::value][decltype(E)::value] = Real(0); });
     });
-    const double AC[3] = {bra.Ax - ket.Ax, bra.Ay - ket.Ay, bra.Az - ket.Az};
+    const Real AC[3] = {Real(bra.Ax - ket.Ax), Real(bra.Ay - ket.Ay), Real(bra.Az - ket.Az)};
     for (int ib = 0; ib < bra.npp; ++ib) {
-        const PrimPair P = pp[bra.pp0 + ib];
+        const PrimPairT<Real> P = pp[bra.pp0 + ib];
         for (int ik = 0; ik < ket.npp; ++ik) {
-            const PrimPair Q = pp[ket.pp0 + ik];
-            prim_quartet_f64<Dm>(P, Q, AC, tab, etab, acc);
+            const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+            prim_quartet<Dm, Real>(P, Q, AC, bt, acc);
         }
     }
     // bra HRR for every ket index f
-    const double AB[3] = {bra.ABx, bra.ABy, bra.ABz};
-    const double CD[3] = {ket.ABx, ket.ABy, ket.ABz};
-    double Y[Dm::NFA][Dm::NAB];
+    const Real AB[3] = {Real(bra.ABx), Real(bra.ABy), Real(bra.ABz)};
+    const Real CD[3] = {Real(ket.ABx), Real(ket.ABy), Real(ket.ABz)};
+    Real Y[Dm::NFA][Dm::NAB];
     static_for<0, Dm::NFA>([&](auto F) {
         constexpr int f = decltype(F)::value;
-        hrr_1<Dm::LA, Dm::LB>(acc[f], AB, Y[f]);
+        hrr_1<Dm::LA, Dm::LB, Real>(acc[f], AB, Y[f]);
     });
     // ket HRR for every bra (a, b)
     static_for<0, Dm::NAB>([&](auto AB_) {
         constexpr int ab = decltype(AB_)::value;
-        double Xk[Dm::NFA];
+        Real Xk[Dm::NFA];
         static_for<0, Dm::NFA>([&](auto F) { Xk[decltype(F)::value] = Y[decltype(F)::value][ab]; });
-        double Yk[Dm::NCD];
-        hrr_1<Dm::LC, Dm::LD>(Xk, CD, Yk);
+        Real Yk[Dm::NCD];
+        hrr_1<Dm::LC, Dm::LD, Real>(Xk, CD, Yk);
         constexpr int a = ab / Dm::NB, b = ab % Dm::NB;
         constexpr double sab = comp_scale<Dm::LA>(a) * comp_scale<Dm::LB>(b);
         static_for<0, Dm::NCD>([&](auto CD_) {
@@ -272,9 +332,17 @@ __device__ __forceinline__ void eri_quartet_f64(const PairInfo &bra, const PairI
             if constexpr (s == 1.0)
                 out[ab * Dm::NCD + cd] = Yk[cd];
             else
-                out[ab * Dm::NCD + cd] = Yk[cd] * s;
+                out[ab * Dm::NCD + cd] = Yk[cd] * Real(s);
         });
     });
+}
+
+template <class Dm>
+__device__ __forceinline__ void eri_quartet_f64(const PairInfo &bra, const PairInfo &ket,
+                                                const PrimPair *__restrict__ pp, const double *__restrict__ tab,
+                                                const double *__restrict__ etab, double (&out)[Dm::NOUT]) {
+    const BoysTabs bt{tab, etab, nullptr, nullptr};
+    eri_quartet<Dm, double>(bra, ket, pp, bt, out);
 }
 
 }  // namespace mess

@@ -41,14 +41,12 @@ __global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pai
 
 // Dense N^4 store: every unique quartet writes its block to all eight
 // index permutations.
-template <class Dm>
+template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra,
                                                    const int64_t *__restrict__ rowstart,
-                                                   const PrimPair *__restrict__ pp,
-                                                   const double *__restrict__ tab,
-                                                   const double *__restrict__ etab, int64_t N,
-                                                   double *__restrict__ eri) {
+                                                   const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
+                                                   int64_t N, double *__restrict__ eri) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -56,14 +54,14 @@ __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ 
         const int j = static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
-        double out[Dm::NOUT];
-        eri_quartet_f64<Dm>(bra, ket, pp, tab, etab, out);
+        Real out[Dm::NOUT];
+        eri_quartet<Dm, Real>(bra, ket, pp, bt, out);
         static_for<0, Dm::NOUT>([&](auto I) {
             constexpr int k = decltype(I)::value;
             constexpr int a = k / (Dm::NB * Dm::NCD), b = (k / Dm::NCD) % Dm::NB;
             constexpr int c = (k / Dm::ND) % Dm::NC, d = k % Dm::ND;
             const int64_t ia = bra.bfa + a, ib = bra.bfb + b, ic = ket.bfa + c, id = ket.bfb + d;
-            const double v = out[k];
+            const double v = (double)out[k];
             eri[((ia * N + ib) * N + ic) * N + id] = v;
             eri[((ib * N + ia) * N + ic) * N + id] = v;
             eri[((ia * N + ib) * N + id) * N + ic] = v;
@@ -82,68 +80,68 @@ __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ 
 //   Gk[a,c] += v' D[b,d]        Gk[b,c] += v' D[a,d]
 //   Gk[a,d] += v' D[b,c]        Gk[b,d] += v' D[a,c]
 // which is the sum of the eight permutation updates of (ab|cd).
-template <class Dm>
-__device__ __forceinline__ void digest_jk(const double (&out)[Dm::NOUT], double fac, int a0, int b0,
+// The partial sums run in the integrals' arithmetic (Real) and are added to
+// the FP64 half-matrices.
+template <class Dm, typename Real>
+__device__ __forceinline__ void digest_jk(const Real (&out)[Dm::NOUT], double fac, int a0, int b0,
                                           int c0, int d0, const double *__restrict__ D, int N,
                                           double *__restrict__ Gj, double *__restrict__ Gk) {
     constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND;
-    auto O = [&](int a, int b, int c, int d) -> double { return out[((a * NB + b) * NC + c) * ND + d]; };
-    auto Dv = [&](int r, int c) -> double { return D[(int64_t)r * N + c]; };
+    auto O = [&](int a, int b, int c, int d) -> Real { return out[((a * NB + b) * NC + c) * ND + d]; };
+    auto Dv = [&](int r, int c) -> Real { return Real(D[(int64_t)r * N + c]); };
     if (Gj) {
-        double Dcd[NC][ND], Dab[NA][NB];
+        Real Dcd[NC][ND], Dab[NA][NB];
         static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
             Dcd[C][Dd] = Dv(c0 + C, d0 + Dd); }); });
         static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
             Dab[A][B] = Dv(a0 + A, b0 + B); }); });
         static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
                 s += O(A, B, C, Dd) * Dcd[C][Dd]; }); });
-            unsafeAtomicAdd(&Gj[(int64_t)(a0 + A) * N + b0 + B], 2.0 * fac * s);
+            unsafeAtomicAdd(&Gj[(int64_t)(a0 + A) * N + b0 + B], 2.0 * fac * (double)s);
         }); });
         static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
                 s += O(A, B, C, Dd) * Dab[A][B]; }); });
-            unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * fac * s);
+            unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * fac * (double)s);
         }); });
     }
     if (Gk) {
-        double Dbd[NB][ND], Dad[NA][ND], Dbc[NB][NC], Dac[NA][NC];
+        Real Dbd[NB][ND], Dad[NA][ND], Dbc[NB][NC], Dac[NA][NC];
         static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { Dbd[B][Dd] = Dv(b0 + B, d0 + Dd); }); });
         static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { Dad[A][Dd] = Dv(a0 + A, d0 + Dd); }); });
         static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { Dbc[B][C] = Dv(b0 + B, c0 + C); }); });
         static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { Dac[A][C] = Dv(a0 + A, c0 + C); }); });
         static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dbd[B][Dd]; }); });
-            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + c0 + C], fac * s);
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + c0 + C], fac * (double)s);
         }); });
         static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dad[A][Dd]; }); });
-            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + c0 + C], fac * s);
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + c0 + C], fac * (double)s);
         }); });
         static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dbc[B][C]; }); });
-            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + d0 + Dd], fac * s);
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + A) * N + d0 + Dd], fac * (double)s);
         }); });
         static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) {
-            double s = 0.0;
+            Real s = Real(0);
             static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dac[A][C]; }); });
-            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + d0 + Dd], fac * s);
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + B) * N + d0 + Dd], fac * (double)s);
         }); });
     }
 }
 
-template <class Dm>
+template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra, int same_class,
                                                    const int64_t *__restrict__ rowstart,
-                                                   const PrimPair *__restrict__ pp,
-                                                   const double *__restrict__ tab,
-                                                   const double *__restrict__ etab,
+                                                   const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    const double *__restrict__ D, int N,
                                                    double *__restrict__ Gj, double *__restrict__ Gk) {
     const int64_t total = rowstart[nbra];
@@ -153,13 +151,13 @@ __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ 
         const int j = static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
-        double out[Dm::NOUT];
-        eri_quartet_f64<Dm>(bra, ket, pp, tab, etab, out);
+        Real out[Dm::NOUT];
+        eri_quartet<Dm, Real>(bra, ket, pp, bt, out);
         double fac = 1.0;
         if (bra.sa == bra.sb) fac *= 0.5;
         if (ket.sa == ket.sb) fac *= 0.5;
         if (same_class && i == j) fac *= 0.5;
-        digest_jk<Dm>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
+        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
     }
 }
 

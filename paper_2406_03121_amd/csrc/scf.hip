@@ -57,6 +57,7 @@ struct mess_scf {
     double *Bm = nullptr;                                // DIIS B matrix kMaxDiis^2
     mess::ScfScalars *sc = nullptr;
     double *partial = nullptr;                           // reduction partials
+    double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
     int sp2_iters_last = 0;
@@ -451,7 +452,7 @@ static int lowdin_newton_schulz(mess_scf *st, hipStream_t s, bool *ok) {
 static void free_scf(mess_scf *st) {
     if (!st) return;
     for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
-                      st->P2, st->Fh, st->Eh, st->Bm, st->partial})
+                      st->P2, st->Fh, st->Eh, st->Bm, st->partial, st->Dprev, st->dD, st->Gja, st->Gka})
         hipFree(p);
     hipFree(st->sc);
     delete st;
@@ -519,6 +520,9 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * nn * nd));
     MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * nn * nd));
     MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kMaxDiis * kMaxDiis));
+    if (st->opts.prec == MESS_FP32)
+        for (double **p : {&st->Dprev, &st->dD, &st->Gja, &st->Gka})
+            MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
     MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
     MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
     MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
@@ -559,10 +563,35 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     const int N = st->N, M = st->M;
     const int64_t nn = (int64_t)N * N, mm = (int64_t)M * M;
     // J, K half matrices
-    if (st->opts.jk_mode == MESS_JK_DIRECT)
+    if (st->opts.prec == MESS_FP32) {
+        // Incremental builds: a full FP64 build at the first iteration and
+        // every 8th, otherwise the FP32 build of dD = D_k - D_{k-1} added to
+        // the FP64 running half-matrices (an FP32 error in a full build would
+        // enter the converged energy at first order; in dD it vanishes as the
+        // iteration converges).
+        const bool full = (st->iter % 8) == 0;
+        if (full) {
+            if (st->opts.jk_mode == MESS_JK_DIRECT)
+                MESS_TRY(jk_direct_half(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
+            else
+                MESS_TRY(jk_stored(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
+        } else {
+            MESS_TRY(axpby(s, nn, 1.0, st->D, -1.0, st->Dprev, st->dD));
+            if (st->opts.jk_mode == MESS_JK_DIRECT)
+                MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, MESS_FP32, st->opts.schwarz_tol, s));
+            else
+                MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, MESS_FP32, st->opts.schwarz_tol, s));
+            MESS_TRY(axpby(s, nn, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
+            MESS_TRY(axpby(s, nn, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
+        }
+        MESS_HIP(hipMemcpyAsync(st->Dprev, st->D, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        MESS_HIP(hipMemcpyAsync(st->Gj, st->Gja, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        MESS_HIP(hipMemcpyAsync(st->Gk, st->Gka, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+    } else if (st->opts.jk_mode == MESS_JK_DIRECT) {
         MESS_TRY(jk_direct_half(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
-    else
+    } else {
         MESS_TRY(jk_stored(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+    }
     hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, st->D, st->F, st->partial);
     hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc, st->sc);
     MESS_LAUNCH_CHECK();
