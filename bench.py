@@ -47,9 +47,9 @@ def make_workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
-def scf_once(mess, mol, tau, conv_tol, max_iter=100, verbose=True):
+def scf_once(mess, mol, tau, conv_tol, max_iter=100, verbose=True, prec=0, jk_mode=0):
     B = mess.basis_from_molecule(mol)
-    st = mess.mess_scf_create(B, schwarz_tol=tau, conv_tol=conv_tol, diis_size=8)
+    st = mess.mess_scf_create(B, schwarz_tol=tau, conv_tol=conv_tol, diis_size=8, prec=prec, jk_mode=jk_mode)
     e, it, conv = 0.0, 0, False
     for it in range(1, max_iter + 1):
         e, de, resid, conv = mess.mess_scf_step(st)
@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--conv", type=float, default=1e-8)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-J/K comparison")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -176,6 +178,53 @@ def main():
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None},
         "cpu_baseline": None,
     }
+    golden = os.path.join(ROOT, "tests", "golden", f"{mol.name.replace('/', '_')}_rhf.json")
+    if os.path.exists(golden):
+        ref = json.load(open(golden))["energy"]
+        line["delta_e_vs_oracle_hartree"] = energies[-1] - ref
+    if not a.no_fp32:
+        # same molecule, mixed precision (FP32 dD builds), timed separately
+        scf_once(mess, mol, a.tau, a.conv, verbose=False, prec=mess.MESS_FP32)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r32 = [scf_once(mess, mol, a.tau, a.conv, verbose=False, prec=mess.MESS_FP32) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        fp32 = {"ms_per_step": (t3 - t2) / a.steps * 1e3, "molecules_per_s": a.steps / (t3 - t2),
+                "scf_iterations": r32[-1][1], "energy_hartree": r32[-1][0],
+                "delta_e_vs_fp64_hartree": r32[-1][0] - energies[-1]}
+        fp32["speedup_vs_fp64"] = fp32["molecules_per_s"] / line["molecules_per_s"]
+        if "delta_e_vs_oracle_hartree" in line:
+            fp32["delta_e_vs_oracle_hartree"] = r32[-1][0] - ref
+        line["fp32_mixed"] = fp32
+        log(f"fp32: {fp32}")
+    if not a.no_stored:
+        # same molecule, stored J/K: blocks computed once per SCF (first
+        # Fock build), streamed from HBM by the later builds
+        scf_once(mess, mol, a.tau, a.conv, verbose=False, jk_mode=mess.MESS_JK_STORED)
+        torch.cuda.synchronize()
+        mess.mess_prof_enable(True)
+        t4 = time.perf_counter()
+        rst = [scf_once(mess, mol, a.tau, a.conv, verbose=False, jk_mode=mess.MESS_JK_STORED)
+               for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        sb, sms = 0.0, 0.0
+        for c in range(21):
+            r = mess.mess_prof_read(32 + c)
+            sb += r["alg_flops"]
+            sms += r["ms"]
+        mess.mess_prof_enable(False)
+        stored = {"ms_per_step": (t5 - t4) / a.steps * 1e3, "molecules_per_s": a.steps / (t5 - t4),
+                  "scf_iterations": rst[-1][1], "energy_hartree": rst[-1][0],
+                  "delta_e_vs_direct_hartree": rst[-1][0] - energies[-1],
+                  "jk_stream_bytes_per_build": sb / max(1, a.steps * (rst[-1][1] - 1)),
+                  "jk_stream_ms_per_build": sms / max(1, a.steps * (rst[-1][1] - 1)),
+                  "jk_gbps": sb / (sms * 1e-3) / 1e9 if sms > 0 else None,
+                  "speedup_vs_direct": (a.steps / (t5 - t4)) / line["molecules_per_s"]}
+        line["stored_jk"] = stored
+        line["jk_gbps"] = stored["jk_gbps"]
+        log(f"stored: {stored}")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a quartet sample")
         line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)

@@ -66,8 +66,9 @@ typedef struct mess_scf_opts {
     int32_t max_iter;    /* informational for callers driving mess_scf_step */
     int32_t diis_size;   /* Pulay DIIS history length; 0 = plain Roothaan iteration */
     int32_t prec;        /* MESS_FP64, or MESS_FP32: Fock builds of the density change
-                            dD = D_k - D_{k-1} in FP32 arithmetic added to FP64 J/K, with a
-                            full FP64 build at the first iteration and every 8th */
+                            dD = D_k - D_{k-1} added to FP64 J/K, in FP32 arithmetic once the
+                            previous |dE| < 1e-3 Ha (FP64 before); full FP64 build at the
+                            first iteration and every 8th */
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
     int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X */
     int32_t reserved;

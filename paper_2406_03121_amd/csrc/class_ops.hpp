@@ -28,6 +28,11 @@ struct ClassOps {
     static int dense(const ClassLaunch &L, double *eri, int prec);
     // Gj, Gk half-matrices (either may be NULL) from density D.
     static int jk(const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec);
+    // Unique blocks of every quartet into base (FP64 or FP32 by prec),
+    // element k of quartet t at base[k * total + t].
+    static int store(const ClassLaunch &L, void *base, int prec);
+    // Gj, Gk from the stored blocks.
+    static int jk_stored(const ClassLaunch &L, const void *base, int prec, const double *D, double *Gj, double *Gk);
 };
 
 // Calls f(integral_constant<CB>, integral_constant<CK>) for a runtime

@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(64) k_coop(CoopArgs A, int region, const PairI
             }
         }
         __syncthreads();
-        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
+        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);
         __syncthreads();  // H reused by the next quartet
     }
 }
@@ -509,6 +509,8 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     switch (mode) {
         case kModeSchwarz: MESS_COOP_M(kModeSchwarz); break;
         case kModeDense: MESS_COOP_M(kModeDense); break;
+        case kModeStore64: MESS_COOP_M(kModeStore64); break;
+        case kModeStore32: MESS_COOP_M(kModeStore32); break;
         default: MESS_COOP_M(kModeJK);
     }
 #undef MESS_COOP_M
@@ -534,6 +536,60 @@ int coop_jk(int cb, int ck, const ClassLaunch &L, const double *D, double *Gj, d
 
 }  // namespace mess
 
+namespace mess {
+
+// J/K from stored blocks for the high classes: one wave per quartet, lanes
+// over the six digestion families, block elements read from the class's
+// structure-of-arrays store.
+template <typename Real>
+__global__ void __launch_bounds__(64) k_jk_stored_wave(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                      int nbra, int same_class, const int64_t *__restrict__ rowstart,
+                                                      int64_t total, int NA, int NB, int NC, int ND,
+                                                      const Real *__restrict__ base, const double *__restrict__ D, int N,
+                                                      double *__restrict__ Gj, double *__restrict__ Gk) {
+    const int lane = threadIdx.x;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        const int i = find_row(rowstart, nbra, q);
+        const int j = (int)(q - rowstart[i]);
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[ket_off + j];
+        double fac = 1.0;
+        if (bra.sa == bra.sb) fac *= 0.5;
+        if (ket.sa == ket.sb) fac *= 0.5;
+        if (same_class && i == j) fac *= 0.5;
+        auto O = [&](int a, int b, int cc, int d) {
+            return (double)base[(int64_t)(((a * NB + b) * NC + cc) * ND + d) * total + q];
+        };
+        wave_digest(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D, N, Gj, Gk);
+    }
+}
+
+int coop_store(int cb, int ck, const ClassLaunch &L, void *base, int prec) {
+    return coop_launch(prec == MESS_FP32 ? kModeStore32 : kModeStore64, cb, ck, L, L.total,
+                       static_cast<double *>(base), nullptr, nullptr, prec);
+}
+
+int coop_jk_stored(int cb, int ck, const ClassLaunch &L, const void *base, int prec, const double *D, double *Gj,
+                   double *Gk) {
+    if (L.total <= 0) return MESS_OK;
+    int64_t g = L.total;
+    if (g > (1 << 20)) g = 1 << 20;
+    const int NA = ncart(pair_class_la(cb)), NB = ncart(pair_class_lb(cb)), NC = ncart(pair_class_la(ck)),
+              ND = ncart(pair_class_lb(ck));
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL(k_jk_stored_wave<float>, dim3((unsigned)g), dim3(64), 0, L.stream, L.pairs, L.bra_off,
+                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.total, NA, NB, NC, ND,
+                           static_cast<const float *>(base), D, L.N, Gj, Gk);
+    else
+        hipLaunchKernelGGL(k_jk_stored_wave<double>, dim3((unsigned)g), dim3(64), 0, L.stream, L.pairs, L.bra_off,
+                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.total, NA, NB, NC, ND,
+                           static_cast<const double *>(base), D, L.N, Gj, Gk);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+}  // namespace mess
+
 // The high classes are reached through the same ClassOps interface as the
 // unrolled ones; eri_class.hip is not compiled for them.
 namespace mess {
@@ -553,6 +609,15 @@ namespace mess {
     template <>                                                                                        \
     int ClassOps<B, K>::jk(const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec) {  \
         return coop_jk(B, K, L, D, Gj, Gk, prec);                                                      \
+    }                                                                                                  \
+    template <>                                                                                        \
+    int ClassOps<B, K>::store(const ClassLaunch &L, void *base, int prec) {                            \
+        return coop_store(B, K, L, base, prec);                                                        \
+    }                                                                                                  \
+    template <>                                                                                        \
+    int ClassOps<B, K>::jk_stored(const ClassLaunch &L, const void *base, int prec, const double *D,   \
+                                  double *Gj, double *Gk) {                                            \
+        return coop_jk_stored(B, K, L, base, prec, D, Gj, Gk);                                         \
     }
 MESS_COOP_CLASS(4, 2)
 MESS_COOP_CLASS(4, 4)

@@ -35,7 +35,7 @@ struct CoopArgs {
     int NA, NB, NC, ND;
 };
 
-enum { kModeSchwarz = 0, kModeDense = 1, kModeJK = 2 };
+enum { kModeSchwarz = 0, kModeDense = 1, kModeJK = 2, kModeStore64 = 3, kModeStore32 = 4 };
 
 __device__ __forceinline__ double coop_boys(int m, double T, const double *__restrict__ tab) {
     // F_m(T), m <= 8, directly (no recurrence): Taylor about the nearest grid
@@ -70,6 +70,71 @@ __device__ __forceinline__ double run_op(const int4 op, const double *__restrict
     return v;
 }
 
+// J/K digestion of one quartet's block by a wave: lanes over the elements of
+// the six target families Gj[a,b], Gj[c,d], Gk[a,c], Gk[b,c], Gk[a,d],
+// Gk[b,d] (each a sum over the block weighted by density elements).
+template <typename OF>
+__device__ __forceinline__ void wave_digest(const int lane, const int NA, const int NB, const int NC, const int ND,
+                                            const double fac, const int a0, const int b0, const int c0, const int d0,
+                                            OF &&O, const double *__restrict__ D, const int N,
+                                            double *__restrict__ Gj, double *__restrict__ Gk) {
+    auto Dv = [&](int r, int cidx) { return D[(int64_t)r * N + cidx]; };
+    const int nab = NA * NB, ncd = NC * ND;
+    const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
+    const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0, t_bd = Gk ? NB * ND : 0;
+    const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
+    for (int t = lane; t < ntgt; t += 64) {
+        int r = t;
+        double s = 0.0;
+        if (r < t_ab) {
+            const int a = r / NB, b = r % NB;
+            for (int cc = 0; cc < NC; ++cc)
+                for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(c0 + cc, d0 + d);
+            unsafeAtomicAdd(&Gj[(int64_t)(a0 + a) * N + b0 + b], 2.0 * fac * s);
+            continue;
+        }
+        r -= t_ab;
+        if (r < t_cd) {
+            const int cc = r / ND, d = r % ND;
+            for (int a = 0; a < NA; ++a)
+                for (int b = 0; b < NB; ++b) s += O(a, b, cc, d) * Dv(a0 + a, b0 + b);
+            unsafeAtomicAdd(&Gj[(int64_t)(c0 + cc) * N + d0 + d], 2.0 * fac * s);
+            continue;
+        }
+        r -= t_cd;
+        if (r < t_ac) {
+            const int a = r / NC, cc = r % NC;
+            for (int b = 0; b < NB; ++b)
+                for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(b0 + b, d0 + d);
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + c0 + cc], fac * s);
+            continue;
+        }
+        r -= t_ac;
+        if (r < t_bc) {
+            const int b = r / NC, cc = r % NC;
+            for (int a = 0; a < NA; ++a)
+                for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(a0 + a, d0 + d);
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + c0 + cc], fac * s);
+            continue;
+        }
+        r -= t_bc;
+        if (r < t_ad) {
+            const int a = r / ND, d = r % ND;
+            for (int b = 0; b < NB; ++b)
+                for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(b0 + b, c0 + cc);
+            unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + d0 + d], fac * s);
+            continue;
+        }
+        r -= t_ad;
+        {
+            const int b = r / ND, d = r % ND;
+            for (int a = 0; a < NA; ++a)
+                for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(a0 + a, c0 + cc);
+            unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + d0 + d], fac * s);
+        }
+    }
+}
+
 // Horizontal recursion of the accumulated [e0|f0] (in H[0, nacc)) and the
 // per-mode output of one quartet, shared by the wave.
 template <int MODE>
@@ -77,7 +142,7 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
                                             const int lane, const PairInfo &bra, const PairInfo &ket, const int i,
                                             const int j, const int bra_off, const int same_class,
                                             const double *__restrict__ D, const int N, double *__restrict__ out0,
-                                            double *__restrict__ out1) {
+                                            double *__restrict__ out1, const int64_t q = 0, const int64_t total = 0) {
         if (lane == 0) {
             hc[kH0] = 0.0; hc[kH1] = 1.0;
             hc[kHAB + 0] = bra.ABx; hc[kHAB + 1] = bra.ABy; hc[kHAB + 2] = bra.ABz;
@@ -105,6 +170,12 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
                     for (int b = 0; b < NB; ++b) m = fmax(m, fabs(O(a, b, a, b)));
                 out0[bra_off + i] = sqrt(m);
             }
+        } else if (MODE == kModeStore64 || MODE == kModeStore32) {
+            for (int o = lane; o < A.nout; o += 64) {
+                const double v = H[A.outslot[o]] * A.outscale[o];
+                if (MODE == kModeStore64) out0[(int64_t)o * total + q] = v;
+                else reinterpret_cast<float *>(out0)[(int64_t)o * total + q] = (float)v;
+            }
         } else if (MODE == kModeDense) {
             const int64_t NN = N;
             for (int o = lane; o < A.nout; o += 64) {
@@ -125,65 +196,7 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
             if (bra.sa == bra.sb) fac *= 0.5;
             if (ket.sa == ket.sb) fac *= 0.5;
             if (same_class && i == j) fac *= 0.5;
-            const int a0 = bra.bfa, b0 = bra.bfb, c0 = ket.bfa, d0 = ket.bfb;
-            auto Dv = [&](int r, int cidx) { return D[(int64_t)r * N + cidx]; };
-            double *Gj = out0, *Gk = out1;
-            const int nab = NA * NB, ncd = NC * ND;
-            // six target families, lanes over their elements
-            const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
-            const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0,
-                      t_bd = Gk ? NB * ND : 0;
-            const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
-            for (int t = lane; t < ntgt; t += 64) {
-                int r = t;
-                double s = 0.0;
-                if (r < t_ab) {
-                    const int a = r / NB, b = r % NB;
-                    for (int cc = 0; cc < NC; ++cc)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(c0 + cc, d0 + d);
-                    unsafeAtomicAdd(&Gj[(int64_t)(a0 + a) * N + b0 + b], 2.0 * fac * s);
-                    continue;
-                }
-                r -= t_ab;
-                if (r < t_cd) {
-                    const int cc = r / ND, d = r % ND;
-                    for (int a = 0; a < NA; ++a)
-                        for (int b = 0; b < NB; ++b) s += O(a, b, cc, d) * Dv(a0 + a, b0 + b);
-                    unsafeAtomicAdd(&Gj[(int64_t)(c0 + cc) * N + d0 + d], 2.0 * fac * s);
-                    continue;
-                }
-                r -= t_cd;
-                if (r < t_ac) {
-                    const int a = r / NC, cc = r % NC;
-                    for (int b = 0; b < NB; ++b)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(b0 + b, d0 + d);
-                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + c0 + cc], fac * s);
-                    continue;
-                }
-                r -= t_ac;
-                if (r < t_bc) {
-                    const int b = r / NC, cc = r % NC;
-                    for (int a = 0; a < NA; ++a)
-                        for (int d = 0; d < ND; ++d) s += O(a, b, cc, d) * Dv(a0 + a, d0 + d);
-                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + c0 + cc], fac * s);
-                    continue;
-                }
-                r -= t_bc;
-                if (r < t_ad) {
-                    const int a = r / ND, d = r % ND;
-                    for (int b = 0; b < NB; ++b)
-                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(b0 + b, c0 + cc);
-                    unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + d0 + d], fac * s);
-                    continue;
-                }
-                r -= t_ad;
-                {
-                    const int b = r / ND, d = r % ND;
-                    for (int a = 0; a < NA; ++a)
-                        for (int cc = 0; cc < NC; ++cc) s += O(a, b, cc, d) * Dv(a0 + a, c0 + cc);
-                    unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + d0 + d], fac * s);
-                }
-            }
+            wave_digest(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D, N, out0, out1);
         }
 }
 

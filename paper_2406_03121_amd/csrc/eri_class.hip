@@ -67,4 +67,36 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
     return MESS_OK;
 }
 
+template <>
+int ClassOps<MESS_CB, MESS_CK>::store(const ClassLaunch &L, void *base, int prec) {
+    using Dm = ClassOf<MESS_CB, MESS_CK>;
+    if (L.total <= 0) return MESS_OK;
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL((k_eri_store<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.ppf, bt, static_cast<float *>(base));
+    else
+        hipLaunchKernelGGL((k_eri_store<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.pp, bt, static_cast<double *>(base));
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+template <>
+int ClassOps<MESS_CB, MESS_CK>::jk_stored(const ClassLaunch &L, const void *base, int prec, const double *D,
+                                          double *Gj, double *Gk) {
+    using Dm = ClassOf<MESS_CB, MESS_CK>;
+    if (L.total <= 0) return MESS_OK;
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL((k_jk_stored<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, static_cast<const float *>(base),
+                           D, L.N, Gj, Gk);
+    else
+        hipLaunchKernelGGL((k_jk_stored<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
+                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, static_cast<const double *>(base),
+                           D, L.N, Gj, Gk);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
 }  // namespace mess

@@ -74,6 +74,26 @@ __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ 
     }
 }
 
+// Stored layout of one class: element k of quartet t at base[k * nq + t]
+// (structure of arrays, so that consecutive lanes touch consecutive words).
+template <class Dm, typename Real>
+__global__ void __launch_bounds__(128) k_eri_store(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                   int nbra, const int64_t *__restrict__ rowstart,
+                                                   const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
+                                                   Real *__restrict__ base) {
+    const int64_t total = rowstart[nbra];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = find_row(rowstart, nbra, t);
+        const int j = static_cast<int>(t - rowstart[i]);
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[ket_off + j];
+        Real out[Dm::NOUT];
+        eri_quartet<Dm, Real>(bra, ket, pp, bt, out);
+        static_for<0, Dm::NOUT>([&](auto I) { base[(int64_t)decltype(I)::value * total + t] = out[I]; });
+    }
+}
+
 // Digest one unique quartet block into the half-matrices Gj, Gk
 // (J = Gj + Gj^T, K = Gk + Gk^T).  With v' = v / ((1+d_ab)(1+d_cd)(1+d_ab,cd)):
 //   Gj[a,b] += 2 v' D[c,d]      Gj[c,d] += 2 v' D[a,b]
@@ -153,6 +173,29 @@ __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ 
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
         eri_quartet<Dm, Real>(bra, ket, pp, bt, out);
+        double fac = 1.0;
+        if (bra.sa == bra.sb) fac *= 0.5;
+        if (ket.sa == ket.sb) fac *= 0.5;
+        if (same_class && i == j) fac *= 0.5;
+        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
+    }
+}
+
+// J/K from stored blocks: one lane per quartet streams its NOUT values.
+template <class Dm, typename Real>
+__global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                   int nbra, int same_class, const int64_t *__restrict__ rowstart,
+                                                   const Real *__restrict__ base, const double *__restrict__ D,
+                                                   int N, double *__restrict__ Gj, double *__restrict__ Gk) {
+    const int64_t total = rowstart[nbra];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = find_row(rowstart, nbra, t);
+        const int j = static_cast<int>(t - rowstart[i]);
+        const PairInfo bra = pairs[bra_off + i];
+        const PairInfo ket = pairs[ket_off + j];
+        Real out[Dm::NOUT];
+        static_for<0, Dm::NOUT>([&](auto I) { out[I] = base[(int64_t)decltype(I)::value * total + t]; });
         double fac = 1.0;
         if (bra.sa == bra.sb) fac *= 0.5;
         if (ket.sa == ket.sb) fac *= 0.5;

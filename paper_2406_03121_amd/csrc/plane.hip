@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
             if (idx < NACC) H[idx] = (double)part[I];
         });
         __syncthreads();
-        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1);
+        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);
         __syncthreads();
     }
 }
@@ -111,6 +111,14 @@ void PlaneOps<MESS_PCB, MESS_PCK, MESS_PREAL>::launch(int mode, const CoopArgs &
             break;
         case kModeDense:
             hipLaunchKernelGGL((k_plane<Dm, kModeDense, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, pp, bt, D, L.N, out0, out1);
+            break;
+        case kModeStore64:
+            hipLaunchKernelGGL((k_plane<Dm, kModeStore64, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, total, pp, bt, D, L.N, out0, out1);
+            break;
+        case kModeStore32:
+            hipLaunchKernelGGL((k_plane<Dm, kModeStore32, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
                                L.ket_off, L.nbra, L.same_class, L.rowstart, total, pp, bt, D, L.N, out0, out1);
             break;
         default:

@@ -58,6 +58,7 @@ struct mess_scf {
     mess::ScfScalars *sc = nullptr;
     double *partial = nullptr;                           // reduction partials
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
+    double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
     int sp2_iters_last = 0;
@@ -565,11 +566,14 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     // J, K half matrices
     if (st->opts.prec == MESS_FP32) {
         // Incremental builds: a full FP64 build at the first iteration and
-        // every 8th, otherwise the FP32 build of dD = D_k - D_{k-1} added to
-        // the FP64 running half-matrices (an FP32 error in a full build would
-        // enter the converged energy at first order; in dD it vanishes as the
-        // iteration converges).
+        // every 8th, otherwise the build of dD = D_k - D_{k-1} added to the
+        // FP64 running half-matrices.  The dD build runs in FP32 once the
+        // previous energy change is below 1e-3 Ha (its FP32 rounding then
+        // scales with a small change and stays far below 1e-6 Ha in E);
+        // earlier, larger changes are built in FP64, since an FP32 error in
+        // them would persist in the running Fock matrix.
         const bool full = (st->iter % 8) == 0;
+        const int dprec = st->last_de < 1e-3 ? MESS_FP32 : MESS_FP64;
         if (full) {
             if (st->opts.jk_mode == MESS_JK_DIRECT)
                 MESS_TRY(jk_direct_half(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
@@ -578,9 +582,9 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         } else {
             MESS_TRY(axpby(s, nn, 1.0, st->D, -1.0, st->Dprev, st->dD));
             if (st->opts.jk_mode == MESS_JK_DIRECT)
-                MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, MESS_FP32, st->opts.schwarz_tol, s));
+                MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, dprec, st->opts.schwarz_tol, s));
             else
-                MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, MESS_FP32, st->opts.schwarz_tol, s));
+                MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, dprec, st->opts.schwarz_tol, s));
             MESS_TRY(axpby(s, nn, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
             MESS_TRY(axpby(s, nn, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
         }
@@ -620,6 +624,7 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     if (resid) *resid = h.resid;
     if (converged) *converged = conv ? 1 : 0;
     st->e_prev = h.energy;
+    st->last_de = st->iter > 0 ? std::fabs(de) : 1e300;
     st->iter += 1;
     if (conv) return MESS_OK;  // D stays the density that gave E_k
     // DIIS

@@ -72,15 +72,20 @@ def test_eri_dense(case):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("tau", [0.0, 1e-10])
-def test_jk_direct(case, tau):
+@pytest.mark.parametrize("mode", ["direct", "stored"])
+def test_jk(case, tau, mode):
     mess = need_gpu()
     mol = CASES[case]()
-    announce(f"jk_direct {case} tau={tau} nbf={mol.n_bf}")
+    announce(f"jk {mode} {case} tau={tau} nbf={mol.n_bf}")
     B = mess.basis_from_molecule(mol)
     N = B.nbf
     D = random_density(N, seed=11)
     J, K = zeros(N, N), zeros(N, N)
-    mess.mess_jk(B, dev(D), J, K, mode=mess.MESS_JK_DIRECT, schwarz_tol=tau)
+    m = mess.MESS_JK_DIRECT if mode == "direct" else mess.MESS_JK_STORED
+    mess.mess_jk(B, dev(D), J, K, mode=m, schwarz_tol=tau)
+    if mode == "stored":  # second call streams the cached blocks
+        D = random_density(N, seed=12)
+        mess.mess_jk(B, dev(D), J, K, mode=m, schwarz_tol=tau)
     Jo, Ko, _ = core.jk_unique(mol, D, tau)
     assert _rel_err(host(J), Jo) < 1e-11
     assert _rel_err(host(K), Ko) < 1e-11

@@ -65,16 +65,18 @@ CONVERGE = {
 
 
 @pytest.mark.parametrize("case", list(CONVERGE))
-def test_converged_energy(case):
+@pytest.mark.parametrize("jk", ["direct", "stored"])
+def test_converged_energy(case, jk):
     mess = need_gpu()
     mol = CONVERGE[case]()
     if mol.n_bf > 60:
         pytest.skip("oracle dense tensor too large for this test")
-    announce(f"scf converge {case} nbf={mol.n_bf}")
+    announce(f"scf converge {case} jk={jk} nbf={mol.n_bf}")
     ref = oscf.RHF(mol, jk="dense", conv_tol=1e-10, max_iter=200).run()
     assert ref["converged"]
     B = mess.basis_from_molecule(mol)
-    st = mess.mess_scf_create(B, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8)
+    mode = mess.MESS_JK_DIRECT if jk == "direct" else mess.MESS_JK_STORED
+    st = mess.mess_scf_create(B, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8, jk_mode=mode)
     energies = []
     for _ in range(200):
         e, de, resid, conv = mess.mess_scf_step(st)
