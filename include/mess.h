@@ -43,6 +43,7 @@ extern "C" {
 
 typedef struct mess_basis mess_basis;
 typedef struct mess_scf mess_scf;
+typedef struct mess_batch_scf mess_batch_scf;
 typedef void *mess_stream;
 
 enum {
@@ -88,6 +89,34 @@ int mess_basis_create(int32_t n_atoms, const int32_t *Z, const double *xyz_bohr,
                       int32_t n_shells, const int32_t *shell_atom, const int32_t *shell_l,
                       const int32_t *shell_nprim, const double *exps, const double *coefs,
                       int32_t charge, mess_basis **out);
+
+/* A batch of independent molecules in one basis handle, so that the
+ * shell quartets of every molecule share one launch per angular class
+ * (the paper's batching of many small systems, section 5).  Molecules are
+ * given back to back: molecule m has mol_atoms[m] atoms and
+ * mol_shells[m] shells; Z, xyz_bohr, shell_atom, shell_l, shell_nprim,
+ * exps and coefs are the concatenation of the per-molecule arrays of
+ * mess_basis_create, with shell_atom indices local to each molecule.
+ * charges[n_mol] may be NULL (all neutral).  Host arrays, copied.
+ * Functions are numbered molecule by molecule.  Every matrix of a batch
+ * handle is PACKED BLOCK-DIAGONAL: molecule m's nbf_m x nbf_m row-major
+ * block at element offset moff[m] (mess_batch_info), total moff[n_mol]
+ * doubles; mess_one_electron and mess_jk read and write this layout.
+ * Quartets never couple two molecules.  mess_eri and mess_scf_create
+ * reject a batch of more than one molecule (MESS_E_UNSUPPORTED / _ARG).
+ * Errors: as mess_basis_create, and MESS_E_ARG if the per-molecule counts
+ * do not cover the arrays. */
+int mess_batch_create(int32_t n_mol, const int32_t *mol_atoms, const int32_t *mol_shells,
+                      const int32_t *charges, const int32_t *Z, const double *xyz_bohr,
+                      const int32_t *shell_atom, const int32_t *shell_l, const int32_t *shell_nprim,
+                      const double *exps, const double *coefs, mess_basis **out);
+
+/* Per-molecule layout of a basis handle (a single molecule is a batch of
+ * one): n_mol; nbf[n_mol]; moff[n_mol + 1] packed offsets; n_occ[n_mol];
+ * e_nuc[n_mol].  Host outputs, any may be NULL (arrays sized by the
+ * caller from a first call with only n_mol). */
+int mess_batch_info(const mess_basis *basis, int32_t *n_mol, int32_t *nbf, int64_t *moff,
+                    int32_t *n_occ, double *e_nuc);
 
 /* Frees every device allocation of the handle.  NULL is a no-op. */
 void mess_basis_destroy(mess_basis *basis);
@@ -153,6 +182,38 @@ int mess_scf_fock(const mess_scf *scf, double *F, mess_stream stream);
 
 /* NULL is a no-op. */
 void mess_scf_destroy(mess_scf *scf);
+
+/* Batched SCF over every molecule of a batch handle: the step of
+ * mess_scf_step applied to each molecule, with all molecules' ERI classes,
+ * Fock builds, DIIS and density purifications sharing launches.  FP64
+ * only (opts->prec must be MESS_FP64); X is the Loewdin S^{-1/2} of each
+ * molecule (MESS_E_NUMERIC if an overlap block may be near-singular).
+ * D0: device packed initial density, or NULL for the core-Hamiltonian
+ * guess.  use_graph != 0 captures the first step into a HIP graph and
+ * replays it on later steps (the caller's stream must not be capturing;
+ * class profiling must be off).  Builds the work lists (and, for
+ * MESS_JK_STORED, the stored integrals) before returning, so that a step
+ * allocates nothing.  Synchronous. */
+int mess_batch_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const double *D0,
+                          int32_t use_graph, mess_batch_scf **out);
+
+/* Enqueue one SCF iteration for every molecule on the stream; does not
+ * synchronise.  A molecule with k > 0 and |E_k - E_{k-1}| < conv_tol is
+ * frozen: its energy and density stay those of that step. */
+int mess_batch_scf_step(mess_batch_scf *scf, mess_stream stream);
+
+/* Synchronise and read per-molecule results of the last step (host arrays
+ * of n_mol, any may be NULL): energy, delta_e, resid, converged flag, and
+ * the number converged.  MESS_E_NUMERIC if an energy is not finite or a
+ * density purification did not finish. */
+int mess_batch_scf_status(const mess_batch_scf *scf, double *energy, double *delta_e, double *resid,
+                          int32_t *converged, int32_t *n_converged, mess_stream stream);
+
+/* Copy the current packed density into D (device). */
+int mess_batch_scf_density(const mess_batch_scf *scf, double *D, mess_stream stream);
+
+/* NULL is a no-op. */
+void mess_batch_scf_destroy(mess_batch_scf *scf);
 
 /* ---- Instrumentation (not part of the method; used by benchmarks). ----
  * Class index cls = cb (cb + 1) / 2 + ck for bra pair class cb >= ket pair

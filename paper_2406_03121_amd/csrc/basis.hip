@@ -79,12 +79,13 @@ static void normalise(const int l, const int np, const double *a, const double *
 struct ShellDev {
     double x, y, z;
     int prim0, nprim;
+    int bf0, moff, mN;  // first function within its molecule; packed block of the molecule
 };
 
 __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__restrict__ pp0,
-                              const ShellDev *__restrict__ sh, const int *__restrict__ bf0,
-                              const double *__restrict__ alpha, const double *__restrict__ ct,
-                              PairInfo *__restrict__ pairs, PrimPair *__restrict__ pp) {
+                              const ShellDev *__restrict__ sh, const double *__restrict__ alpha,
+                              const double *__restrict__ ct, PairInfo *__restrict__ pairs,
+                              PrimPair *__restrict__ pp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int sa = ab[i].x, sb = ab[i].y;
@@ -95,7 +96,8 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
     pi.pp0 = pp0[i];
     pi.npp = A.nprim * B.nprim;
     pi.sa = sa; pi.sb = sb;
-    pi.bfa = bf0[sa]; pi.bfb = bf0[sb];
+    pi.bfa = A.bf0; pi.bfb = B.bf0;
+    pi.moff = A.moff; pi.mN = A.mN;
     pairs[i] = pi;
     const double ab2 = pi.ABx * pi.ABx + pi.ABy * pi.ABy + pi.ABz * pi.ABz;
     int k = pi.pp0;
@@ -117,25 +119,20 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
     }
 }
 
-// Rank of each pair within its class by descending Q (ties by index);
-// perm[off + rank] = local index.
-__global__ void k_rank_desc(const double *__restrict__ Q, int off, int n, int *__restrict__ perm) {
-    __shared__ double tile[256];
+// Rank of each pair within its (class, molecule) segment by descending Q
+// (ties by index); perm[off + seg_lo + rank] = local index.
+__global__ void k_rank_desc(const double *__restrict__ Q, int off, int n, const int *__restrict__ seg_lo,
+                            const int *__restrict__ seg_hi, int *__restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const double qi = i < n ? Q[off + i] : 0.0;
+    if (i >= n) return;
+    const double qi = Q[off + i];
+    const int lo = seg_lo[off + i], hi = seg_hi[off + i];
     int rank = 0;
-    for (int j0 = 0; j0 < n; j0 += 256) {
-        const int j = j0 + threadIdx.x;
-        tile[threadIdx.x] = j < n ? Q[off + j] : 0.0;
-        __syncthreads();
-        const int m = min(256, n - j0);
-        for (int t = 0; t < m; ++t) {
-            const double qj = tile[t];
-            rank += (qj > qi) || (qj == qi && j0 + t < i);
-        }
-        __syncthreads();
+    for (int j = lo; j < hi; ++j) {
+        const double qj = Q[off + j];
+        rank += (qj > qi) || (qj == qi && j < i);
     }
-    if (i < n) perm[off + rank] = i;
+    perm[off + lo + rank] = i;
 }
 
 __global__ void k_gather_pairs(int off, int n, const int *__restrict__ perm,
@@ -148,23 +145,26 @@ __global__ void k_gather_pairs(int off, int n, const int *__restrict__ perm,
     Qdst[off + r] = Qsrc[off + i];
 }
 
-// Kets of bra row i: kets j (sorted descending) with Q_i Q_j >= tau; for a
-// same-class list only j <= i.
-__global__ void k_row_counts(const double *__restrict__ Q, int bra_off, int nbra, int ket_off,
-                             int nket, int same_class, double tau, int64_t *__restrict__ counts) {
+// Kets of bra row i: the kets of its molecule's segment [k0, k0 + nk)
+// (sorted descending) with Q_i Q_j >= tau; for a same-class list only kets
+// up to the bra itself.
+__global__ void k_row_counts(const double *__restrict__ Q, int bra_off, int nbra, int ket_off, int nket,
+                             const int *__restrict__ rowket0, const int *__restrict__ rownket, int same_class,
+                             double tau, int64_t *__restrict__ counts) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nbra) return;
-    int cnt = nket;
+    const int k0 = rowket0 ? rowket0[i] : 0, nk = rownket ? rownket[i] : nket;
+    int cnt = nk;
     if (tau > 0.0) {
         const double qi = Q[bra_off + i];
-        int lo = 0, hi = nket;  // first j with qi*Q_j < tau
+        int lo = 0, hi = nk;  // first j with qi*Q_j < tau
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (qi * Q[ket_off + mid] >= tau) lo = mid + 1; else hi = mid;
+            if (qi * Q[ket_off + k0 + mid] >= tau) lo = mid + 1; else hi = mid;
         }
         cnt = lo;
     }
-    if (same_class) cnt = min(cnt, i + 1);
+    if (same_class) cnt = min(cnt, i - k0 + 1);
     counts[i] = cnt;
 }
 
@@ -206,6 +206,7 @@ static int make_class_launch(const mess_basis *B, ClassLaunch &L, hipStream_t s)
     L.N = B->nbf;
     L.stream = s;
     L.rowstart = nullptr;
+    L.rowket0 = nullptr;
     L.total = 0;
     L.bra_off = L.ket_off = L.nbra = L.same_class = 0;
     return MESS_OK;
@@ -218,6 +219,7 @@ int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, C
     L.nbra = cl.nbra;
     L.same_class = cl.cb == cl.ck;
     L.rowstart = cl.d_rowstart;
+    L.rowket0 = cl.d_rowket0;
     L.total = cl.total;
     return MESS_OK;
 }
@@ -259,9 +261,32 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                 rc = MESS_E_NOMEM;
                 break;
             }
+            // per bra row: its molecule's ket segment
+            std::vector<int> rk0, rnk;
+            int *d_rnk = nullptr;
+            if (B->n_mol > 1) {
+                rk0.resize(cl.nbra);
+                rnk.resize(cl.nbra);
+                for (int m = 0; m < B->n_mol; ++m)
+                    for (int r = 0; r < B->seg_cnt[cb][m]; ++r) {
+                        rk0[B->seg_off[cb][m] + r] = B->seg_off[ck][m];
+                        rnk[B->seg_off[cb][m] + r] = B->seg_cnt[ck][m];
+                    }
+                if (hipMalloc(&cl.d_rowket0, sizeof(int) * cl.nbra) != hipSuccess ||
+                    hipMalloc(&d_rnk, sizeof(int) * cl.nbra) != hipSuccess ||
+                    hipMemcpy(cl.d_rowket0, rk0.data(), sizeof(int) * cl.nbra, hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(d_rnk, rnk.data(), sizeof(int) * cl.nbra, hipMemcpyHostToDevice) != hipSuccess) {
+                    hipFree(cl.d_rowstart);
+                    hipFree(cl.d_rowket0);
+                    hipFree(d_rnk);
+                    set_error("hipMalloc(work list) failed");
+                    rc = MESS_E_NOMEM;
+                    break;
+                }
+            }
             hipLaunchKernelGGL(k_row_counts, dim3((cl.nbra + 255) / 256), dim3(256), 0, s, B->d_pairQ,
-                               B->pair_class_off[cb], cl.nbra, B->pair_class_off[ck], nket, cb == ck ? 1 : 0,
-                               tau, d_counts);
+                               B->pair_class_off[cb], cl.nbra, B->pair_class_off[ck], nket, cl.d_rowket0, d_rnk,
+                               cb == ck ? 1 : 0, tau, d_counts);
             hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, d_counts, cl.nbra, cl.d_rowstart);
             cl.h_rowstart.resize(cl.nbra + 1);
             if (hipGetLastError() != hipSuccess ||
@@ -269,10 +294,13 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                                hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 hipFree(cl.d_rowstart);
+                hipFree(cl.d_rowket0);
+                hipFree(d_rnk);
                 set_error("work-list construction failed on the device");
                 rc = MESS_E_DEVICE;
                 break;
             }
+            hipFree(d_rnk);
             cl.total = cl.h_rowstart[cl.nbra];
             {
                 // primitive quartets: sum_i npp(bra_i) * sum_{j < count_i} npp(ket_j)
@@ -282,7 +310,8 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                 int64_t tot = 0;
                 for (int i = 0; i < cl.nbra; ++i) {
                     const int64_t cnt = cl.h_rowstart[i + 1] - cl.h_rowstart[i];
-                    tot += (int64_t)B->pairs_host[boff + i].npp * kpre[cnt];
+                    const int k0 = rk0.empty() ? 0 : rk0[i];
+                    tot += (int64_t)B->pairs_host[boff + i].npp * (kpre[k0 + cnt] - kpre[k0]);
                 }
                 cl.prim_quartets = tot;
             }
@@ -290,8 +319,10 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
         }
     hipFree(d_counts);
     if (rc != MESS_OK) {
-        for (auto &cl : W->classes)
+        for (auto &cl : W->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
+            if (cl.d_rowket0) hipFree(cl.d_rowket0);
+        }
         delete W;
         return rc;
     }
@@ -303,8 +334,10 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
 static void free_basis(mess_basis *B) {
     if (!B) return;
     for (auto &kv : B->lists) {
-        for (auto &cl : kv.second->classes)
+        for (auto &cl : kv.second->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
+            if (cl.d_rowket0) hipFree(cl.d_rowket0);
+        }
         delete kv.second;
     }
     void free_stored(mess_basis *);
@@ -320,22 +353,50 @@ static void free_basis(mess_basis *B) {
     hipFree(B->d_pp);
     hipFree(B->d_ppf);
     hipFree(B->scratch_jk);
+    hipFree(B->d_mol_moff);
+    hipFree(B->d_mol_nbf);
     delete B;
 }
 
-static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int32_t n_shells,
+// Molecules are given back to back: molecule m owns atoms
+// [atom0_m, atom0_m + natom_m) and shells [sh0_m, sh0_m + nsh_m), with
+// shell_atom holding global atom indices.
+static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_nsh, const int32_t *charges,
+                       int32_t n_atoms, const int32_t *Z, const double *xyz, int32_t n_shells,
                        const int32_t *shell_atom, const int32_t *shell_l, const int32_t *shell_nprim,
-                       const double *exps, const double *coefs, int32_t charge, mess_basis *B) {
-    if (n_atoms <= 0 || n_shells <= 0 || !Z || !xyz || !shell_atom || !shell_l || !shell_nprim || !exps ||
-        !coefs) {
+                       const double *exps, const double *coefs, mess_basis *B) {
+    if (n_mol <= 0 || n_atoms <= 0 || n_shells <= 0 || !Z || !xyz || !shell_atom || !shell_l || !shell_nprim ||
+        !exps || !coefs) {
         set_error("mess_basis_create: NULL array or non-positive count");
         return MESS_E_ARG;
     }
+    B->n_mol = n_mol;
     B->nat = n_atoms;
     B->nsh = n_shells;
     B->Z.assign(Z, Z + n_atoms);
     B->xyz.assign(xyz, xyz + 3 * n_atoms);
-    int zsum = 0;
+    std::vector<int> atom_mol(n_atoms), shell_mol(n_shells);
+    {
+        int a0 = 0, s0 = 0;
+        for (int m = 0; m < n_mol; ++m) {
+            if (mol_natom[m] <= 0 || mol_nsh[m] <= 0) {
+                set_error("mess_basis_create: molecule %d has no atoms or no shells", m);
+                return MESS_E_ARG;
+            }
+            B->mol_atom0.push_back(a0);
+            B->mol_natom.push_back(mol_natom[m]);
+            B->mol_sh0.push_back(s0);
+            B->mol_nsh.push_back(mol_nsh[m]);
+            for (int a = a0; a < a0 + mol_natom[m] && a < n_atoms; ++a) atom_mol[a] = m;
+            for (int q = s0; q < s0 + mol_nsh[m] && q < n_shells; ++q) shell_mol[q] = m;
+            a0 += mol_natom[m];
+            s0 += mol_nsh[m];
+        }
+        if (a0 != n_atoms || s0 != n_shells) {
+            set_error("mess_basis_create: per-molecule atom/shell counts do not add up");
+            return MESS_E_ARG;
+        }
+    }
     for (int a = 0; a < n_atoms; ++a) {
         if (Z[a] < 0 || Z[a] > 118) {
             set_error("mess_basis_create: atomic number %d out of range", Z[a]);
@@ -346,14 +407,7 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
                 set_error("mess_basis_create: non-finite coordinate of atom %d", a);
                 return MESS_E_ARG;
             }
-        zsum += Z[a];
     }
-    B->nelec = zsum - charge;
-    if (B->nelec < 0) {
-        set_error("mess_basis_create: negative electron count");
-        return MESS_E_ARG;
-    }
-    B->nocc = B->nelec / 2;
     int nprim = 0, nbf = 0;
     B->sh_atom.resize(n_shells);
     B->sh_l.resize(n_shells);
@@ -361,7 +415,8 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     B->sh_prim0.resize(n_shells);
     B->sh_bf0.resize(n_shells);
     for (int s = 0; s < n_shells; ++s) {
-        if (shell_atom[s] < 0 || shell_atom[s] >= n_atoms) {
+        const int m = shell_mol[s];
+        if (shell_atom[s] < B->mol_atom0[m] || shell_atom[s] >= B->mol_atom0[m] + B->mol_natom[m]) {
             set_error("mess_basis_create: shell %d on atom %d out of range", s, shell_atom[s]);
             return MESS_E_ARG;
         }
@@ -383,6 +438,49 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
         nbf += ncart(shell_l[s]);
     }
     B->nbf = nbf;
+    // per molecule: functions, packed block, electrons, nuclear repulsion
+    B->mol_moff.assign(1, 0);
+    B->packed = 0;
+    int tot_e = 0;
+    double tot_en = 0.0;
+    for (int m = 0; m < n_mol; ++m) {
+        const int s0 = B->mol_sh0[m], s1 = s0 + B->mol_nsh[m];
+        const int bf0 = B->sh_bf0[s0];
+        const int bf1 = s1 < n_shells ? B->sh_bf0[s1] : nbf;
+        B->mol_bf0.push_back(bf0);
+        B->mol_nbf.push_back(bf1 - bf0);
+        B->packed += (int64_t)(bf1 - bf0) * (bf1 - bf0);
+        B->mol_moff.push_back(B->packed);
+        int zsum = 0;
+        double en = 0.0;
+        const int a0 = B->mol_atom0[m], a1 = a0 + B->mol_natom[m];
+        for (int a = a0; a < a1; ++a) {
+            zsum += Z[a];
+            for (int b = a0; b < a; ++b) {
+                const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
+                             dz = xyz[3 * a + 2] - xyz[3 * b + 2];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                if (r == 0.0 && Z[a] * Z[b] != 0) {
+                    set_error("mess_basis_create: atoms %d and %d coincide", a, b);
+                    return MESS_E_ARG;
+                }
+                if (r > 0.0) en += (double)Z[a] * Z[b] / r;
+            }
+        }
+        const int ne = zsum - (charges ? charges[m] : 0);
+        if (ne < 0) {
+            set_error("mess_basis_create: negative electron count in molecule %d", m);
+            return MESS_E_ARG;
+        }
+        B->mol_nelec.push_back(ne);
+        B->mol_nocc.push_back(ne / 2);
+        B->mol_enuc.push_back(en);
+        tot_e += ne;
+        tot_en += en;
+    }
+    B->nelec = tot_e;
+    B->nocc = tot_e / 2;
+    B->enuc = tot_en;
     B->alpha.assign(exps, exps + nprim);
     B->ctilde.assign(nprim, 0.0);
     for (int p = 0; p < nprim; ++p)
@@ -398,20 +496,6 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
             set_error("mess_basis_create: contraction of shell with primitive %d cannot be normalised", p);
             return MESS_E_ARG;
         }
-    // nuclear repulsion
-    double en = 0.0;
-    for (int a = 0; a < n_atoms; ++a)
-        for (int b = 0; b < a; ++b) {
-            const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1],
-                         dz = xyz[3 * a + 2] - xyz[3 * b + 2];
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            if (r == 0.0 && Z[a] * Z[b] != 0) {
-                set_error("mess_basis_create: atoms %d and %d coincide", a, b);
-                return MESS_E_ARG;
-            }
-            if (r > 0.0) en += (double)Z[a] * Z[b] / r;
-        }
-    B->enuc = en;
     MESS_HIP(hipGetDevice(&B->device));
 
     // Boys tables
@@ -429,27 +513,45 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
 
     // atoms
     std::vector<double> Zd(Z, Z + n_atoms);
+    B->nbf_max = 0;
+    for (int m = 0; m < n_mol; ++m) B->nbf_max = std::max(B->nbf_max, B->mol_nbf[m]);
+    MESS_HIP(hipMalloc(&B->d_mol_moff, sizeof(int64_t) * (n_mol + 1)));
+    MESS_HIP(hipMalloc(&B->d_mol_nbf, sizeof(int) * n_mol));
+    MESS_HIP(hipMemcpy(B->d_mol_moff, B->mol_moff.data(), sizeof(int64_t) * (n_mol + 1), hipMemcpyHostToDevice));
+    MESS_HIP(hipMemcpy(B->d_mol_nbf, B->mol_nbf.data(), sizeof(int) * n_mol, hipMemcpyHostToDevice));
     MESS_HIP(hipMalloc(&B->d_xyz, sizeof(double) * 3 * n_atoms));
     MESS_HIP(hipMalloc(&B->d_Zd, sizeof(double) * n_atoms));
     MESS_HIP(hipMemcpy(B->d_xyz, xyz, sizeof(double) * 3 * n_atoms, hipMemcpyHostToDevice));
     MESS_HIP(hipMemcpy(B->d_Zd, Zd.data(), sizeof(double) * n_atoms, hipMemcpyHostToDevice));
 
-    // shell pairs (a, b) with l_a > l_b, or l_a == l_b and a >= b, grouped by class
-    std::vector<std::vector<int2>> by_class(kNumPairClasses);
-    for (int a = 0; a < n_shells; ++a)
-        for (int b = 0; b < n_shells; ++b) {
-            const int la = B->sh_l[a], lb = B->sh_l[b];
-            if (la > lb || (la == lb && a >= b)) by_class[pair_class_of(la, lb)].push_back(make_int2(a, b));
-        }
+    // shell pairs (a, b) of one molecule with l_a > l_b, or l_a == l_b and
+    // a >= b, grouped by class, then by molecule
     std::vector<int2> pairs_ab;
     std::vector<int> pp0;
+    std::vector<int> seg_lo, seg_hi;  // per pair: its (class, molecule) segment, relative to the class
     int npp = 0;
     for (int c = 0; c < kNumPairClasses; ++c) {
         B->pair_class_off[c] = (int)pairs_ab.size();
-        for (auto ab : by_class[c]) {
-            pairs_ab.push_back(ab);
-            pp0.push_back(npp);
-            npp += B->sh_np[ab.x] * B->sh_np[ab.y];
+        B->seg_off[c].assign(n_mol, 0);
+        B->seg_cnt[c].assign(n_mol, 0);
+        for (int m = 0; m < n_mol; ++m) {
+            const int lo = (int)pairs_ab.size() - B->pair_class_off[c];
+            const int s0 = B->mol_sh0[m], s1 = s0 + B->mol_nsh[m];
+            for (int a = s0; a < s1; ++a)
+                for (int b = s0; b < s1; ++b) {
+                    const int la = B->sh_l[a], lb = B->sh_l[b];
+                    if (!(la > lb || (la == lb && a >= b)) || pair_class_of(la, lb) != c) continue;
+                    pairs_ab.push_back(make_int2(a, b));
+                    pp0.push_back(npp);
+                    npp += B->sh_np[a] * B->sh_np[b];
+                }
+            const int hi = (int)pairs_ab.size() - B->pair_class_off[c];
+            B->seg_off[c][m] = lo;
+            B->seg_cnt[c][m] = hi - lo;
+            for (int k = lo; k < hi; ++k) {
+                seg_lo.push_back(lo);
+                seg_hi.push_back(hi);
+            }
         }
     }
     B->pair_class_off[kNumPairClasses] = (int)pairs_ab.size();
@@ -457,18 +559,19 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     B->npp = npp;
     std::vector<ShellDev> shd(n_shells);
     for (int s = 0; s < n_shells; ++s) {
-        const int a = B->sh_atom[s];
-        shd[s] = ShellDev{xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], B->sh_prim0[s], B->sh_np[s]};
+        const int a = B->sh_atom[s], m = shell_mol[s];
+        shd[s] = ShellDev{xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2], B->sh_prim0[s], B->sh_np[s],
+                          B->sh_bf0[s] - B->mol_bf0[m], (int)B->mol_moff[m], B->mol_nbf[m]};
     }
 
     int2 *d_ab = nullptr;
-    int *d_pp0 = nullptr, *d_bf0 = nullptr, *d_perm = nullptr;
+    int *d_pp0 = nullptr, *d_perm = nullptr, *d_seglo = nullptr, *d_seghi = nullptr;
     ShellDev *d_sh = nullptr;
     double *d_alpha = nullptr, *d_ct = nullptr, *d_Qraw = nullptr;
     PairInfo *d_pairs_raw = nullptr;
     int rc = MESS_OK;
     auto cleanup = [&]() {
-        hipFree(d_ab); hipFree(d_pp0); hipFree(d_bf0); hipFree(d_perm); hipFree(d_sh);
+        hipFree(d_ab); hipFree(d_pp0); hipFree(d_seglo); hipFree(d_seghi); hipFree(d_perm); hipFree(d_sh);
         hipFree(d_alpha); hipFree(d_ct); hipFree(d_Qraw); hipFree(d_pairs_raw);
     };
 #define MESS_HIPC(call)                                                                         \
@@ -483,7 +586,8 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     const int np_ = B->npair;
     MESS_HIPC(hipMalloc(&d_ab, sizeof(int2) * np_));
     MESS_HIPC(hipMalloc(&d_pp0, sizeof(int) * np_));
-    MESS_HIPC(hipMalloc(&d_bf0, sizeof(int) * n_shells));
+    MESS_HIPC(hipMalloc(&d_seglo, sizeof(int) * np_));
+    MESS_HIPC(hipMalloc(&d_seghi, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_perm, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_sh, sizeof(ShellDev) * n_shells));
     MESS_HIPC(hipMalloc(&d_alpha, sizeof(double) * nprim));
@@ -495,13 +599,14 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     MESS_HIPC(hipMalloc(&B->d_pp, sizeof(PrimPair) * npp));
     MESS_HIPC(hipMemcpy(d_ab, pairs_ab.data(), sizeof(int2) * np_, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_pp0, pp0.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
-    MESS_HIPC(hipMemcpy(d_bf0, B->sh_bf0.data(), sizeof(int) * n_shells, hipMemcpyHostToDevice));
+    MESS_HIPC(hipMemcpy(d_seglo, seg_lo.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
+    MESS_HIPC(hipMemcpy(d_seghi, seg_hi.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_sh, shd.data(), sizeof(ShellDev) * n_shells, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_alpha, exps, sizeof(double) * nprim, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_ct, B->ctilde.data(), sizeof(double) * nprim, hipMemcpyHostToDevice));
     hipStream_t s = nullptr;
-    hipLaunchKernelGGL(k_build_pairs, dim3((np_ + 127) / 128), dim3(128), 0, s, np_, d_ab, d_pp0, d_sh, d_bf0,
-                       d_alpha, d_ct, d_pairs_raw, B->d_pp);
+    hipLaunchKernelGGL(k_build_pairs, dim3((np_ + 127) / 128), dim3(128), 0, s, np_, d_ab, d_pp0, d_sh, d_alpha,
+                       d_ct, d_pairs_raw, B->d_pp);
     MESS_HIPC(hipGetLastError());
 
     // Schwarz factors per pair (diagonal quartets), then sort each class by Q
@@ -522,7 +627,8 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
     for (int c = 0; c < kNumPairClasses; ++c) {
         const int off = B->pair_class_off[c], n = B->pair_class_off[c + 1] - off;
         if (n == 0) continue;
-        hipLaunchKernelGGL(k_rank_desc, dim3((n + 255) / 256), dim3(256), 0, s, d_Qraw, off, n, d_perm);
+        hipLaunchKernelGGL(k_rank_desc, dim3((n + 255) / 256), dim3(256), 0, s, d_Qraw, off, n, d_seglo, d_seghi,
+                           d_perm);
         hipLaunchKernelGGL(k_gather_pairs, dim3((n + 255) / 256), dim3(256), 0, s, off, n, d_perm, d_pairs_raw,
                            d_Qraw, B->d_pairs, B->d_pairQ);
     }
@@ -548,7 +654,7 @@ static int create_impl(int32_t n_atoms, const int32_t *Z, const double *xyz, int
         MESS_HIPC(hipMalloc(&B->d_ppf, sizeof(PrimPairF) * npp));
         MESS_HIPC(hipMemcpy(B->d_ppf, hf.data(), sizeof(PrimPairF) * npp, hipMemcpyHostToDevice));
     }
-    MESS_HIPC(hipMalloc(&B->scratch_jk, sizeof(double) * 2 * (size_t)nbf * nbf));
+    MESS_HIPC(hipMalloc(&B->scratch_jk, sizeof(double) * 2 * (size_t)B->packed));
 #undef MESS_HIPC
     cleanup();
     return MESS_OK;
@@ -572,13 +678,72 @@ int mess_basis_create(int32_t n_atoms, const int32_t *Z, const double *xyz_bohr,
     }
     *out = nullptr;
     auto *B = new mess_basis();
-    int rc = create_impl(n_atoms, Z, xyz_bohr, n_shells, shell_atom, shell_l, shell_nprim, exps, coefs, charge,
-                         B);
+    int rc = create_impl(1, &n_atoms, &n_shells, &charge, n_atoms, Z, xyz_bohr, n_shells, shell_atom, shell_l,
+                         shell_nprim, exps, coefs, B);
     if (rc != MESS_OK) {
         free_basis(B);
         return rc;
     }
     *out = B;
+    return MESS_OK;
+}
+
+int mess_batch_create(int32_t n_mol, const int32_t *mol_atoms, const int32_t *mol_shells, const int32_t *charges,
+                      const int32_t *Z, const double *xyz_bohr, const int32_t *shell_atom, const int32_t *shell_l,
+                      const int32_t *shell_nprim, const double *exps, const double *coefs, mess_basis **out) {
+    g_err[0] = 0;
+    if (!out || n_mol <= 0 || !mol_atoms || !mol_shells || !shell_atom) {
+        set_error("mess_batch_create: NULL argument or no molecules");
+        return MESS_E_ARG;
+    }
+    *out = nullptr;
+    int64_t na = 0, ns = 0;
+    for (int m = 0; m < n_mol; ++m) {
+        na += mol_atoms[m];
+        ns += mol_shells[m];
+    }
+    if (na <= 0 || ns <= 0 || na > (1 << 30) || ns > (1 << 30)) {
+        set_error("mess_batch_create: atom/shell totals out of range");
+        return MESS_E_ARG;
+    }
+    // shell_atom is molecule-local: convert to global atom indices
+    std::vector<int32_t> sa(ns);
+    {
+        int64_t a0 = 0, s0 = 0;
+        for (int m = 0; m < n_mol; ++m) {
+            for (int k = 0; k < mol_shells[m]; ++k) {
+                const int32_t la = shell_atom[s0 + k];
+                sa[s0 + k] = (la >= 0 && la < mol_atoms[m]) ? (int32_t)(a0 + la) : -1;
+            }
+            a0 += mol_atoms[m];
+            s0 += mol_shells[m];
+        }
+    }
+    auto *B = new mess_basis();
+    int rc = create_impl(n_mol, mol_atoms, mol_shells, charges, (int32_t)na, Z, xyz_bohr, (int32_t)ns, sa.data(),
+                         shell_l, shell_nprim, exps, coefs, B);
+    if (rc != MESS_OK) {
+        free_basis(B);
+        return rc;
+    }
+    *out = B;
+    return MESS_OK;
+}
+
+int mess_batch_info(const mess_basis *B, int32_t *n_mol, int32_t *nbf, int64_t *moff, int32_t *n_occ,
+                    double *e_nuc) {
+    if (!B) {
+        set_error("mess_batch_info: basis is NULL");
+        return MESS_E_ARG;
+    }
+    if (n_mol) *n_mol = B->n_mol;
+    for (int m = 0; m < B->n_mol; ++m) {
+        if (nbf) nbf[m] = B->mol_nbf[m];
+        if (moff) moff[m] = B->mol_moff[m];
+        if (n_occ) n_occ[m] = B->mol_nocc[m];
+        if (e_nuc) e_nuc[m] = B->mol_enuc[m];
+    }
+    if (moff) moff[B->n_mol] = B->packed;
     return MESS_OK;
 }
 

@@ -15,6 +15,7 @@ struct ClassLaunch {
     const float *tabf, *etabf;
     int bra_off, ket_off, nbra, same_class;
     const int64_t *rowstart;
+    const int *rowket0;  // per bra row: offset of its molecule's kets (NULL: 0)
     int64_t total;
     int N;
     hipStream_t stream;

@@ -196,7 +196,8 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
             if (bra.sa == bra.sb) fac *= 0.5;
             if (ket.sa == ket.sb) fac *= 0.5;
             if (same_class && i == j) fac *= 0.5;
-            wave_digest(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D, N, out0, out1);
+            wave_digest(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D + bra.moff, bra.mN,
+                        out0 ? out0 + bra.moff : nullptr, out1 ? out1 + bra.moff : nullptr);
         }
 }
 

@@ -44,14 +44,14 @@ __global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pai
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra,
-                                                   const int64_t *__restrict__ rowstart,
+                                                   const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    int64_t N, double *__restrict__ eri) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int i = find_row(rowstart, nbra, t);
-        const int j = static_cast<int>(t - rowstart[i]);
+        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -78,14 +78,14 @@ __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ 
 // (structure of arrays, so that consecutive lanes touch consecutive words).
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_eri_store(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
-                                                   int nbra, const int64_t *__restrict__ rowstart,
+                                                   int nbra, const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    Real *__restrict__ base) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int i = find_row(rowstart, nbra, t);
-        const int j = static_cast<int>(t - rowstart[i]);
+        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -160,7 +160,7 @@ __device__ __forceinline__ void digest_jk(const Real (&out)[Dm::NOUT], double fa
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra, int same_class,
-                                                   const int64_t *__restrict__ rowstart,
+                                                   const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    const double *__restrict__ D, int N,
                                                    double *__restrict__ Gj, double *__restrict__ Gk) {
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ 
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int i = find_row(rowstart, nbra, t);
-        const int j = static_cast<int>(t - rowstart[i]);
+        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -177,21 +177,22 @@ __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ 
         if (bra.sa == bra.sb) fac *= 0.5;
         if (ket.sa == ket.sb) fac *= 0.5;
         if (same_class && i == j) fac *= 0.5;
-        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
+        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D + bra.moff, bra.mN,
+                            Gj ? Gj + bra.moff : nullptr, Gk ? Gk + bra.moff : nullptr);
     }
 }
 
 // J/K from stored blocks: one lane per quartet streams its NOUT values.
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
-                                                   int nbra, int same_class, const int64_t *__restrict__ rowstart,
+                                                   int nbra, int same_class, const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
                                                    const Real *__restrict__ base, const double *__restrict__ D,
                                                    int N, double *__restrict__ Gj, double *__restrict__ Gk) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int i = find_row(rowstart, nbra, t);
-        const int j = static_cast<int>(t - rowstart[i]);
+        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -200,7 +201,8 @@ __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ 
         if (bra.sa == bra.sb) fac *= 0.5;
         if (ket.sa == ket.sb) fac *= 0.5;
         if (same_class && i == j) fac *= 0.5;
-        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D, N, Gj, Gk);
+        digest_jk<Dm, Real>(out, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, D + bra.moff, bra.mN,
+                            Gj ? Gj + bra.moff : nullptr, Gk ? Gk + bra.moff : nullptr);
     }
 }
 

@@ -4,6 +4,8 @@
 #include "class_ops.hpp"
 #include "mess_internal.hpp"
 
+#include <algorithm>
+
 namespace mess {
 
 int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out);
@@ -15,11 +17,19 @@ __global__ void k_fill_zero(double *__restrict__ p, int64_t n) {
         p[i] = 0.0;
 }
 
-// out = G + G^T (N x N).
-__global__ void k_symmetrise(const double *__restrict__ G, int N, double *__restrict__ out) {
+// out = G + G^T for every diagonal block of a packed block-diagonal matrix
+// (block m: n_m x n_m at offset moff[m]); blockIdx.z strides over blocks.
+__global__ void k_symmetrise(const double *__restrict__ G, int nmol, const int64_t *__restrict__ moff,
+                             const int *__restrict__ nb, double *__restrict__ out) {
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N && j < N) out[(int64_t)i * N + j] = G[(int64_t)i * N + j] + G[(int64_t)j * N + i];
+    for (int m = blockIdx.z; m < nmol; m += gridDim.z) {
+        const int n = nb[m];
+        if (i < n && j < n) {
+            const int64_t o = moff[m];
+            out[o + (int64_t)i * n + j] = G[o + (int64_t)i * n + j] + G[o + (int64_t)j * n + i];
+        }
+    }
 }
 
 int zero_async(double *p, int64_t n, hipStream_t s) {
@@ -31,21 +41,21 @@ int zero_async(double *p, int64_t n, hipStream_t s) {
     return MESS_OK;
 }
 
-int symmetrise_async(const double *G, int N, double *out, hipStream_t s) {
-    dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
-    hipLaunchKernelGGL(k_symmetrise, grd, blk, 0, s, G, N, out);
+int symmetrise_async(const mess_basis *B, const double *G, double *out, hipStream_t s) {
+    const int N = B->nbf_max;
+    dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8, (unsigned)std::min(B->n_mol, 65535));
+    hipLaunchKernelGGL(k_symmetrise, grd, blk, 0, s, G, B->n_mol, B->d_mol_moff, B->d_mol_nbf, out);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
 
-// Gj, Gk (device, N x N, may be NULL) <- half-matrices of J and K.
+// Gj, Gk (device, packed block-diagonal, may be NULL) <- half-matrices of J and K.
 int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau,
                    hipStream_t s) {
     WorkLists *W = nullptr;
     MESS_TRY(get_work_lists(B, tau, s, &W));
-    const int64_t NN = (int64_t)B->nbf * B->nbf;
-    if (Gj) MESS_TRY(zero_async(Gj, NN, s));
-    if (Gk) MESS_TRY(zero_async(Gk, NN, s));
+    if (Gj) MESS_TRY(zero_async(Gj, B->packed, s));
+    if (Gk) MESS_TRY(zero_async(Gk, B->packed, s));
     const bool prof = prof_on();
     for (const ClassList &cl : W->classes) {
         if (cl.total == 0) continue;
@@ -67,15 +77,14 @@ int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int p
 
 int jk_full(mess_basis *B, const double *D, double *J, double *K, int mode, int prec, double tau,
             hipStream_t s) {
-    const int N = B->nbf;
     double *Gj = J ? static_cast<double *>(B->scratch_jk) : nullptr;
-    double *Gk = K ? static_cast<double *>(B->scratch_jk) + (int64_t)N * N : nullptr;
+    double *Gk = K ? static_cast<double *>(B->scratch_jk) + B->packed : nullptr;
     if (mode == MESS_JK_DIRECT)
         MESS_TRY(jk_direct_half(B, D, Gj, Gk, prec, tau, s));
     else
         MESS_TRY(jk_stored(B, D, Gj, Gk, prec, tau, s));
-    if (J) MESS_TRY(symmetrise_async(Gj, N, J, s));
-    if (K) MESS_TRY(symmetrise_async(Gk, N, K, s));
+    if (J) MESS_TRY(symmetrise_async(B, Gj, J, s));
+    if (K) MESS_TRY(symmetrise_async(B, Gk, K, s));
     return MESS_OK;
 }
 
@@ -100,6 +109,10 @@ int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwa
         return MESS_E_UNSUPPORTED;
     }
     auto *B = const_cast<mess_basis *>(basis);
+    if (B->n_mol != 1) {
+        set_error("mess_eri: the dense tensor is built for a single molecule, not a batch of %d", B->n_mol);
+        return MESS_E_UNSUPPORTED;
+    }
     const int64_t N = B->nbf;
     const size_t need = sizeof(double) * (size_t)(N * N * N * N);
     if (out_bytes < need) {

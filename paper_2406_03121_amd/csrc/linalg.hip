@@ -16,14 +16,14 @@ namespace mess {
 
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
+// One output tile (rows row0.., columns col0..) of C = alpha op(A) op(B) + beta C.
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                              int lda, const double *__restrict__ B, int ldb, double beta,
-                                              double *__restrict__ C, int ldc) {
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, const double *__restrict__ A, int lda,
+                                          const double *__restrict__ B, int ldb, double beta,
+                                          double *__restrict__ C, int ldc, int row0, int col0) {
     __shared__ double As[kTK][kTM + 1];
     __shared__ double Bs[kTK][kTN + 1];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
     double acc[4][4] = {};
     for (int k0 = 0; k0 < K; k0 += kTK) {
         for (int t = threadIdx.x; t < kTK * kTM; t += 256) {
@@ -70,6 +70,30 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha,
     }
 }
 
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                              int lda, const double *__restrict__ B, int ldb, double beta,
+                                              double *__restrict__ C, int ldc) {
+    gemm_tile<TA, TB>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.y * kTM, blockIdx.x * kTN);
+}
+
+// Batched square products over a packed block-diagonal layout: block m is
+// n_m x n_m at offset off[m] in A, B and C; blockIdx.z strides over blocks.
+// Each block's product is computed exactly as gemm() computes it.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_blocks(int nmol, const int64_t *__restrict__ off,
+                                                     const int *__restrict__ nb, double alpha,
+                                                     const double *__restrict__ A, const double *__restrict__ B,
+                                                     double beta, double *__restrict__ C) {
+    for (int m = blockIdx.z; m < nmol; m += gridDim.z) {
+        const int n = nb[m];
+        const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
+        if (row0 >= n || col0 >= n) continue;  // uniform over the block
+        const int64_t o = off[m];
+        gemm_tile<TA, TB>(n, n, n, alpha, A + o, n, B + o, n, beta, C + o, n, row0, col0);
+    }
+}
+
 int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
          const double *B, int ldb, double beta, double *C, int ldc) {
     if (M <= 0 || N <= 0) return MESS_OK;
@@ -82,6 +106,22 @@ int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, con
         hipLaunchKernelGGL((k_gemm<false, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     else
         hipLaunchKernelGGL((k_gemm<true, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
+int gemm_blocks(hipStream_t s, bool ta, bool tb, int nmol, int nmax, const int64_t *off, const int *nb,
+                double alpha, const double *A, const double *B, double beta, double *C) {
+    if (nmol <= 0 || nmax <= 0) return MESS_OK;
+    dim3 grid((nmax + kTN - 1) / kTN, (nmax + kTM - 1) / kTM, (unsigned)(nmol < 65535 ? nmol : 65535)), blk(256);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((k_gemm_blocks<false, false>), grid, blk, 0, s, nmol, off, nb, alpha, A, B, beta, C);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((k_gemm_blocks<true, false>), grid, blk, 0, s, nmol, off, nb, alpha, A, B, beta, C);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((k_gemm_blocks<false, true>), grid, blk, 0, s, nmol, off, nb, alpha, A, B, beta, C);
+    else
+        hipLaunchKernelGGL((k_gemm_blocks<true, true>), grid, blk, 0, s, nmol, off, nb, alpha, A, B, beta, C);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }

@@ -10,6 +10,12 @@ namespace mess {
 int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
          const double *B, int ldb, double beta, double *C, int ldc);
 
+// Batched square products on packed block-diagonal matrices: for each
+// block m (n_m x n_m at offset off[m], device arrays), C_m = alpha op(A_m)
+// op(B_m) + beta C_m.  nmax >= every n_m sizes the grid.
+int gemm_blocks(hipStream_t s, bool ta, bool tb, int nmol, int nmax, const int64_t *off, const int *nb,
+                double alpha, const double *A, const double *B, double beta, double *C);
+
 // Eigen-decomposition of a symmetric n x n matrix A (device, row-major,
 // destroyed): eigenvalues w[n] ascending, eigenvectors as the columns of
 // V[n x n] (row-major), by cyclic Jacobi rotations in one workgroup.

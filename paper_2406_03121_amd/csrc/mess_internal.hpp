@@ -112,7 +112,8 @@ struct PairInfo {
     double ABx, ABy, ABz;
     int pp0, npp;
     int sa, sb;    // shell indices
-    int bfa, bfb;  // first basis function of each shell
+    int bfa, bfb;  // first basis function of each shell, within its molecule
+    int moff, mN;  // packed-matrix offset and dimension of the molecule
 };
 
 // One primitive pair (alpha on A, beta on B): p = alpha + beta,
@@ -159,6 +160,7 @@ struct ClassList {
     int64_t total = 0;               // shell quartets
     int64_t prim_quartets = 0;       // sum over quartets of (bra prim pairs) x (ket prim pairs)
     int64_t *d_rowstart = nullptr;   // nbra + 1
+    int *d_rowket0 = nullptr;        // per bra row: first ket of its molecule (NULL: 0)
     std::vector<int64_t> h_rowstart;  // host copy
 };
 
@@ -186,6 +188,18 @@ struct StoredEri;  // mess_jk(STORED) cache
 struct mess_basis {
     int nat = 0, nsh = 0, nbf = 0, nelec = 0, nocc = 0;
     double enuc = 0.0;
+    // Batches of molecules (a single molecule is a batch of one): functions
+    // are numbered molecule by molecule; matrices are packed block-diagonal,
+    // molecule m's nbf_m x nbf_m block at offset mol_moff[m].
+    int n_mol = 1;
+    std::vector<int> mol_atom0, mol_natom, mol_sh0, mol_nsh, mol_bf0, mol_nbf, mol_nelec, mol_nocc;
+    std::vector<int64_t> mol_moff;  // n_mol + 1
+    std::vector<double> mol_enuc;
+    int64_t packed = 0;             // sum of nbf_m^2
+    int64_t *d_mol_moff = nullptr;  // device copies: n_mol + 1 offsets, n_mol dimensions
+    int *d_mol_nbf = nullptr;
+    int nbf_max = 0;
+    std::vector<int> seg_off[mess::kNumPairClasses], seg_cnt[mess::kNumPairClasses];  // per molecule
     std::vector<int> Z, sh_atom, sh_l, sh_np, sh_prim0, sh_bf0;
     std::vector<double> xyz, alpha, ctilde;  // ctilde: normalised coefs (l,0,0)
     int device = 0;
@@ -210,5 +224,5 @@ struct mess_basis {
 
     std::map<double, mess::WorkLists *> lists;  // keyed by tau
     std::map<std::pair<int, double>, mess::StoredEri *> stored;  // (prec, tau)
-    void *scratch_jk = nullptr;   // [2 * nbf * nbf] doubles: Gj, Gk
+    void *scratch_jk = nullptr;   // [2 * packed] doubles: Gj, Gk
 };

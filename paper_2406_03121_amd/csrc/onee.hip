@@ -15,23 +15,28 @@ namespace mess {
 
 struct ShellLite {
     double x, y, z;
-    int l, prim0, nprim, bf0;
+    int l, prim0, nprim, bf0;  // bf0 within the molecule
+    int moff, mN;              // packed block of the molecule
+    int at0, nat;              // the molecule's nuclei
 };
 
 template <int LA, int LB>
-__global__ void __launch_bounds__(64) k_one_electron(int nsh, const ShellLite *__restrict__ sh,
+__global__ void __launch_bounds__(64) k_one_electron(int npairs, const int2 *__restrict__ ab,
+                                                     const ShellLite *__restrict__ sh,
                                                      const double *__restrict__ alpha,
-                                                     const double *__restrict__ ct, int nat,
+                                                     const double *__restrict__ ct,
                                                      const double *__restrict__ xyz,
                                                      const double *__restrict__ Zc,
                                                      const double *__restrict__ tab,
-                                                     const double *__restrict__ etab, int N,
+                                                     const double *__restrict__ etab,
                                                      double *__restrict__ S, double *__restrict__ T,
                                                      double *__restrict__ V) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nsh * nsh) return;
-    const ShellLite A = sh[t / nsh], B = sh[t % nsh];
+    if (t >= npairs) return;
+    const int2 q = ab[t];
+    const ShellLite A = sh[q.x], B = sh[q.y];
     if (A.l != LA || B.l != LB) return;
+    const int N = A.mN;
     constexpr int NA = ncart(LA), NB = ncart(LB), LAB = LA + LB;
     constexpr int E0 = cart_off(LA), NE = cart_off(LAB + 1);
     const double AB[3] = {A.x - B.x, A.y - B.y, A.z - B.z};
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(64) k_one_electron(int nsh, const ShellLite *_
                 });
             });
             // nuclear attraction
-            for (int c = 0; c < nat; ++c) {
+            for (int c = A.at0; c < A.at0 + A.nat; ++c) {
                 const double PC[3] = {(A.x - xyz[3 * c]) + PA[0], (A.y - xyz[3 * c + 1]) + PA[1],
                                       (A.z - xyz[3 * c + 2]) + PA[2]};
                 const double Tb = p * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
@@ -124,7 +129,7 @@ __global__ void __launch_bounds__(64) k_one_electron(int nsh, const ShellLite *_
         static_for<0, NB>([&](auto IB) {
             constexpr int ia = decltype(IA)::value, ib = decltype(IB)::value;
             constexpr double sc = comp_scale<LA>(ia) * comp_scale<LB>(ib);
-            const int64_t idx = (int64_t)(A.bf0 + ia) * N + B.bf0 + ib;
+            const int64_t idx = A.moff + (int64_t)(A.bf0 + ia) * N + B.bf0 + ib;
             if (S) S[idx] = sc * sacc[ia * NB + ib];
             if (T) T[idx] = sc * tacc[ia * NB + ib];
             if (V) V[idx] = sc * vout[ia * NB + ib];
@@ -144,33 +149,41 @@ extern "C" int mess_one_electron(const mess_basis *B, double *S, double *T, doub
     if (!S && !T && !V) return MESS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<ShellLite> h(B->nsh);
-    for (int i = 0; i < B->nsh; ++i) {
-        const int a = B->sh_atom[i];
-        h[i] = ShellLite{B->xyz[3 * a], B->xyz[3 * a + 1], B->xyz[3 * a + 2], B->sh_l[i], B->sh_prim0[i],
-                         B->sh_np[i], B->sh_bf0[i]};
+    std::vector<int2> pairs;
+    for (int m = 0; m < B->n_mol; ++m) {
+        const int s0 = B->mol_sh0[m], s1 = s0 + B->mol_nsh[m];
+        for (int i = s0; i < s1; ++i) {
+            const int a = B->sh_atom[i];
+            h[i] = ShellLite{B->xyz[3 * a],         B->xyz[3 * a + 1],     B->xyz[3 * a + 2], B->sh_l[i],
+                             B->sh_prim0[i],        B->sh_np[i],           B->sh_bf0[i] - B->mol_bf0[m],
+                             (int)B->mol_moff[m],   B->mol_nbf[m],         B->mol_atom0[m],   B->mol_natom[m]};
+            for (int j = s0; j < s1; ++j) pairs.push_back(make_int2(i, j));
+        }
     }
+    const int npairs = (int)pairs.size();
+    int2 *d_ab = nullptr;
     ShellLite *d_sh = nullptr;
     double *d_alpha = nullptr, *d_ct = nullptr;
     const size_t np = B->alpha.size();
     int rc = MESS_OK;
-    if (hipMalloc(&d_sh, sizeof(ShellLite) * B->nsh) != hipSuccess || hipMalloc(&d_alpha, sizeof(double) * np) != hipSuccess ||
+    if (hipMalloc(&d_ab, sizeof(int2) * npairs) != hipSuccess || hipMalloc(&d_sh, sizeof(ShellLite) * B->nsh) != hipSuccess || hipMalloc(&d_alpha, sizeof(double) * np) != hipSuccess ||
         hipMalloc(&d_ct, sizeof(double) * np) != hipSuccess) {
         set_error("mess_one_electron: device allocation failed");
         rc = MESS_E_NOMEM;
     }
     if (rc == MESS_OK &&
-        (hipMemcpyAsync(d_sh, h.data(), sizeof(ShellLite) * B->nsh, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (hipMemcpyAsync(d_ab, pairs.data(), sizeof(int2) * npairs, hipMemcpyHostToDevice, s) != hipSuccess ||
+         hipMemcpyAsync(d_sh, h.data(), sizeof(ShellLite) * B->nsh, hipMemcpyHostToDevice, s) != hipSuccess ||
          hipMemcpyAsync(d_alpha, B->alpha.data(), sizeof(double) * np, hipMemcpyHostToDevice, s) != hipSuccess ||
          hipMemcpyAsync(d_ct, B->ctilde.data(), sizeof(double) * np, hipMemcpyHostToDevice, s) != hipSuccess)) {
         set_error("mess_one_electron: host-to-device copy failed");
         rc = MESS_E_DEVICE;
     }
     if (rc == MESS_OK) {
-        const int n2 = B->nsh * B->nsh;
-        dim3 g((n2 + 63) / 64), blk(64);
+        dim3 g((npairs + 63) / 64), blk(64);
 #define MESS_ONEE(la, lb)                                                                                  \
-    hipLaunchKernelGGL((k_one_electron<la, lb>), g, blk, 0, s, B->nsh, d_sh, d_alpha, d_ct, B->nat,        \
-                       B->d_xyz, B->d_Zd, B->d_boys, B->d_boys_exp, B->nbf, S, T, V);
+    hipLaunchKernelGGL((k_one_electron<la, lb>), g, blk, 0, s, npairs, d_ab, d_sh, d_alpha, d_ct, B->d_xyz, \
+                       B->d_Zd, B->d_boys, B->d_boys_exp, S, T, V);
         MESS_ONEE(0, 0) MESS_ONEE(0, 1) MESS_ONEE(0, 2)
         MESS_ONEE(1, 0) MESS_ONEE(1, 1) MESS_ONEE(1, 2)
         MESS_ONEE(2, 0) MESS_ONEE(2, 1) MESS_ONEE(2, 2)
@@ -185,6 +198,7 @@ extern "C" int mess_one_electron(const mess_basis *B, double *S, double *T, doub
             rc = MESS_E_DEVICE;
         }
     }
+    hipFree(d_ab);
     hipFree(d_sh);
     hipFree(d_alpha);
     hipFree(d_ct);

@@ -681,6 +681,11 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
         return MESS_E_ARG;
     }
     *out = nullptr;
+    if (basis->n_mol != 1) {
+        set_error("mess_scf_create: the basis holds a batch of %d molecules; use mess_batch_scf_create",
+                  basis->n_mol);
+        return MESS_E_ARG;
+    }
     if (basis->nelec % 2) {
         set_error("mess_scf_create: %d electrons; only closed-shell (even) systems are supported", basis->nelec);
         return MESS_E_UNSUPPORTED;

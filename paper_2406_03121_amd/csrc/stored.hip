@@ -85,9 +85,8 @@ int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, 
     WorkLists *W = nullptr;
     StoredEri *E = nullptr;
     MESS_TRY(get_stored(B, prec, tau, s, &W, &E));
-    const int64_t NN = (int64_t)B->nbf * B->nbf;
-    if (Gj) MESS_TRY(zero_async(Gj, NN, s));
-    if (Gk) MESS_TRY(zero_async(Gk, NN, s));
+    if (Gj) MESS_TRY(zero_async(Gj, B->packed, s));
+    if (Gk) MESS_TRY(zero_async(Gk, B->packed, s));
     const bool prof = prof_on();
     for (size_t c = 0; c < W->classes.size(); ++c) {
         const ClassList &cl = W->classes[c];

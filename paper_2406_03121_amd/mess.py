@@ -26,6 +26,8 @@ EXPORTED = [
     "mess_eri", "mess_jk", "mess_scf_create", "mess_scf_step", "mess_scf_density",
     "mess_scf_fock", "mess_scf_destroy", "mess_last_error",
     "mess_work_stats", "mess_prof_enable", "mess_prof_read",
+    "mess_batch_create", "mess_batch_info", "mess_batch_scf_create", "mess_batch_scf_step",
+    "mess_batch_scf_status", "mess_batch_scf_density", "mess_batch_scf_destroy",
 ]
 
 
@@ -69,6 +71,14 @@ def lib():
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
         i64 = ctypes.c_int64
+        L.mess_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.mess_batch_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mess_batch_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, i32, ctypes.POINTER(vp)]
+        L.mess_batch_scf_step.argtypes = [vp, vp]
+        L.mess_batch_scf_status.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mess_batch_scf_density.argtypes = [vp, vp, vp]
+        L.mess_batch_scf_destroy.argtypes = [vp]
+        L.mess_batch_scf_destroy.restype = None
         L.mess_work_stats.argtypes = [vp, f64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(f64)]
         L.mess_prof_enable.argtypes = [i32]
         L.mess_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64),
@@ -110,7 +120,10 @@ def _host(a, dtype):
 
 
 class Basis:
-    """Owning wrapper of a mess_basis handle."""
+    """Owning wrapper of a mess_basis handle (one molecule or a batch).
+
+    For a batch, mol_nbf / mol_moff / mol_nocc / mol_enuc describe the
+    packed block-diagonal layout of every matrix (packed = mol_moff[-1])."""
 
     def __init__(self, handle):
         self.handle = handle
@@ -118,6 +131,18 @@ class Basis:
         _check(lib().mess_basis_info(handle, ctypes.byref(nbf), ctypes.byref(nocc), ctypes.byref(enuc)),
                "mess_basis_info")
         self.nbf, self.n_occ, self.e_nuc = nbf.value, nocc.value, enuc.value
+        nm = ctypes.c_int32()
+        _check(lib().mess_batch_info(handle, ctypes.byref(nm), None, None, None, None), "mess_batch_info")
+        self.n_mol = nm.value
+        self.mol_nbf = np.zeros(self.n_mol, np.int32)
+        self.mol_moff = np.zeros(self.n_mol + 1, np.int64)
+        self.mol_nocc = np.zeros(self.n_mol, np.int32)
+        self.mol_enuc = np.zeros(self.n_mol, np.float64)
+        _check(lib().mess_batch_info(handle, None, self.mol_nbf.ctypes.data_as(ctypes.c_void_p),
+                                     self.mol_moff.ctypes.data_as(ctypes.c_void_p),
+                                     self.mol_nocc.ctypes.data_as(ctypes.c_void_p),
+                                     self.mol_enuc.ctypes.data_as(ctypes.c_void_p)), "mess_batch_info")
+        self.packed = int(self.mol_moff[-1])
 
     def close(self):
         if self.handle:
@@ -149,6 +174,26 @@ def basis_from_molecule(mol) -> Basis:
     """Convenience: a mess_inputs.Molecule -> Basis."""
     return mess_basis_create(mol.Z, mol.xyz, mol.shell_atom, mol.shell_l, mol.shell_nprim, mol.exps,
                              mol.coefs, mol.charge)
+
+
+def mess_batch_create(mols) -> Basis:
+    """A batch handle over a list of mess_inputs.Molecule (per-molecule
+    shell_atom indices stay local)."""
+    cat = lambda f, dt: np.ascontiguousarray(np.concatenate([np.asarray(getattr(m, f)) for m in mols]), dt)  # noqa: E731
+    na, pna = _host([len(m.Z) for m in mols], np.int32)
+    ns, pns = _host([len(m.shell_l) for m in mols], np.int32)
+    ch, pch = _host([m.charge for m in mols], np.int32)
+    Z, pZ = _host(cat("Z", np.int32), np.int32)
+    xyz, pX = _host(np.concatenate([np.asarray(m.xyz, np.float64).reshape(-1, 3) for m in mols]), np.float64)
+    sa, pA = _host(cat("shell_atom", np.int32), np.int32)
+    sl, pL = _host(cat("shell_l", np.int32), np.int32)
+    sn, pN = _host(cat("shell_nprim", np.int32), np.int32)
+    ex, pE = _host(cat("exps", np.float64), np.float64)
+    co, pC = _host(cat("coefs", np.float64), np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().mess_batch_create(len(mols), pna, pns, pch, pZ, pX, pA, pL, pN, pE, pC, ctypes.byref(h)),
+           "mess_batch_create")
+    return Basis(h)
 
 
 def mess_one_electron(basis: Basis, S=None, T=None, V=None, stream=None):
@@ -209,6 +254,54 @@ def mess_scf_density(scf: Scf, D, stream=None):
 
 def mess_scf_fock(scf: Scf, F, stream=None):
     _check(lib().mess_scf_fock(scf.handle, _ptr(F), _stream(stream)), "mess_scf_fock")
+
+
+class BatchScf:
+    """Owning wrapper of a mess_batch_scf handle."""
+
+    def __init__(self, handle, basis):
+        self.handle, self.basis = handle, basis
+
+    def close(self):
+        if self.handle:
+            lib().mess_batch_scf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mess_batch_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
+                          jk_mode=MESS_JK_DIRECT, D0=None, use_graph=False) -> BatchScf:
+    opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), MESS_FP64,
+                   int(jk_mode), MESS_XC_HF, 0)
+    h = ctypes.c_void_p()
+    _check(lib().mess_batch_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), 1 if use_graph else 0,
+                                       ctypes.byref(h)), "mess_batch_scf_create")
+    return BatchScf(h, basis)
+
+
+def mess_batch_scf_step(scf: BatchScf, stream=None):
+    _check(lib().mess_batch_scf_step(scf.handle, _stream(stream)), "mess_batch_scf_step")
+
+
+def mess_batch_scf_status(scf: BatchScf, stream=None):
+    """dict of per-molecule numpy arrays energy, delta_e, resid, converged, and n_converged."""
+    n = scf.basis.n_mol
+    e, de, r = np.zeros(n), np.zeros(n), np.zeros(n)
+    c = np.zeros(n, np.int32)
+    nc = ctypes.c_int32()
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _check(lib().mess_batch_scf_status(scf.handle, vp(e), vp(de), vp(r), vp(c), ctypes.byref(nc),
+                                       _stream(stream)), "mess_batch_scf_status")
+    return {"energy": e, "delta_e": de, "resid": r, "converged": c.astype(bool), "n_converged": nc.value}
+
+
+def mess_batch_scf_density(scf: BatchScf, D, stream=None):
+    _check(lib().mess_batch_scf_density(scf.handle, _ptr(D), _stream(stream)), "mess_batch_scf_density")
 
 
 def class_index(cb, ck):

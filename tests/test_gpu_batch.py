@@ -1,0 +1,170 @@
+"""Batched molecules: one handle over several molecules must give, molecule
+by molecule, what a handle over that molecule alone gives (one-electron
+matrices, J/K, and the whole SCF trajectory), in the packed block-diagonal
+layout.  The single-molecule path is itself held to the oracle by the other
+GPU tests; the converged energies are also checked against the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import announce, dev, host, need_gpu, random_density, zeros  # noqa: E402
+
+from mess_inputs import generators as gen  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# mol3to20_spd molecules whose SCF converges from the core guess (seed 1002,
+# for one, oscillates for 80 steps in both paths)
+SEEDS = (1000, 1001, 1003, 1004)
+
+
+def _mols():
+    mols = [gen.batched_molecule(s) for s in SEEDS]
+    mols.insert(2, gen.random_small_molecule(3))
+    return mols
+
+
+@pytest.fixture(scope="module")
+def batch():
+    mess = need_gpu()
+    mols = _mols()
+    announce(f"batch of {len(mols)} molecules, nbf {[m.n_bf for m in mols]}")
+    B = mess.mess_batch_create(mols)
+    singles = [mess.basis_from_molecule(m) for m in mols]
+    return mess, mols, B, singles
+
+
+def _blocks(B, flat):
+    return [flat[B.mol_moff[m]:B.mol_moff[m + 1]].reshape(B.mol_nbf[m], B.mol_nbf[m]) for m in range(B.n_mol)]
+
+
+def test_layout(batch):
+    mess, mols, B, singles = batch
+    assert B.n_mol == len(mols)
+    assert list(B.mol_nbf) == [m.n_bf for m in mols]
+    assert B.packed == sum(m.n_bf ** 2 for m in mols)
+    for m, s in enumerate(singles):
+        assert B.mol_nocc[m] == s.n_occ
+        assert abs(B.mol_enuc[m] - s.e_nuc) <= 1e-12 * abs(s.e_nuc)
+
+
+def test_one_electron_batch_equals_single(batch):
+    mess, mols, B, singles = batch
+    S, T, V = zeros(B.packed), zeros(B.packed), zeros(B.packed)
+    mess.mess_one_electron(B, S, T, V)
+    for m, s in enumerate(singles):
+        n = s.nbf
+        Ss, Ts, Vs = zeros(n, n), zeros(n, n), zeros(n, n)
+        mess.mess_one_electron(s, Ss, Ts, Vs)
+        for got, ref in ((S, Ss), (T, Ts), (V, Vs)):
+            g = _blocks(B, host(got))[m]
+            assert np.array_equal(g, host(ref)), m
+
+
+@pytest.mark.parametrize("mode,tau", [(0, 0.0), (0, 1e-10), (1, 1e-10)])
+def test_jk_batch_equals_single(batch, mode, tau):
+    mess, mols, B, singles = batch
+    announce(f"batch J/K mode={mode} tau={tau}")
+    Ds = [random_density(s.nbf, seed=7 + m) for m, s in enumerate(singles)]
+    D = dev(np.concatenate([d.ravel() for d in Ds]))
+    J, K = zeros(B.packed), zeros(B.packed)
+    mess.mess_jk(B, D, J, K, mode=mode, schwarz_tol=tau)
+    Jb, Kb = _blocks(B, host(J)), _blocks(B, host(K))
+    for m, s in enumerate(singles):
+        n = s.nbf
+        Js, Ks = zeros(n, n), zeros(n, n)
+        mess.mess_jk(s, dev(Ds[m]), Js, Ks, mode=mode, schwarz_tol=tau)
+        Js, Ks = host(Js), host(Ks)
+        assert np.abs(Jb[m] - Js).max() <= 1e-12 * max(1.0, np.abs(Js).max()), m
+        assert np.abs(Kb[m] - Ks).max() <= 1e-12 * max(1.0, np.abs(Ks).max()), m
+
+
+def _single_trajectories(mess, singles, steps, tau):
+    out = []
+    for s in singles:
+        scf = mess.mess_scf_create(s, schwarz_tol=tau, conv_tol=1e-9, diis_size=8)
+        es, conv_at = [], None
+        for k in range(steps):
+            e, de, r, c = mess.mess_scf_step(scf)
+            es.append(e)
+            if c:
+                conv_at = k
+                break
+        n = s.nbf
+        D = zeros(n, n)
+        mess.mess_scf_density(scf, D)
+        out.append((es, conv_at, host(D)))
+        scf.close()
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_scf_equals_single(batch, use_graph):
+    mess, mols, B, singles = batch
+    tau, steps = 1e-10, 80
+    announce(f"batched SCF graph={use_graph}")
+    ref = _single_trajectories(mess, singles, steps, tau)
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=tau, conv_tol=1e-9, diis_size=8, use_graph=use_graph)
+    traj = []
+    for k in range(steps):
+        mess.mess_batch_scf_step(bs)
+        st = mess.mess_batch_scf_status(bs)
+        traj.append(st)
+        if st["n_converged"] == B.n_mol:
+            break
+    for m, (es, conv_at, Dref) in enumerate(ref):
+        conv_b = [k for k in range(len(traj)) if traj[k]["converged"][m]]
+        print(f"molecule {m}: nbf {B.mol_nbf[m]} single converged at {conv_at}, batch at "
+              f"{conv_b[0] if conv_b else None}; E {es[-1]!r} vs {traj[-1]['energy'][m]!r}")
+    for m, (es, conv_at, Dref) in enumerate(ref):
+        # the same energy at every step while both run
+        for k in range(min(len(es), len(traj))):
+            assert abs(traj[k]["energy"][m] - es[k]) <= 1e-10 * abs(es[k]), (m, k)
+    for m, (es, conv_at, Dref) in enumerate(ref):
+        assert conv_at is not None, m
+        cb = min(k for k in range(len(traj)) if traj[k]["converged"][m])
+        # the same step converges (|dE| may sit at the tolerance: one step either way)
+        assert abs(cb - conv_at) <= 1, (m, cb, conv_at)
+        # frozen afterwards
+        assert traj[-1]["energy"][m] == traj[cb]["energy"][m]
+    assert traj[-1]["n_converged"] == B.n_mol
+    D = zeros(B.packed)
+    mess.mess_batch_scf_density(bs, D)
+    Db = _blocks(B, host(D))
+    for m, (es, conv_at, Dref) in enumerate(ref):
+        assert np.abs(Db[m] - Dref).max() <= 1e-8, m
+    bs.close()
+
+
+def test_batched_scf_converged_energy_vs_oracle(batch):
+    """Converged energies of two molecules of the batch against the oracle's SCF."""
+    mess, mols, B, singles = batch
+    from oracle import scf as oscf
+    tau = 0.0
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=tau, conv_tol=1e-10, diis_size=8, use_graph=True)
+    for k in range(80):
+        mess.mess_batch_scf_step(bs)
+    st = mess.mess_batch_scf_status(bs)
+    assert st["n_converged"] == B.n_mol
+    small = sorted(range(len(mols)), key=lambda m: mols[m].n_bf)[:2]
+    for m in small:
+        if mols[m].n_bf > 60:
+            continue
+        ref = oscf.RHF(mols[m], jk="dense", conv_tol=1e-10, max_iter=200).run()
+        assert ref["converged"]
+        assert abs(st["energy"][m] - ref["energy"]) <= 1e-8, m
+    bs.close()
+
+
+def test_batch_rejections(batch):
+    mess, mols, B, singles = batch
+    out = zeros(8)
+    with pytest.raises(mess.MessError) as ei:
+        mess.mess_eri(B, out)
+    assert ei.value.code == mess.MESS_E_UNSUPPORTED
+    with pytest.raises(mess.MessError) as ei:
+        mess.mess_scf_create(B)
+    assert ei.value.code == mess.MESS_E_ARG
