@@ -15,12 +15,16 @@ silent (all restated in the design notes):
 * Acceleration: optional Pulay DIIS over at most 8 Fock matrices, applied
   once two are stored, error vector X^T (F D S - S D F) X.
 * Convergence: |E_k - E_{k-1}| < conv_tol, or a fixed iteration count.
+* LDA (xc="lda"): exchange from the Dirac-Slater functional on the
+  molecular grid of ``lda.py`` instead of K:  F = H + J + V_x,
+  E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import core
+from . import lda as olda
 
 
 def canonical_orthogonaliser(S: np.ndarray, thresh: float = 1e-7) -> np.ndarray:
@@ -65,7 +69,7 @@ class RHF:
 
     def __init__(self, mol, jk: str = "dense", tau: float = 0.0, diis: bool = True,
                  diis_size: int = 8, conv_tol: float = 1e-8, max_iter: int = 100,
-                 fixed_iters: int | None = None):
+                 fixed_iters: int | None = None, xc: str = "hf"):
         if mol.n_electrons % 2:
             raise ValueError("closed-shell SCF needs an even electron count")
         self.mol = mol
@@ -78,6 +82,20 @@ class RHF:
         self.diis, self.diis_size = diis, diis_size
         self.conv_tol, self.max_iter, self.fixed_iters = conv_tol, max_iter, fixed_iters
         self._eri = core.eri_dense(mol) if jk == "dense" else None
+        if xc not in ("hf", "lda"):
+            raise ValueError(xc)
+        self.xc = xc
+        self._grid = olda.grid_points(mol) if xc == "lda" else None
+
+    def fock(self, D):
+        """(F, E) at density D for the chosen exchange."""
+        J, K = self.jk(D)
+        if self.xc == "hf":
+            return fock_and_energy(self.H, J, K, D, self.e_nuc)
+        Ex, Vx, _ = olda.lda_x(self.mol, D, grid=self._grid)
+        F = self.H + J + Vx
+        E = float(np.sum(D * self.H)) + 0.5 * float(np.sum(D * J)) + Ex + self.e_nuc
+        return F, E
 
     def jk(self, D):
         if self.jk_mode == "dense":
@@ -90,8 +108,7 @@ class RHF:
 
     def step(self, D):
         """One undamped Roothaan step: D_k -> (F_k, E_k, D_{k+1})."""
-        J, K = self.jk(D)
-        F, E = fock_and_energy(self.H, J, K, D, self.e_nuc)
+        F, E = self.fock(D)
         Dn = density_from_fock(F, self.X, self.n_occ)[0]
         return F, E, Dn
 
@@ -106,8 +123,7 @@ class RHF:
         n_iter = self.fixed_iters if self.fixed_iters is not None else self.max_iter
         F = None
         for k in range(n_iter):
-            J, K = self.jk(D)
-            F, E = fock_and_energy(self.H, J, K, D, self.e_nuc)
+            F, E = self.fock(D)
             D_used = D
             energies.append(E)
             if record:
