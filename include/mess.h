@@ -71,7 +71,8 @@ typedef struct mess_scf_opts {
                             previous |dE| < 1e-3 Ha (FP64 before); full FP64 build at the
                             first iteration and every 8th */
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
-    int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X */
+    int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X (F = H + J + V_x,
+                            E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; FP64 only; see mess_lda_x) */
     int32_t reserved;
 } mess_scf_opts;
 
@@ -152,6 +153,32 @@ int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwa
  * (J, K are always returned in FP64). */
 int mess_jk(const mess_basis *basis, const double *D, double *J, double *K,
             int32_t mode, int32_t prec, double schwarz_tol, mess_stream stream);
+
+/* LDA exchange (the local density approximation the paper names for its
+ * batched DFT example, section 5), as Dirac-Slater exchange on an
+ * atom-centred grid:
+ *   rho_g = sum_{mu nu} phi_mu(r_g) D_{mu nu} phi_nu(r_g),
+ *   E_x = -(3/4)(3/pi)^(1/3) sum_g w_g rho_g^(4/3),
+ *   V_x[mu][nu] = -(3/pi)^(1/3) sum_g w_g rho_g^(1/3) phi_mu(r_g) phi_nu(r_g)
+ * (points with rho_g <= 0 contribute nothing).  Grid per atom: 75 radial
+ * nodes (second-kind Gauss-Chebyshev, x_i = cos(i pi/76), r = (1+x)/(1-x)
+ * bohr) times 17 Gauss-Legendre nodes in cos(theta) times 34 azimuths,
+ * Becke fuzzy-cell weights (three iterations of f(x) = (3x - x^3)/2);
+ * 43,350 points per atom.  The grid and the basis values on it are built on
+ * the first call (synchronous, 8 N bytes per point) and kept in the basis.
+ *   D: device N x N symmetric density.  Vx: device N x N or NULL.
+ *   Ex: host scalar or NULL (non-NULL synchronises the stream).
+ *   rho: device array of mess_grid's point count, or NULL.
+ * Errors: MESS_E_UNSUPPORTED for a batch of more than one molecule,
+ * MESS_E_NOMEM. */
+int mess_lda_x(const mess_basis *basis, const double *D, double *Vx, double *Ex, double *rho,
+               mess_stream stream);
+
+/* The LDA grid: *npts points (host, may be NULL); xyzw (device, may be
+ * NULL) receives [npts][4] = x, y, z (bohr) and weight, ordered by atom,
+ * radial node (largest radius first), theta node (ascending cos theta),
+ * azimuth 2 pi k / 34. */
+int mess_grid(const mess_basis *basis, double *xyzw, int64_t *npts, mess_stream stream);
 
 /* SCF state for the Roothaan equation (section 3, eq. 2) solved by
  * fixed-point iteration.  D0: device N x N initial density, or NULL for

@@ -342,6 +342,8 @@ static void free_basis(mess_basis *B) {
     }
     void free_stored(mess_basis *);
     free_stored(B);
+    void free_xc(mess_basis *);
+    free_xc(B);
     hipFree(B->d_xyz);
     hipFree(B->d_Zd);
     hipFree(B->d_boys);

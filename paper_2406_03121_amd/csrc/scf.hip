@@ -25,6 +25,7 @@ namespace mess {
 int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
 int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
 int zero_async(double *p, int64_t n, hipStream_t s);
+int lda_x_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev);
 
 constexpr int kMaxDiis = 16;
 
@@ -58,6 +59,7 @@ struct mess_scf {
     mess::ScfScalars *sc = nullptr;
     double *partial = nullptr;                           // reduction partials
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
+    double *Vx = nullptr;                                // LDA exchange potential
     double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
@@ -68,20 +70,30 @@ namespace mess {
 
 constexpr int kRedBlocks = 256;
 
-// F = H + (Gj + Gj^T) - 1/2 (Gk + Gk^T), and per-block partial sums of
-// D .* (H + F) (deterministic two-stage reduction).
+// Hartree-Fock (Vx == NULL): F = H + J - K/2 with J = Gj + Gj^T,
+// K = Gk + Gk^T, and per-block partial sums of D .* (H + F);
+// LDA exchange: F = H + J + Vx and partial sums of D .* (2H + J), so that
+// half the total is Tr[D H] + 1/2 Tr[D J] in both cases (deterministic
+// two-stage reduction).
 __global__ void __launch_bounds__(256) k_fock(int N, const double *__restrict__ H, const double *__restrict__ Gj,
-                                              const double *__restrict__ Gk, const double *__restrict__ D,
-                                              double *__restrict__ F, double *__restrict__ partial) {
+                                              const double *__restrict__ Gk, const double *__restrict__ Vx,
+                                              const double *__restrict__ D, double *__restrict__ F,
+                                              double *__restrict__ partial) {
     __shared__ double red[256];
     double acc = 0.0;
     const int64_t NN = (int64_t)N * N;
     for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < NN; idx += (int64_t)gridDim.x * 256) {
         const int i = (int)(idx / N), j = (int)(idx % N);
         const int64_t t = (int64_t)j * N + i;
-        const double f = H[idx] + (Gj[idx] + Gj[t]) - 0.5 * (Gk[idx] + Gk[t]);
-        F[idx] = f;
-        acc += D[idx] * (H[idx] + f);
+        const double J = Gj[idx] + Gj[t];
+        if (Vx) {
+            F[idx] = H[idx] + J + Vx[idx];
+            acc += D[idx] * (2.0 * H[idx] + J);
+        } else {
+            const double f = H[idx] + J - 0.5 * (Gk[idx] + Gk[t]);
+            F[idx] = f;
+            acc += D[idx] * (H[idx] + f);
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -93,7 +105,7 @@ __global__ void __launch_bounds__(256) k_fock(int N, const double *__restrict__ 
 }
 
 __global__ void __launch_bounds__(256) k_finish_energy(int nblk, const double *__restrict__ partial, double enuc,
-                                                       ScfScalars *__restrict__ sc) {
+                                                       const double *__restrict__ ex, ScfScalars *__restrict__ sc) {
     __shared__ double red[256];
     double acc = 0.0;
     for (int i = threadIdx.x; i < nblk; i += 256) acc += partial[i];
@@ -103,7 +115,7 @@ __global__ void __launch_bounds__(256) k_finish_energy(int nblk, const double *_
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sc->energy = 0.5 * red[0] + enuc;
+    if (threadIdx.x == 0) sc->energy = 0.5 * red[0] + enuc + (ex ? ex[0] : 0.0);
 }
 
 // C = M - M^T
@@ -453,7 +465,7 @@ static int lowdin_newton_schulz(mess_scf *st, hipStream_t s, bool *ok) {
 static void free_scf(mess_scf *st) {
     if (!st) return;
     for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
-                      st->P2, st->Fh, st->Eh, st->Bm, st->partial, st->Dprev, st->dD, st->Gja, st->Gka})
+                      st->P2, st->Fh, st->Eh, st->Bm, st->partial, st->Dprev, st->dD, st->Gja, st->Gka, st->Vx})
         hipFree(p);
     hipFree(st->sc);
     delete st;
@@ -524,6 +536,7 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     if (st->opts.prec == MESS_FP32)
         for (double **p : {&st->Dprev, &st->dD, &st->Gja, &st->Gka})
             MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
+    if (st->opts.xc == MESS_XC_LDA_X) MESS_HIP(hipMalloc(&st->Vx, sizeof(double) * std::max<size_t>(nn, 16)));
     MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
     MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
     MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
@@ -591,13 +604,19 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         MESS_HIP(hipMemcpyAsync(st->Dprev, st->D, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
         MESS_HIP(hipMemcpyAsync(st->Gj, st->Gja, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
         MESS_HIP(hipMemcpyAsync(st->Gk, st->Gka, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-    } else if (st->opts.jk_mode == MESS_JK_DIRECT) {
-        MESS_TRY(jk_direct_half(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
     } else {
-        MESS_TRY(jk_stored(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+        // LDA exchange needs no K
+        double *Gk = st->Vx ? nullptr : st->Gk;
+        if (st->opts.jk_mode == MESS_JK_DIRECT)
+            MESS_TRY(jk_direct_half(B, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
+        else
+            MESS_TRY(jk_stored(B, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
     }
-    hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, st->D, st->F, st->partial);
-    hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc, st->sc);
+    const double *ex = nullptr;
+    if (st->Vx) MESS_TRY(lda_x_async(B, st->D, st->Vx, s, &ex));
+    hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, st->Vx, st->D, st->F,
+                       st->partial);
+    hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc, ex, st->sc);
     MESS_LAUNCH_CHECK();
     // commutator e = X^T (F D S - S D F) X, stored at the next DIIS slot
     const int nd = std::min(st->opts.diis_size, kMaxDiis);
@@ -698,8 +717,12 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
         set_error("mess_scf_create: unknown precision %d", opts->prec);
         return MESS_E_UNSUPPORTED;
     }
-    if (opts->xc != MESS_XC_HF) {
-        set_error("mess_scf_create: exchange form %d is not built", opts->xc);
+    if (opts->xc != MESS_XC_HF && opts->xc != MESS_XC_LDA_X) {
+        set_error("mess_scf_create: unknown exchange form %d", opts->xc);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (opts->xc == MESS_XC_LDA_X && opts->prec != MESS_FP64) {
+        set_error("mess_scf_create: LDA exchange runs in FP64 only");
         return MESS_E_UNSUPPORTED;
     }
     if (opts->diis_size < 0 || opts->diis_size > kMaxDiis || !(opts->conv_tol >= 0.0)) {

@@ -28,6 +28,7 @@ EXPORTED = [
     "mess_work_stats", "mess_prof_enable", "mess_prof_read",
     "mess_batch_create", "mess_batch_info", "mess_batch_scf_create", "mess_batch_scf_step",
     "mess_batch_scf_status", "mess_batch_scf_density", "mess_batch_scf_destroy",
+    "mess_lda_x", "mess_grid",
 ]
 
 
@@ -71,6 +72,8 @@ def lib():
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
         i64 = ctypes.c_int64
+        L.mess_lda_x.argtypes = [vp, vp, vp, ctypes.POINTER(f64), vp, vp]
+        L.mess_grid.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
         L.mess_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.mess_batch_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mess_batch_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, i32, ctypes.POINTER(vp)]
@@ -211,6 +214,21 @@ def mess_jk(basis: Basis, D, J=None, K=None, mode=MESS_JK_DIRECT, prec=MESS_FP64
             stream=None):
     _check(lib().mess_jk(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(mode), int(prec), float(schwarz_tol),
                          _stream(stream)), "mess_jk")
+
+
+def mess_lda_x(basis: Basis, D, Vx=None, rho=None, stream=None):
+    """E_x (host float); fills Vx (N x N) and rho (grid points) if given."""
+    ex = ctypes.c_double()
+    _check(lib().mess_lda_x(basis.handle, _ptr(D), _ptr(Vx), ctypes.byref(ex), _ptr(rho), _stream(stream)),
+           "mess_lda_x")
+    return ex.value
+
+
+def mess_grid(basis: Basis, xyzw=None, stream=None):
+    """Number of LDA grid points; fills xyzw [npts, 4] if given."""
+    n = ctypes.c_int64()
+    _check(lib().mess_grid(basis.handle, _ptr(xyzw), ctypes.byref(n), _stream(stream)), "mess_grid")
+    return n.value
 
 
 class Scf:
