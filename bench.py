@@ -94,6 +94,71 @@ def cpu_baseline(mol, target_seconds):
                       f"FP64 McMurchie-Davidson oracle, {dt:.1f} s"}
 
 
+def lda_block(mess, mol, a, torch):
+    """LDA exchange on the same molecule: V_x builds timed with HIP events
+    (grid and basis values built beforehand), then one LDA SCF."""
+    B = mess.basis_from_molecule(mol)
+    n = mess.mess_grid(B)
+    N = mol.n_bf
+    D = torch.eye(N, dtype=torch.float64, device="cuda") * (2.0 * (mol.n_electrons // 2) / N)
+    Vx = torch.zeros(N, N, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    mess.mess_lda_x(B, D, Vx)  # builds grid and basis values
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    reps = 5
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        mess.mess_lda_x(B, D, Vx, None)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    flops = 4.0 * N * N * n  # rho: 2 N^2 per point; V_x: 2 N^2 per point
+    tf = flops / (ms * 1e-3) / 1e12
+    B.close()
+    B = mess.basis_from_molecule(mol)
+    t1 = time.perf_counter()
+    st = mess.mess_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, xc=mess.MESS_XC_LDA_X)
+    e, it, conv = 0.0, 0, False
+    for it in range(1, 101):
+        e, de, resid, conv = mess.mess_scf_step(st)
+        if conv:
+            break
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st.close()
+    return {"grid_points": n, "grid_and_basis_values_s": build_s, "vx_ms_per_build": ms,
+            "vx_alg_tflops": tf, "vx_frac_of_fp64_peak": tf / FP64_VALU_PEAK_TFLOPS,
+            "scf_s": t2 - t1, "scf_iterations": it, "scf_converged": bool(conv), "energy_hartree": e}
+
+
+def batch_block(mess, a, torch):
+    """Batched SCF over many small molecules (seeds 1000...), one HIP graph
+    per step, a fixed number of steps."""
+    from mess_inputs import generators as G
+    mols = G.batch_of_molecules(a.batch_molecules)
+    t0 = time.perf_counter()
+    B = mess.mess_batch_create(mols)
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, use_graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    conv_hist = []
+    for k in range(a.batch_steps):
+        mess.mess_batch_scf_step(bs)
+        st = mess.mess_batch_scf_status(bs)
+        conv_hist.append(st["n_converged"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    q = sum(mess.mess_work_stats(B, a.tau, c)[0] for c in range(21))
+    bs.close()
+    return {"molecules": len(mols), "n_bf_total": int(B.nbf), "packed_doubles": int(B.packed),
+            "shell_quartets_per_step": q, "setup_s": t1 - t0, "steps": a.batch_steps,
+            "ms_per_step": (t2 - t1) / a.batch_steps * 1e3, "converged_after_steps": conv_hist,
+            "converged_molecules_per_s": conv_hist[-1] / (t2 - t0),
+            "shell_quartets_per_s": q * a.batch_steps / (t2 - t1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +172,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-J/K comparison")
+    ap.add_argument("--no-lda", action="store_true", help="skip the LDA-exchange measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 1024-molecule batched SCF")
+    ap.add_argument("--batch-molecules", type=int, default=1024)
+    ap.add_argument("--batch-steps", type=int, default=20)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -225,6 +294,12 @@ def main():
         line["stored_jk"] = stored
         line["jk_gbps"] = stored["jk_gbps"]
         log(f"stored: {stored}")
+    if not a.no_lda:
+        line["lda"] = lda_block(mess, mol, a, torch)
+        log(f"lda: {line['lda']}")
+    if not a.no_batch:
+        line["batch"] = batch_block(mess, a, torch)
+        log(f"batch: {line['batch']}")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a quartet sample")
         line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
