@@ -276,3 +276,29 @@ WORKLOADS = {
 
 def workload(name: str, seed: int = 0) -> Molecule:
     return WORKLOADS[name](seed)
+
+
+# ---------------------------------------------------------------- learned guess
+
+MLP_SHAPES = ((256, 64), (256,), (256, 256), (256,), (128, 256), (128,))
+MLP_NPARAM = sum(int(np.prod(s)) for s in MLP_SHAPES)  # 115,328
+
+
+def mlp_initial_params(seed: int = 0) -> np.ndarray:
+    """Initial parameters of the 64 -> 256 -> 256 -> 128 perceptron, flat
+    float32 in the order W1 [256][64], b1, W2 [256][256], b2, W3 [128][256],
+    b3: weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero."""
+    rng = _rng(seed)
+    out = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = math.sqrt(6.0 / (shape[0] + shape[1]))
+            out.append(rng.uniform(-lim, lim, size=shape).astype(np.float32).ravel())
+        else:
+            out.append(np.zeros(shape, np.float32))
+    return np.concatenate(out)
+
+
+def guess_train_seeds():
+    """Training, validation and test molecule seeds of the learned guess."""
+    return range(100000, 110000), range(110000, 110500), range(1000, 2024)
