@@ -44,6 +44,7 @@ extern "C" {
 typedef struct mess_basis mess_basis;
 typedef struct mess_scf mess_scf;
 typedef struct mess_batch_scf mess_batch_scf;
+typedef struct mess_mlp mess_mlp;
 typedef void *mess_stream;
 
 enum {
@@ -241,6 +242,71 @@ int mess_batch_scf_density(const mess_batch_scf *scf, double *D, mess_stream str
 
 /* NULL is a no-op. */
 void mess_batch_scf_destroy(mess_batch_scf *scf);
+
+/* ---- Learned initial guess ----
+ * The paper writes its energies as differentiable programs so that learned
+ * components can be fitted to data (sections 1 and 5); here a perceptron
+ * predicts the initial density from atom-pair features.
+ *
+ * Pair rows: for each molecule of a basis (single or batch), atom pairs
+ * A <= B in A-major order.  Features, float [rows][64] (42 used): one-hot
+ * element of A and of B over (H, C, N, O); 16 Gaussians
+ * exp(-((R_AB - 2k/3)/(2/3))^2), k = 0..15; unit vector A->B and its six
+ * products (xx, xy, xz, yy, yz, zz), zero for A = B; per-element counts of
+ * the other atoms around A and around B weighted by (cos(pi R/6) + 1)/2
+ * below R = 6 bohr; a self-pair flag.  Outputs, float [rows][128]: element
+ * 11 i + j is the density between function i of A and function j of B
+ * (atoms carry 1..11 functions, contiguous; H, C, N, O only, else
+ * MESS_E_UNSUPPORTED).
+ *
+ * Perceptron 64 -> 256 -> 256 -> 128, SiLU on both hidden layers.  FP32
+ * parameters, MESS_MLP_NPARAM floats in the order W1 [256][64], b1[256],
+ * W2 [256][256], b2[256], W3 [128][256], b3[128] (y = W x + b).  Every layer
+ * product runs on the BF16 matrix cores: operands (inputs, weights,
+ * activations, back-propagated gradients) rounded to BF16 (nearest, ties
+ * to even), FP32 accumulation; biases, pre-activations and gradients FP32.
+ * Training loss: mean of M (Y - T)^2 over the elements with mask M = 1;
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 masters.
+ * All row arrays are device pointers; at most 2^21 rows per call. */
+enum { MESS_MLP_IN = 64, MESS_MLP_HIDDEN = 256, MESS_MLP_OUT = 128, MESS_MLP_NPARAM = 115328 };
+
+/* params: host, MESS_MLP_NPARAM floats (copied).  Adam moments start at 0. */
+int mess_mlp_create(const float *params, mess_mlp **out);
+void mess_mlp_destroy(mess_mlp *mlp);
+/* Copy the FP32 parameters to host params[MESS_MLP_NPARAM] (synchronous). */
+int mess_mlp_params(const mess_mlp *mlp, float *params);
+/* Y[n][128] = perceptron(X[n][64]). */
+int mess_mlp_forward(mess_mlp *mlp, int64_t n, const float *X, float *Y, mess_stream stream);
+/* Gradient of the masked loss into grad[MESS_MLP_NPARAM] (device, may be
+ * NULL) and the loss into *loss (host, may be NULL; synchronises). */
+int mess_mlp_grad(mess_mlp *mlp, int64_t n, const float *X, const float *T, const float *M, float *grad,
+                  double *loss, mess_stream stream);
+/* Gradient, then one Adam step with learning rate lr > 0. */
+int mess_mlp_train_step(mess_mlp *mlp, int64_t n, const float *X, const float *T, const float *M, float lr,
+                        double *loss, mess_stream stream);
+
+/* Number of pair rows of a basis (host output). */
+int mess_guess_rows(const mess_basis *basis, int64_t *n_rows);
+/* Features of every pair row into X (device [rows][64]). */
+int mess_guess_features(const mess_basis *basis, float *X, mess_stream stream);
+/* Training targets from a density (device, packed): T = the pair blocks of
+ * D, M = 1 inside each block; either may be NULL. */
+int mess_guess_targets(const mess_basis *basis, const double *D, float *T, float *M, mess_stream stream);
+/* Density (device, packed) from outputs Y: D[A_i][B_j] = D[B_j][A_i] =
+ * Y[11 i + j]; diagonal blocks take the mean of Y[11 i + j] and Y[11 j + i]. */
+int mess_guess_assemble(const mess_basis *basis, const float *Y, double *D, mess_stream stream);
+/* In place: D <- 2 S^-1/2 V V^T S^-1/2 per molecule, V the n_occ
+ * eigenvectors of S^1/2 D S^1/2 of largest eigenvalue (idempotent in the
+ * metric S, trace N_e), computed with the Loewdin S^-1/2 and the batched
+ * purification.  Synchronous.  MESS_E_NUMERIC if purification fails. */
+int mess_guess_project(const mess_basis *basis, double *D, mess_stream stream);
+/* Per molecule, keep D0's block if its first commutator residual
+ * max |X^T (F D S - S D F) X| (Hartree-Fock F, opts as for
+ * mess_batch_scf_create) is below the core-Hamiltonian guess's, else
+ * replace it by the core guess; used[n_mol] (host, may be NULL) receives
+ * 1 where D0 was kept.  Synchronous. */
+int mess_guess_judge(const mess_basis *basis, const mess_scf_opts *opts, double *D0, int32_t *used,
+                     mess_stream stream);
 
 /* ---- Instrumentation (not part of the method; used by benchmarks). ----
  * Class index cls = cb (cb + 1) / 2 + ck for bra pair class cb >= ket pair

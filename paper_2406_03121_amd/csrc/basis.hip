@@ -344,6 +344,8 @@ static void free_basis(mess_basis *B) {
     free_stored(B);
     void free_xc(mess_basis *);
     free_xc(B);
+    void free_guess_tables(mess_basis *);
+    free_guess_tables(B);
     hipFree(B->d_xyz);
     hipFree(B->d_Zd);
     hipFree(B->d_boys);

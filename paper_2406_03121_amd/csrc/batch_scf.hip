@@ -612,7 +612,8 @@ static int batch_lowdin(mess_batch_scf *st, hipStream_t s) {
     return MESS_OK;
 }
 
-static int batch_create_impl(mess_batch_scf *st, const double *D0) {
+// ortho_only: one-electron matrices and X only (no density, no J/K set-up).
+static int batch_create_impl(mess_batch_scf *st, const double *D0, bool ortho_only = false) {
     mess_basis *B = st->basis;
     st->nmol = B->n_mol;
     st->nmax = B->nbf_max;
@@ -642,6 +643,11 @@ static int batch_create_impl(mess_batch_scf *st, const double *D0) {
     MESS_TRY(mess_one_electron(B, st->S, st->W1, st->W2, s));
     MESS_TRY(axpby(s, B->packed, 1.0, st->W1, 1.0, st->W2, st->H));
     MESS_TRY(batch_lowdin(st, s));
+    if (ortho_only) {
+        MESS_HIP(hipStreamSynchronize(s));
+        MESS_HIP(hipMemset(st->ms, 0, sizeof(MolScalars) * st->nmol));
+        return MESS_OK;
+    }
     if (D0) {
         MESS_HIP(hipMemcpyAsync(st->D, D0, sizeof(double) * B->packed, hipMemcpyDeviceToDevice, s));
     } else {
@@ -662,11 +668,103 @@ static int batch_create_impl(mess_batch_scf *st, const double *D0) {
     return MESS_OK;
 }
 
+// Natural-orbital projection: with X = S^-1/2 and S^1/2 = S X, the
+// projector P onto the n_occ lowest eigenvectors of -S^1/2 D S^1/2 (the
+// n_occ largest of S^1/2 D S^1/2) by the same purification as the SCF step;
+// D <- 2 X P X.
+static int project_impl(mess_batch_scf *st, double *D, hipStream_t s) {
+    const BLaunch L = blaunch(st);
+    MESS_TRY(bgemm(st, s, false, false, 1.0, st->S, st->X, 0.0, st->Gj));   // S^1/2
+    MESS_TRY(bgemm(st, s, false, false, 1.0, st->Gj, D, 0.0, st->Gk));
+    MESS_TRY(bgemm(st, s, false, false, 1.0, st->Gk, st->Gj, 0.0, st->W3));
+    hipLaunchKernelGGL(k_bident_plus, L.ew, dim3(256), 0, s, L.nmol, L.moff, L.nb, 0.0, -1.0, st->W3, st->Fx);
+    MESS_LAUNCH_CHECK();
+    MESS_TRY(purify_density(st, st->Fx, D, s));
+    return MESS_OK;
+}
+
 }  // namespace mess
 
 using namespace mess;
 
 extern "C" {
+
+int mess_guess_project(const mess_basis *basis, double *D, mess_stream stream) {
+    if (!basis || !D) {
+        set_error("mess_guess_project: NULL argument");
+        return MESS_E_ARG;
+    }
+    for (int m = 0; m < basis->n_mol; ++m)
+        if (basis->mol_nelec[m] % 2) {
+            set_error("mess_guess_project: molecule %d has an odd electron count", m);
+            return MESS_E_UNSUPPORTED;
+        }
+    auto *st = new mess_batch_scf();
+    st->basis = const_cast<mess_basis *>(basis);
+    st->opts.diis_size = 0;
+    int rc = batch_create_impl(st, nullptr, true);
+    if (rc == MESS_OK) rc = project_impl(st, D, static_cast<hipStream_t>(stream));
+    if (rc == MESS_OK && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) {
+        set_error("mess_guess_project: device error");
+        rc = MESS_E_DEVICE;
+    }
+    if (rc == MESS_OK) {
+        std::vector<MolScalars> h(st->nmol);
+        if (hipMemcpy(h.data(), st->ms, sizeof(MolScalars) * st->nmol, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = MESS_E_DEVICE;
+        } else {
+            for (int m = 0; m < st->nmol; ++m)
+                if (h[m].sp2_fail) {
+                    set_error("mess_guess_project: purification of molecule %d did not finish", m);
+                    rc = MESS_E_NUMERIC;
+                    break;
+                }
+        }
+    }
+    free_batch(st);
+    return rc;
+}
+
+int mess_guess_judge(const mess_basis *basis, const mess_scf_opts *opts, double *D0, int32_t *used,
+                     mess_stream stream) {
+    if (!basis || !opts || !D0) {
+        set_error("mess_guess_judge: NULL argument");
+        return MESS_E_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MESS_HIP(hipStreamSynchronize(s));
+    mess_batch_scf *a = nullptr, *b = nullptr;
+    MESS_TRY(mess_batch_scf_create(basis, opts, D0, 0, &a));
+    int rc = mess_batch_scf_create(basis, opts, nullptr, 0, &b);
+    double *Dcore = nullptr;
+    std::vector<double> ra(basis->n_mol), rb(basis->n_mol);
+    if (rc == MESS_OK && hipMalloc(&Dcore, sizeof(double) * std::max<int64_t>(basis->packed, 1)) != hipSuccess)
+        rc = MESS_E_NOMEM;
+    if (rc == MESS_OK && hipMemcpyAsync(Dcore, b->D, sizeof(double) * basis->packed, hipMemcpyDeviceToDevice, s) !=
+                             hipSuccess)
+        rc = MESS_E_DEVICE;
+    if (rc == MESS_OK) rc = mess_batch_scf_step(a, s);
+    if (rc == MESS_OK) rc = mess_batch_scf_step(b, s);
+    if (rc == MESS_OK) rc = mess_batch_scf_status(a, nullptr, nullptr, ra.data(), nullptr, nullptr, s);
+    if (rc == MESS_OK) rc = mess_batch_scf_status(b, nullptr, nullptr, rb.data(), nullptr, nullptr, s);
+    if (rc == MESS_OK) {
+        for (int m = 0; m < basis->n_mol && rc == MESS_OK; ++m) {
+            const bool keep = ra[m] < rb[m];
+            if (used) used[m] = keep ? 1 : 0;
+            if (!keep &&
+                hipMemcpyAsync(D0 + basis->mol_moff[m], Dcore + basis->mol_moff[m],
+                               sizeof(double) * (size_t)basis->mol_nbf[m] * basis->mol_nbf[m],
+                               hipMemcpyDeviceToDevice, s) != hipSuccess)
+                rc = MESS_E_DEVICE;
+        }
+        if (rc == MESS_OK && hipStreamSynchronize(s) != hipSuccess) rc = MESS_E_DEVICE;
+        if (rc == MESS_E_DEVICE) set_error("mess_guess_judge: device copy failed");
+    }
+    hipFree(Dcore);
+    mess_batch_scf_destroy(a);
+    mess_batch_scf_destroy(b);
+    return rc;
+}
 
 int mess_batch_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const double *D0, int32_t use_graph,
                           mess_batch_scf **out) {

@@ -226,4 +226,5 @@ struct mess_basis {
     std::map<std::pair<int, double>, mess::StoredEri *> stored;  // (prec, tau)
     void *scratch_jk = nullptr;   // [2 * packed] doubles: Gj, Gk
     void *xc = nullptr;           // LDA grid and basis values (built on first use)
+    void *guess = nullptr;        // learned-guess pair tables (built on first use)
 };

@@ -29,7 +29,11 @@ EXPORTED = [
     "mess_batch_create", "mess_batch_info", "mess_batch_scf_create", "mess_batch_scf_step",
     "mess_batch_scf_status", "mess_batch_scf_density", "mess_batch_scf_destroy",
     "mess_lda_x", "mess_grid",
+    "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
+    "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
+    "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
 ]
+MESS_MLP_NPARAM = 115328
 
 
 class MessError(RuntimeError):
@@ -72,6 +76,20 @@ def lib():
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
         i64 = ctypes.c_int64
+        f32 = ctypes.c_float
+        L.mess_mlp_create.argtypes = [vp, ctypes.POINTER(vp)]
+        L.mess_mlp_destroy.argtypes = [vp]
+        L.mess_mlp_destroy.restype = None
+        L.mess_mlp_params.argtypes = [vp, vp]
+        L.mess_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+        L.mess_mlp_grad.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(f64), vp]
+        L.mess_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, f32, ctypes.POINTER(f64), vp]
+        L.mess_guess_rows.argtypes = [vp, ctypes.POINTER(i64)]
+        L.mess_guess_features.argtypes = [vp, vp, vp]
+        L.mess_guess_targets.argtypes = [vp, vp, vp, vp, vp]
+        L.mess_guess_assemble.argtypes = [vp, vp, vp, vp]
+        L.mess_guess_project.argtypes = [vp, vp, vp]
+        L.mess_guess_judge.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, vp, vp]
         L.mess_lda_x.argtypes = [vp, vp, vp, ctypes.POINTER(f64), vp, vp]
         L.mess_grid.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
         L.mess_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -320,6 +338,84 @@ def mess_batch_scf_status(scf: BatchScf, stream=None):
 
 def mess_batch_scf_density(scf: BatchScf, D, stream=None):
     _check(lib().mess_batch_scf_density(scf.handle, _ptr(D), _stream(stream)), "mess_batch_scf_density")
+
+
+class Mlp:
+    """Owning wrapper of a mess_mlp handle (the learned-guess perceptron)."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != MESS_MLP_NPARAM:
+            raise ValueError(f"expected {MESS_MLP_NPARAM} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        _check(lib().mess_mlp_create(p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)), "mess_mlp_create")
+        self.handle = h
+
+    def params(self):
+        out = np.zeros(MESS_MLP_NPARAM, np.float32)
+        _check(lib().mess_mlp_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)), "mess_mlp_params")
+        return out
+
+    def forward(self, X, Y, stream=None):
+        _check(lib().mess_mlp_forward(self.handle, X.shape[0], _ptr(X), _ptr(Y), _stream(stream)),
+               "mess_mlp_forward")
+
+    def grad(self, X, T, M, grad=None, stream=None):
+        loss = ctypes.c_double()
+        _check(lib().mess_mlp_grad(self.handle, X.shape[0], _ptr(X), _ptr(T), _ptr(M), _ptr(grad),
+                                   ctypes.byref(loss), _stream(stream)), "mess_mlp_grad")
+        return loss.value
+
+    def train_step(self, X, T, M, lr=1e-3, want_loss=True, stream=None):
+        loss = ctypes.c_double()
+        _check(lib().mess_mlp_train_step(self.handle, X.shape[0], _ptr(X), _ptr(T), _ptr(M), float(lr),
+                                         ctypes.byref(loss) if want_loss else None, _stream(stream)),
+               "mess_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.handle:
+            lib().mess_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mess_guess_rows(basis: Basis):
+    n = ctypes.c_int64()
+    _check(lib().mess_guess_rows(basis.handle, ctypes.byref(n)), "mess_guess_rows")
+    return n.value
+
+
+def mess_guess_features(basis: Basis, X, stream=None):
+    _check(lib().mess_guess_features(basis.handle, _ptr(X), _stream(stream)), "mess_guess_features")
+
+
+def mess_guess_targets(basis: Basis, D, T=None, M=None, stream=None):
+    _check(lib().mess_guess_targets(basis.handle, _ptr(D), _ptr(T), _ptr(M), _stream(stream)),
+           "mess_guess_targets")
+
+
+def mess_guess_assemble(basis: Basis, Y, D, stream=None):
+    _check(lib().mess_guess_assemble(basis.handle, _ptr(Y), _ptr(D), _stream(stream)), "mess_guess_assemble")
+
+
+def mess_guess_project(basis: Basis, D, stream=None):
+    _check(lib().mess_guess_project(basis.handle, _ptr(D), _stream(stream)), "mess_guess_project")
+
+
+def mess_guess_judge(basis: Basis, D0, schwarz_tol=1e-10, stream=None):
+    """Replaces, per molecule, D0's block by the core guess where that has the
+    smaller first commutator residual; returns the per-molecule 'kept' flags."""
+    opts = ScfOpts(float(schwarz_tol), 1e-8, 100, 8, MESS_FP64, MESS_JK_DIRECT, MESS_XC_HF, 0)
+    used = np.zeros(basis.n_mol, np.int32)
+    _check(lib().mess_guess_judge(basis.handle, ctypes.byref(opts), _ptr(D0), used.ctypes.data_as(ctypes.c_void_p),
+                                  _stream(stream)), "mess_guess_judge")
+    return used.astype(bool)
 
 
 def class_index(cb, ck):
