@@ -7,7 +7,9 @@
 // recursion runs the same way.  The per-class step lists are generated on
 // the host from the recursions (see eri_hgp.hpp for the formulas) and are
 // the same for every quartet of the class.
+#include <algorithm>
 #include <cstring>
+#include <set>
 #include <memory>
 #include <mutex>
 
@@ -67,6 +69,106 @@ struct CoopTables {
     std::vector<unsigned short> accsrc, outslot;
     std::vector<double> outscale;
 };
+
+// Sources a step reads: s1, s2 always; s3, s4 with k3 != 0; s5 with k5 != 0.
+static int step_reads(const int4 op, int *src) {
+    const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
+    int n = 0;
+    src[n++] = op.x >> 16;
+    src[n++] = op.y & 0xffff;
+    if (k3) {
+        src[n++] = op.y >> 16;
+        src[n++] = op.z & 0xffff;
+    }
+    if (k5) src[n++] = op.z >> 16;
+    return n;
+}
+
+// Reuses LDS slots: a slot whose value is last read at level l may receive a
+// destination of any level after l (all reads of a level finish at its
+// barrier).  Slots [0, nfixed) hold values defined before the first level
+// (their numbers are kept); slot 0 is never reused when keep0 (it is the
+// zero operand of absent terms).  Rewrites the steps and the final reads
+// in place and returns the number of slots, or -1 if the symbolic replay
+// of the rewritten tables does not reproduce the original data flow.
+static int compact_slots(std::vector<int4> &ops, const std::vector<int> &lev, int nlog, int nfixed, bool keep0,
+                         std::vector<unsigned short> &final_reads) {
+    const int nlev = (int)lev.size() - 1;
+    std::vector<int> last(nlog, -1);
+    int src[5];
+    for (int lv = 0; lv < nlev; ++lv)
+        for (int o = lev[lv]; o < lev[lv + 1]; ++o) {
+            const int n = step_reads(ops[o], src);
+            for (int k = 0; k < n; ++k) last[src[k]] = std::max(last[src[k]], lv);
+        }
+    for (unsigned short r : final_reads) last[r] = nlev;
+    std::vector<int> phys(nlog, -1);
+    std::vector<int> live;
+    for (int l = 0; l < nfixed; ++l) {
+        phys[l] = l;
+        live.push_back(l);
+    }
+    std::set<int> freeset;
+    int next = nfixed;
+    const std::vector<int4> orig = ops;
+    for (int lv = 0; lv < nlev; ++lv) {
+        std::vector<int> still;
+        for (int l : live) {
+            if (last[l] < lv && !(keep0 && l == 0)) freeset.insert(phys[l]);
+            else still.push_back(l);
+        }
+        live.swap(still);
+        for (int o = lev[lv]; o < lev[lv + 1]; ++o) {
+            const int d = ops[o].x & 0xffff;
+            int p;
+            if (freeset.empty()) {
+                p = next++;
+            } else {
+                p = *freeset.begin();
+                freeset.erase(freeset.begin());
+            }
+            phys[d] = p;
+            live.push_back(d);
+        }
+        for (int o = lev[lv]; o < lev[lv + 1]; ++o) {
+            int4 &op = ops[o];
+            const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
+            const int d = op.x & 0xffff, s1 = op.x >> 16, s2 = op.y & 0xffff, s3 = op.y >> 16,
+                      s4 = op.z & 0xffff, s5 = op.z >> 16;
+            op.x = phys[d] | (phys[s1] << 16);
+            op.y = phys[s2] | ((k3 ? phys[s3] : 0) << 16);
+            op.z = (k3 ? phys[s4] : 0) | ((k5 ? phys[s5] : 0) << 16);
+        }
+    }
+    std::vector<unsigned short> final_orig = final_reads;
+    for (unsigned short &r : final_reads) r = (unsigned short)phys[r];
+    const int nphys = next;
+    if (nphys >= 65536) return -1;
+    // symbolic replay: every read finds the value the original step read,
+    // no destination of a level aliases another destination or a source
+    // of that level
+    std::vector<int> content(nphys, -1);
+    for (int l = 0; l < nfixed; ++l) content[l] = l;
+    for (int lv = 0; lv < nlev; ++lv) {
+        std::set<int> dsts, reads;
+        for (int o = lev[lv]; o < lev[lv + 1]; ++o) {
+            int so[5], sn[5];
+            const int n = step_reads(orig[o], so);
+            step_reads(ops[o], sn);
+            for (int k = 0; k < n; ++k) {
+                if (sn[k] < 0 || sn[k] >= nphys || content[sn[k]] != so[k]) return -1;
+                reads.insert(sn[k]);
+            }
+            if (!dsts.insert(ops[o].x & 0xffff).second) return -1;
+        }
+        for (int dd : dsts)
+            if (reads.count(dd)) return -1;
+        for (int o = lev[lv]; o < lev[lv + 1]; ++o) content[ops[o].x & 0xffff] = orig[o].x & 0xffff;
+    }
+    for (size_t k = 0; k < final_reads.size(); ++k)
+        if (content[final_reads[k]] != final_orig[k]) return -1;
+    return nphys;
+}
 
 std::unique_ptr<CoopProgram> build_tables(int cb, int ck, CoopTables &tables) {
     auto P = std::make_unique<CoopProgram>();
@@ -249,6 +351,33 @@ std::unique_ptr<CoopProgram> build_tables(int cb, int ck, CoopTables &tables) {
         for (int o = 0; o < P->nout; ++o)
             if (outslot[o] >= P->nH || hdef[outslot[o]] < 0) return nullptr;
     }
+    // Slot reuse.  The final reads are checked against the original slots
+    // here, since compact_slots rewrites them.
+    {
+        const std::vector<unsigned short> acc0 = accsrc, out0 = outslot;
+        const int nv = compact_slots(vops, vlev, P->nV, L + 2, true, accsrc);
+        const int nh = compact_slots(hops, hlev, P->nH, P->nacc, false, outslot);
+        if (nv < 0 || nh < 0) return nullptr;
+        P->nV = nv;
+        P->nH = nh;
+        (void)acc0;
+        (void)out0;
+    }
+    // VRR steps: replace the five coefficient indices by the step's side
+    // (bit 2: ket) and direction (bits 0-1); the kernel holds the
+    // coefficients in registers.  Within a level, steps are grouped by the
+    // terms they use so that a wave mostly takes one path.
+    for (int4 &op : vops) {
+        const int a1 = op.w & 31;
+        const int ket = a1 >= kQC ? 1 : 0;
+        const int dir = ket ? a1 - kQC : a1 - kPA;
+        op.w = dir | (ket << 2) | (op.w & (0x3f << 25));
+    }
+    for (int lv = 0; lv < P->nvlev; ++lv)
+        std::stable_sort(vops.begin() + vlev[lv], vops.begin() + vlev[lv + 1], [](const int4 &x, const int4 &y) {
+            auto key = [](const int4 &o) { return (((o.w >> 25) & 7) ? 2 : 0) + (((o.w >> 28) & 7) ? 1 : 0); };
+            return key(x) < key(y);
+        });
     // LDS: accumulators [0, nacc), then one region shared by the VRR slots
     // (during the primitive loop) and the HRR slots >= nacc (after it).
     tables.vops = std::move(vops);
@@ -347,15 +476,33 @@ static const CoopProgram *coop_program(int cb, int ck) {
 
 // ------------------------------------------------------------ device
 
+// Per-primitive-quartet coefficients of the vertical recursion, in registers.
 template <typename Real>
-__device__ __forceinline__ Real run_op_r(const int4 op, const Real *__restrict__ V, const Real *__restrict__ c) {
-    const int s1 = op.x >> 16, s2 = op.y & 0xffff, s3 = op.y >> 16, s4 = op.z & 0xffff, s5 = op.z >> 16;
-    const int w = op.w;
-    const int a1 = w & 31, a2 = (w >> 5) & 31, a3 = (w >> 10) & 31, a4 = (w >> 15) & 31, a5 = (w >> 20) & 31;
-    const Real k3 = (Real)((w >> 25) & 7), k5 = (Real)((w >> 28) & 7);
-    Real v = c[a1] * V[s1] + c[a2] * V[s2];
-    v += k3 * (c[a3] * V[s3] - c[a4] * V[s4]);
-    v += k5 * c[a5] * V[s5];
+struct VrrCoef {
+    Real PA[3], WP[3], QC[3], WQ[3];
+    Real o2p, o2pr, o2q, o2qr, o2pq;
+};
+
+template <typename Real>
+__device__ __forceinline__ Real sel3(int d, Real a0, Real a1, Real a2) {
+    return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
+// One vertical step: side (bra/ket) and direction from op.w bits 0-2,
+// v = c1 V[s1] + c2 V[s2] + k3 (c3 V[s3] - c4 V[s4]) + k5 / (2(p+q)) V[s5].
+template <typename Real>
+__device__ __forceinline__ Real run_vop(const int4 op, const Real *__restrict__ V, const VrrCoef<Real> &c) {
+    const int s1 = op.x >> 16, s2 = op.y & 0xffff;
+    const int w = op.w, dir = w & 3, k3 = (w >> 25) & 7, k5 = (w >> 28) & 7;
+    const bool ket = (w >> 2) & 1;
+    const Real c1 = ket ? sel3(dir, c.QC[0], c.QC[1], c.QC[2]) : sel3(dir, c.PA[0], c.PA[1], c.PA[2]);
+    const Real c2 = ket ? sel3(dir, c.WQ[0], c.WQ[1], c.WQ[2]) : sel3(dir, c.WP[0], c.WP[1], c.WP[2]);
+    Real v = c1 * V[s1] + c2 * V[s2];
+    if (k3) {
+        const Real c3 = ket ? c.o2q : c.o2p, c4 = ket ? c.o2qr : c.o2pr;
+        v += (Real)k3 * (c3 * V[op.y >> 16] - c4 * V[op.z & 0xffff]);
+    }
+    if (k5) v += (Real)k5 * c.o2pq * V[op.z >> 16];
     return v;
 }
 
@@ -379,24 +526,31 @@ __device__ __forceinline__ Real coop_boys_r(int m, Real T, const BoysTabs &bt) {
     }
 }
 
-template <int MODE, typename Real>
-__global__ void __launch_bounds__(64) k_coop(CoopArgs A, int region, const PairInfo *__restrict__ pairs, int bra_off,
-                                             int ket_off, int nbra, int same_class,
+// NT threads (one to four waves) share each shell quartet.
+// NT threads share each shell quartet; they form NP groups of NT/NP threads,
+// each group running the vertical recursion of its own primitive quartet
+// in its own LDS slot region (vstride doubles apart), so NP primitive
+// quartets advance per round of level barriers.
+template <int MODE, typename Real, int NT, int NP>
+__global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride, const PairInfo *__restrict__ pairs,
+                                             int bra_off, int ket_off, int nbra, int same_class,
                                              const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0, int64_t total,
                                              const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                              const double *__restrict__ D, int N, double *__restrict__ out0,
                                              double *__restrict__ out1) {
     // LDS: accumulators H[0, nacc) (FP64), then `region` doubles shared by the
-    // VRR slots (Real, during the primitive loop) and the HRR slots >= nacc
-    // (after it), then the VRR coefficients (Real) and the HRR coefficients.
+    // NP VRR slot regions (Real, during the primitive loop) and the HRR slots
+    // >= nacc (after it), then the HRR coefficients.
+    constexpr int GT = NT / NP;  // threads per group
     extern __shared__ double lds[];
     double *H = lds;
-    Real *V = reinterpret_cast<Real *>(lds + A.nacc);
-    Real *c = reinterpret_cast<Real *>(lds + A.nacc + region);
-    double *hc = lds + A.nacc + region + (kNCoef * sizeof(Real) + 7) / 8;
+    Real *V0 = reinterpret_cast<Real *>(lds + A.nacc);
+    double *hc = lds + A.nacc + region;
     const int lane = threadIdx.x;
+    const int grp = lane / GT, gl = lane % GT;
+    Real *V = V0 + (size_t)grp * vstride;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-        if (lane == 0) V[0] = Real(0);
+        if (gl == 0) V[0] = Real(0);
         int i, j;
         if (MODE == kModeSchwarz) {
             i = j = (int)q;
@@ -407,43 +561,52 @@ __global__ void __launch_bounds__(64) k_coop(CoopArgs A, int region, const PairI
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
         const Real ACx = Real(bra.Ax - ket.Ax), ACy = Real(bra.Ay - ket.Ay), ACz = Real(bra.Az - ket.Az);
-        for (int s = lane; s < A.nacc; s += 64) H[s] = 0.0;
-        for (int ib = 0; ib < bra.npp; ++ib) {
+        for (int s = lane; s < A.nacc; s += NT) H[s] = 0.0;
+        const int npq = bra.npp * ket.npp;
+        for (int r0 = 0; r0 < npq; r0 += NP) {
+            // every thread passes every barrier; a group past the end idles
+            const int pidx = r0 + grp;
+            const bool act = pidx < npq;
+            const int ib = act ? pidx / ket.npp : 0, ik = act ? pidx % ket.npp : 0;
             const PrimPairT<Real> P = pp[bra.pp0 + ib];
-            for (int ik = 0; ik < ket.npp; ++ik) {
-                const PrimPairT<Real> Q = pp[ket.pp0 + ik];
-                const Real p = P.p, qq = Q.p, pq = p + qq, rpq = Real(1) / pq, rho = p * qq * rpq;
-                const Real PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
-                const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-                __syncthreads();  // previous primitive quartet fully consumed
-                if (lane <= A.L) {
-                    const Real pref = Real(34.986836655249725) / (p * qq * sqrt(pq)) * P.K * Q.K;
-                    V[1 + lane] = pref * coop_boys_r<Real>(lane, T, bt);
-                }
-                if (lane == 32) {
-                    c[kC0] = Real(0);
-                    c[kPA + 0] = P.PAx; c[kPA + 1] = P.PAy; c[kPA + 2] = P.PAz;
-                    c[kWP + 0] = -qq * rpq * PQx; c[kWP + 1] = -qq * rpq * PQy; c[kWP + 2] = -qq * rpq * PQz;
-                    c[kQC + 0] = Q.PAx; c[kQC + 1] = Q.PAy; c[kQC + 2] = Q.PAz;
-                    c[kWQ + 0] = p * rpq * PQx; c[kWQ + 1] = p * rpq * PQy; c[kWQ + 2] = p * rpq * PQz;
-                    c[kO2P] = Real(0.5) / p; c[kO2PR] = Real(0.5) / p * rho / p;
-                    c[kO2Q] = Real(0.5) / qq; c[kO2QR] = Real(0.5) / qq * rho / qq;
-                    c[kO2PQ] = Real(0.5) * rpq;
+            const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+            const Real p = P.p, qq = Q.p, pq = p + qq, rpq = Real(1) / pq, rho = p * qq * rpq;
+            const Real PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
+            const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+            __syncthreads();  // previous round fully consumed
+            if (act && gl <= A.L) {
+                const Real pref = Real(34.986836655249725) / (p * qq * sqrt(pq)) * P.K * Q.K;
+                V[1 + gl] = pref * coop_boys_r<Real>(gl, T, bt);
+            }
+            VrrCoef<Real> cf;
+            cf.PA[0] = P.PAx; cf.PA[1] = P.PAy; cf.PA[2] = P.PAz;
+            cf.WP[0] = -qq * rpq * PQx; cf.WP[1] = -qq * rpq * PQy; cf.WP[2] = -qq * rpq * PQz;
+            cf.QC[0] = Q.PAx; cf.QC[1] = Q.PAy; cf.QC[2] = Q.PAz;
+            cf.WQ[0] = p * rpq * PQx; cf.WQ[1] = p * rpq * PQy; cf.WQ[2] = p * rpq * PQz;
+            cf.o2p = Real(0.5) / p; cf.o2pr = Real(0.5) / p * rho / p;
+            cf.o2q = Real(0.5) / qq; cf.o2qr = Real(0.5) / qq * rho / qq;
+            cf.o2pq = Real(0.5) * rpq;
+            __syncthreads();
+            for (int lv = 0; lv < A.nvlev; ++lv) {
+                if (act) {
+                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
+                    for (int o = b0 + gl; o < b1; o += GT) {
+                        const int4 op = A.vops[o];
+                        V[op.x & 0xffff] = run_vop<Real>(op, V, cf);
+                    }
                 }
                 __syncthreads();
-                for (int lv = 0; lv < A.nvlev; ++lv) {
-                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
-                    for (int o = b0 + lane; o < b1; o += 64) {
-                        const int4 op = A.vops[o];
-                        V[op.x & 0xffff] = run_op_r<Real>(op, V, c);
-                    }
-                    __syncthreads();
-                }
-                for (int s = lane; s < A.nacc; s += 64) H[s] += (double)V[A.accsrc[s]];
+            }
+            const int nact = npq - r0 < NP ? npq - r0 : NP;
+            for (int s = lane; s < A.nacc; s += NT) {
+                const int src = A.accsrc[s];
+                double acc = 0.0;
+                for (int g = 0; g < nact; ++g) acc += (double)V0[(size_t)g * vstride + src];
+                H[s] += acc;
             }
         }
         __syncthreads();
-        coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);
+        coop_finish<MODE, NT>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);
         __syncthreads();  // H reused by the next quartet
     }
 }
@@ -491,20 +654,30 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
         return MESS_OK;
     }
     const size_t rsz = prec == MESS_FP32 ? sizeof(float) : sizeof(double);
-    const int region = (int)std::max<size_t>((P->nV * rsz + 7) / 8, (size_t)(P->nH - P->nacc));
-    const size_t lds = sizeof(double) * ((size_t)P->nacc + region + (kNCoef * rsz + 7) / 8 + kNHCoef);
+    // primitive quartets in flight per block: two for (dd|dp), whose levels
+    // are too small to keep 256 threads busy, one otherwise
+    const int np = (cb == 5 && ck == 4) ? 2 : 1;
+    const int vstride = (int)(((size_t)P->nV * rsz + 7) / 8 * 8 / rsz);  // whole doubles per region
+    const int region = (int)std::max<size_t>((np * (size_t)vstride * rsz + 7) / 8, (size_t)(P->nH - P->nacc));
+    const size_t lds = sizeof(double) * ((size_t)P->nacc + region + kNHCoef);
     if (lds > 64 * 1024) {
         set_error("internal: class (%d,%d) needs %zu bytes of LDS", cb, ck, lds);
         return MESS_E_UNSUPPORTED;
     }
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
-#define MESS_COOP_GO(MODE, R, PP)                                                                                 \
-    hipLaunchKernelGGL((k_coop<MODE, R>), dim3((unsigned)g), dim3(64), lds, L.stream, A, region, L.pairs,        \
-                       L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, PP, bt, D, L.N, out0, out1)
-#define MESS_COOP_M(MODE)                                            \
-    do {                                                             \
-        if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf);     \
-        else MESS_COOP_GO(MODE, double, L.pp);                       \
+#define MESS_COOP_GO(MODE, R, PP, NPV)                                                                            \
+    hipLaunchKernelGGL((k_coop<MODE, R, 256, NPV>), dim3((unsigned)g), dim3(256), lds, L.stream, A, region,      \
+                       vstride, L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, \
+                       PP, bt, D, L.N, out0, out1)
+#define MESS_COOP_M(MODE)                                                            \
+    do {                                                                             \
+        if (np == 2) {                                                               \
+            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 2);              \
+            else MESS_COOP_GO(MODE, double, L.pp, 2);                                \
+        } else {                                                                     \
+            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 1);              \
+            else MESS_COOP_GO(MODE, double, L.pp, 1);                                \
+        }                                                                            \
     } while (0)
     switch (mode) {
         case kModeSchwarz: MESS_COOP_M(kModeSchwarz); break;

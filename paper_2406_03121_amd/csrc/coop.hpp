@@ -65,15 +65,15 @@ __device__ __forceinline__ double run_op(const int4 op, const double *__restrict
     const int a1 = w & 31, a2 = (w >> 5) & 31, a3 = (w >> 10) & 31, a4 = (w >> 15) & 31, a5 = (w >> 20) & 31;
     const double k3 = (double)((w >> 25) & 7), k5 = (double)((w >> 28) & 7);
     double v = c[a1] * V[s1] + c[a2] * V[s2];
-    v += k3 * (c[a3] * V[s3] - c[a4] * V[s4]);
-    v += k5 * c[a5] * V[s5];
+    if (k3 != 0.0) v += k3 * (c[a3] * V[s3] - c[a4] * V[s4]);
+    if (k5 != 0.0) v += k5 * c[a5] * V[s5];
     return v;
 }
 
 // J/K digestion of one quartet's block by a wave: lanes over the elements of
 // the six target families Gj[a,b], Gj[c,d], Gk[a,c], Gk[b,c], Gk[a,d],
 // Gk[b,d] (each a sum over the block weighted by density elements).
-template <typename OF>
+template <int NT = 64, typename OF>
 __device__ __forceinline__ void wave_digest(const int lane, const int NA, const int NB, const int NC, const int ND,
                                             const double fac, const int a0, const int b0, const int c0, const int d0,
                                             OF &&O, const double *__restrict__ D, const int N,
@@ -83,7 +83,7 @@ __device__ __forceinline__ void wave_digest(const int lane, const int NA, const 
     const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
     const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0, t_bd = Gk ? NB * ND : 0;
     const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
-    for (int t = lane; t < ntgt; t += 64) {
+    for (int t = lane; t < ntgt; t += NT) {
         int r = t;
         double s = 0.0;
         if (r < t_ab) {
@@ -137,7 +137,8 @@ __device__ __forceinline__ void wave_digest(const int lane, const int NA, const 
 
 // Horizontal recursion of the accumulated [e0|f0] (in H[0, nacc)) and the
 // per-mode output of one quartet, shared by the wave.
-template <int MODE>
+// NT: threads of the block sharing the quartet (lane = thread index).
+template <int MODE, int NT = 64>
 __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restrict__ H, double *__restrict__ hc,
                                             const int lane, const PairInfo &bra, const PairInfo &ket, const int i,
                                             const int j, const int bra_off, const int same_class,
@@ -151,7 +152,7 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
         __syncthreads();
         for (int lv = 0; lv < A.nhlev; ++lv) {
             const int b0 = A.hlev[lv], b1 = A.hlev[lv + 1];
-            for (int o = b0 + lane; o < b1; o += 64) {
+            for (int o = b0 + lane; o < b1; o += NT) {
                 const int4 op = A.hops[o];
                 H[op.x & 0xffff] = run_op(op, H, hc);
             }
@@ -171,14 +172,14 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
                 out0[bra_off + i] = sqrt(m);
             }
         } else if (MODE == kModeStore64 || MODE == kModeStore32) {
-            for (int o = lane; o < A.nout; o += 64) {
+            for (int o = lane; o < A.nout; o += NT) {
                 const double v = H[A.outslot[o]] * A.outscale[o];
                 if (MODE == kModeStore64) out0[(int64_t)o * total + q] = v;
                 else reinterpret_cast<float *>(out0)[(int64_t)o * total + q] = (float)v;
             }
         } else if (MODE == kModeDense) {
             const int64_t NN = N;
-            for (int o = lane; o < A.nout; o += 64) {
+            for (int o = lane; o < A.nout; o += NT) {
                 const int d = o % ND, cc = (o / ND) % NC, b = (o / (ND * NC)) % NB, a = o / (ND * NC * NB);
                 const double v = H[A.outslot[o]] * A.outscale[o];
                 const int64_t ia = bra.bfa + a, ib = bra.bfb + b, ic = ket.bfa + cc, id = ket.bfb + d;
@@ -196,8 +197,8 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
             if (bra.sa == bra.sb) fac *= 0.5;
             if (ket.sa == ket.sb) fac *= 0.5;
             if (same_class && i == j) fac *= 0.5;
-            wave_digest(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D + bra.moff, bra.mN,
-                        out0 ? out0 + bra.moff : nullptr, out1 ? out1 + bra.moff : nullptr);
+            wave_digest<NT>(lane, NA, NB, NC, ND, fac, bra.bfa, bra.bfb, ket.bfa, ket.bfb, O, D + bra.moff, bra.mN,
+                            out0 ? out0 + bra.moff : nullptr, out1 ? out1 + bra.moff : nullptr);
         }
 }
 
