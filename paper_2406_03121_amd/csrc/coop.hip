@@ -589,10 +589,19 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
             __syncthreads();
             for (int lv = 0; lv < A.nvlev; ++lv) {
                 if (act) {
+                    // the steps of a level are independent: fetch up to four
+                    // of this thread's steps before running them
                     const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
-                    for (int o = b0 + gl; o < b1; o += GT) {
-                        const int4 op = A.vops[o];
-                        V[op.x & 0xffff] = run_vop<Real>(op, V, cf);
+                    for (int c0 = b0 + gl; c0 < b1; c0 += 4 * GT) {
+                        int4 op[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int o = c0 + r * GT;
+                            op[r] = o < b1 ? A.vops[o] : make_int4(0, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (c0 + r * GT < b1) V[op[r].x & 0xffff] = run_vop<Real>(op[r], V, cf);
                     }
                 }
                 __syncthreads();
@@ -655,7 +664,8 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     }
     const size_t rsz = prec == MESS_FP32 ? sizeof(float) : sizeof(double);
     // primitive quartets in flight per block: two for (dd|dp), whose levels
-    // are too small to keep 256 threads busy, one otherwise
+    // are too small to keep 256 threads busy on one (measured: four for
+    // (dd|dp) and two for (dd|dd) are slower)
     const int np = (cb == 5 && ck == 4) ? 2 : 1;
     const int vstride = (int)(((size_t)P->nV * rsz + 7) / 8 * 8 / rsz);  // whole doubles per region
     const int region = (int)std::max<size_t>((np * (size_t)vstride * rsz + 7) / 8, (size_t)(P->nH - P->nacc));
@@ -671,7 +681,10 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
                        PP, bt, D, L.N, out0, out1)
 #define MESS_COOP_M(MODE)                                                            \
     do {                                                                             \
-        if (np == 2) {                                                               \
+        if (np == 4) {                                                               \
+            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 4);              \
+            else MESS_COOP_GO(MODE, double, L.pp, 4);                                \
+        } else if (np == 2) {                                                        \
             if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 2);              \
             else MESS_COOP_GO(MODE, double, L.pp, 2);                                \
         } else {                                                                     \
