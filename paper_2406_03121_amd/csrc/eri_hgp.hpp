@@ -301,10 +301,13 @@ __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo 
         static_for<0, Dm::NEA>([&](auto E) { acc[decltype(F)::value][decltype(E)::value] = Real(0); });
     });
     const Real AC[3] = {Real(bra.Ax - ket.Ax), Real(bra.Ay - ket.Ay), Real(bra.Az - ket.Az)};
-    for (int ib = 0; ib < bra.npp; ++ib) {
-        const PrimPairT<Real> P = pp[bra.pp0 + ib];
-        for (int ik = 0; ik < ket.npp; ++ik) {
-            const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+    // Lanes of a wave take consecutive quartets of one bra row: the ket's
+    // primitive pairs (different for every lane) are read once each, the
+    // bra's (the same for the wave) in the inner loop.
+    for (int ik = 0; ik < ket.npp; ++ik) {
+        const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+        for (int ib = 0; ib < bra.npp; ++ib) {
+            const PrimPairT<Real> P = pp[bra.pp0 + ib];
             prim_quartet<Dm, Real>(P, Q, AC, bt, acc);
         }
     }
