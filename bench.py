@@ -279,10 +279,15 @@ def main():
         torch.cuda.synchronize()
         t5 = time.perf_counter()
         sb, sms = 0.0, 0.0
+        spc = {}
+        nb = max(1, a.steps * (rst[-1][1] - 1))
         for c in range(21):
             r = mess.mess_prof_read(32 + c)
             sb += r["alg_flops"]
             sms += r["ms"]
+            if r["launches"] and r["ms"] > 0:
+                spc[CLASS_NAMES[c]] = {"ms_per_build": round(r["ms"] / nb, 3),
+                                       "gbps": round(r["alg_flops"] / (r["ms"] * 1e-3) / 1e9, 1)}
         mess.mess_prof_enable(False)
         stored = {"ms_per_step": (t5 - t4) / a.steps * 1e3, "molecules_per_s": a.steps / (t5 - t4),
                   "scf_iterations": rst[-1][1], "energy_hartree": rst[-1][0],
@@ -290,7 +295,8 @@ def main():
                   "jk_stream_bytes_per_build": sb / max(1, a.steps * (rst[-1][1] - 1)),
                   "jk_stream_ms_per_build": sms / max(1, a.steps * (rst[-1][1] - 1)),
                   "jk_gbps": sb / (sms * 1e-3) / 1e9 if sms > 0 else None,
-                  "speedup_vs_direct": (a.steps / (t5 - t4)) / line["molecules_per_s"]}
+                  "speedup_vs_direct": (a.steps / (t5 - t4)) / line["molecules_per_s"],
+                  "per_class_stream": spc}
         line["stored_jk"] = stored
         line["jk_gbps"] = stored["jk_gbps"]
         log(f"stored: {stored}")

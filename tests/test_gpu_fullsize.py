@@ -48,3 +48,29 @@ def test_water60_sampled_jk():
     for k in range(len(mu)):
         assert abs(J0h[mu[k], nu[k]] - Jo[k]) < 1e-10 * max(1.0, abs(Jo[k])), (k, J0h[mu[k], nu[k]], Jo[k])
         assert abs(K0h[mu[k], nu[k]] - Ko[k]) < 1e-10 * max(1.0, abs(Ko[k])), (k, K0h[mu[k], nu[k]], Ko[k])
+
+
+def test_water60_scf_matches_golden():
+    """The full 60-atom SCF (Schwarz 1e-10, DIIS 8, core guess) against the
+    oracle's converged run stored by tests/golden/make_water60_golden.py:
+    every iteration's energy and the converged energy."""
+    import json
+    mess = need_gpu()
+    path = os.path.join(os.path.dirname(__file__), "golden", "water60_spd_seed0_rhf.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    ref = json.load(open(path))
+    mol = G.water_cluster(0)
+    announce("water60 SCF vs golden")
+    B = mess.basis_from_molecule(mol)
+    st = mess.mess_scf_create(B, schwarz_tol=ref["schwarz_tol"], conv_tol=ref["conv_tol"], diis_size=ref["diis"])
+    es = []
+    for _ in range(40):
+        e, de, r, c = mess.mess_scf_step(st)
+        es.append(e)
+        if c:
+            break
+    assert c
+    assert abs(es[-1] - ref["energy"]) < 1e-9, (es[-1], ref["energy"])
+    for k in range(min(len(es), len(ref["energies"]))):
+        assert abs(es[k] - ref["energies"][k]) < 1e-7 * abs(ref["energies"][k]), k
