@@ -488,22 +488,41 @@ __device__ __forceinline__ Real sel3(int d, Real a0, Real a1, Real a2) {
     return d == 0 ? a0 : (d == 1 ? a1 : a2);
 }
 
-// One vertical step: side (bra/ket) and direction from op.w bits 0-2,
+// One vertical step of a bra (KET = false) or ket level, direction from
+// op.w bits 0-1:
 // v = c1 V[s1] + c2 V[s2] + k3 (c3 V[s3] - c4 V[s4]) + k5 / (2(p+q)) V[s5].
-template <typename Real>
+template <bool KET, typename Real>
 __device__ __forceinline__ Real run_vop(const int4 op, const Real *__restrict__ V, const VrrCoef<Real> &c) {
     const int s1 = op.x >> 16, s2 = op.y & 0xffff;
-    const int w = op.w, dir = w & 3, k3 = (w >> 25) & 7, k5 = (w >> 28) & 7;
-    const bool ket = (w >> 2) & 1;
-    const Real c1 = ket ? sel3(dir, c.QC[0], c.QC[1], c.QC[2]) : sel3(dir, c.PA[0], c.PA[1], c.PA[2]);
-    const Real c2 = ket ? sel3(dir, c.WQ[0], c.WQ[1], c.WQ[2]) : sel3(dir, c.WP[0], c.WP[1], c.WP[2]);
+    const int w = op.w, dir = w & 3, k3 = (w >> 25) & 7;
+    const Real c1 = KET ? sel3(dir, c.QC[0], c.QC[1], c.QC[2]) : sel3(dir, c.PA[0], c.PA[1], c.PA[2]);
+    const Real c2 = KET ? sel3(dir, c.WQ[0], c.WQ[1], c.WQ[2]) : sel3(dir, c.WP[0], c.WP[1], c.WP[2]);
     Real v = c1 * V[s1] + c2 * V[s2];
-    if (k3) {
-        const Real c3 = ket ? c.o2q : c.o2p, c4 = ket ? c.o2qr : c.o2pr;
-        v += (Real)k3 * (c3 * V[op.y >> 16] - c4 * V[op.z & 0xffff]);
+    if (k3) v += (Real)k3 * ((KET ? c.o2q : c.o2p) * V[op.y >> 16] - (KET ? c.o2qr : c.o2pr) * V[op.z & 0xffff]);
+    if (KET) {
+        const int k5 = (w >> 28) & 7;
+        if (k5) v += (Real)k5 * c.o2pq * V[op.z >> 16];
     }
-    if (k5) v += (Real)k5 * c.o2pq * V[op.z >> 16];
     return v;
+}
+
+template <bool KET, int GT, typename Real>
+__device__ __forceinline__ void run_level(const CoopArgs &A, int lv, int gl, Real *__restrict__ V,
+                                          const VrrCoef<Real> &cf) {
+    // the steps of a level are independent: fetch up to four of this
+    // thread's steps before running them
+    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
+    for (int c0 = b0 + gl; c0 < b1; c0 += 4 * GT) {
+        int4 op[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = c0 + r * GT;
+            op[r] = o < b1 ? A.vops[o] : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (c0 + r * GT < b1) V[op[r].x & 0xffff] = run_vop<KET, Real>(op[r], V, cf);
+    }
 }
 
 // F_m(T) in the kernel's arithmetic: FP64 form above, or FP32 Taylor for
@@ -587,23 +606,12 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
             cf.o2q = Real(0.5) / qq; cf.o2qr = Real(0.5) / qq * rho / qq;
             cf.o2pq = Real(0.5) * rpq;
             __syncthreads();
-            for (int lv = 0; lv < A.nvlev; ++lv) {
-                if (act) {
-                    // the steps of a level are independent: fetch up to four
-                    // of this thread's steps before running them
-                    const int b0 = A.vlev[lv], b1 = A.vlev[lv + 1];
-                    for (int c0 = b0 + gl; c0 < b1; c0 += 4 * GT) {
-                        int4 op[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int o = c0 + r * GT;
-                            op[r] = o < b1 ? A.vops[o] : make_int4(0, 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (c0 + r * GT < b1) V[op[r].x & 0xffff] = run_vop<Real>(op[r], V, cf);
-                    }
-                }
+            for (int lv = 0; lv < A.nvbra; ++lv) {
+                if (act) run_level<false, GT, Real>(A, lv, gl, V, cf);
+                __syncthreads();
+            }
+            for (int lv = A.nvbra; lv < A.nvlev; ++lv) {
+                if (act) run_level<true, GT, Real>(A, lv, gl, V, cf);
                 __syncthreads();
             }
             const int nact = npq - r0 < NP ? npq - r0 : NP;
@@ -653,6 +661,7 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     A.hops = P->d_hops; A.hlev = P->d_hlev; A.outslot = P->d_outslot; A.outscale = P->d_outscale;
     A.nV = P->nV; A.nH = P->nH; A.nacc = P->nacc; A.nout = P->nout;
     A.nvlev = P->nvlev; A.nhlev = P->nhlev; A.L = P->L;
+    A.nvbra = P->LA + P->LB;
     A.NA = ncart(P->LA); A.NB = ncart(P->LB); A.NC = ncart(P->LC); A.ND = ncart(P->LD);
     int64_t g = total;
     if (g > (1 << 20)) g = 1 << 20;

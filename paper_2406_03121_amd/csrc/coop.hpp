@@ -32,6 +32,7 @@ struct CoopArgs {
     const unsigned short *outslot;
     const double *outscale;
     int nV, nH, nacc, nout, nvlev, nhlev, L;
+    int nvbra;  // VRR levels [0, nvbra) are bra steps, the rest ket steps
     int NA, NB, NC, ND;
 };
 
