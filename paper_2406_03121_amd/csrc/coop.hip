@@ -589,12 +589,12 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
             const int ib = act ? pidx / ket.npp : 0, ik = act ? pidx % ket.npp : 0;
             const PrimPairT<Real> P = pp[bra.pp0 + ib];
             const PrimPairT<Real> Q = pp[ket.pp0 + ik];
-            const Real p = P.p, qq = Q.p, pq = p + qq, rpq = Real(1) / pq, rho = p * qq * rpq;
+            const Real p = P.p, qq = Q.p, pq = p + qq, spq = rsqrt_nr(pq), rpq = spq * spq, rho = p * qq * rpq;
             const Real PQx = ACx + (P.PAx - Q.PAx), PQy = ACy + (P.PAy - Q.PAy), PQz = ACz + (P.PAz - Q.PAz);
             const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
             __syncthreads();  // previous round fully consumed
             if (act && gl <= A.L) {
-                const Real pref = Real(34.986836655249725) / (p * qq * sqrt(pq)) * P.K * Q.K;
+                const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
                 V[1 + gl] = pref * coop_boys_r<Real>(gl, T, bt);
             }
             VrrCoef<Real> cf;
@@ -602,8 +602,8 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
             cf.WP[0] = -qq * rpq * PQx; cf.WP[1] = -qq * rpq * PQy; cf.WP[2] = -qq * rpq * PQz;
             cf.QC[0] = Q.PAx; cf.QC[1] = Q.PAy; cf.QC[2] = Q.PAz;
             cf.WQ[0] = p * rpq * PQx; cf.WQ[1] = p * rpq * PQy; cf.WQ[2] = p * rpq * PQz;
-            cf.o2p = Real(0.5) / p; cf.o2pr = Real(0.5) / p * rho / p;
-            cf.o2q = Real(0.5) / qq; cf.o2qr = Real(0.5) / qq * rho / qq;
+            cf.o2p = Real(0.5) * P.rp; cf.o2pr = Real(0.5) * P.rp * (qq * rpq);
+            cf.o2q = Real(0.5) * Q.rp; cf.o2qr = Real(0.5) * Q.rp * (p * rpq);
             cf.o2pq = Real(0.5) * rpq;
             __syncthreads();
             for (int lv = 0; lv < A.nvbra; ++lv) {

@@ -24,6 +24,21 @@ namespace mess {
 // e^{-T} < 1e-26 relative to every F_n, n <= 8, there) and the upward
 // recurrence F_{n+1} = (2n+1) F_n / (2T).
 
+// 1/sqrt(x), x > 0: the hardware estimate refined by Newton steps
+// y <- y (3 - x y^2) / 2, each of which squares the relative error (two in
+// FP64 reach rounding level, one in FP32).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
 template <int L>
 __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ tab,
                                          const double *__restrict__ etab, double (&F)[L + 1]) {
@@ -56,8 +71,8 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
             });
         }
     } else {
-        const double rT = 1.0 / T;
-        F[0] = 0.5 * sqrt(M_PI * rT);
+        const double sT = rsqrt_nr(T), rT = sT * sT;
+        F[0] = 0.88622692545275801365 * sT;  // sqrt(pi) / 2
         static_for<0, L>([&](auto I) {
             constexpr int m = decltype(I)::value;
             F[m + 1] = F[m] * ((2 * m + 1) * 0.5) * rT;
@@ -156,12 +171,14 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
     constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LCD = Dm::LCD;
     const Real p = P.p, q = Q.p;
     const Real pq = p + q;
-    const Real rpq = Real(1) / pq;
+    // one reciprocal square root serves 1/(p+q) and the prefactor
+    const Real spq = rsqrt_nr(pq);
+    const Real rpq = spq * spq;
     const Real rho = p * q * rpq;
     const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
     const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    // 2 pi^{5/2} = 34.986836655249725
-    const Real pref = Real(34.986836655249725) / (p * q * sqrt(pq)) * P.K * Q.K;
+    // 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd, 2 pi^{5/2} = 34.986836655249725
+    const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
 
     Real F[L + 1];
     boys_eval<L, Real>(T, bt, F);
@@ -173,7 +190,7 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
         const Real PA[3] = {P.PAx, P.PAy, P.PAz};
         // W - P = q/(p+q) (Q - P)
         const Real WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
-        const Real oo2p = Real(0.5) / p, rho_p = rho / p;
+        const Real oo2p = Real(0.5) * P.rp, rho_p = q * rpq;  // rho/p = q/(p+q)
         static_for<1, NE>([&](auto EI) {
             constexpr int e = decltype(EI)::value;
             constexpr Cart c = cart_of(e);
@@ -195,7 +212,7 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
         const Real QC[3] = {Q.PAx, Q.PAy, Q.PAz};
         // W - Q = p/(p+q) (P - Q)
         const Real WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
-        const Real oo2q = Real(0.5) / q, rho_q = rho / q, oo2pq = Real(0.5) * rpq;
+        const Real oo2q = Real(0.5) * Q.rp, rho_q = p * rpq, oo2pq = Real(0.5) * rpq;  // rho/q = p/(p+q)
         static_for<1, NF>([&](auto FI) {
             constexpr int f = decltype(FI)::value;
             constexpr Cart cf = cart_of(f);
