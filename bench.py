@@ -79,11 +79,11 @@ def cpu_baseline(mol, target_seconds):
         return np.array(out, dtype=np.int32)
 
     core.lib()
-    n = 200
+    n = 5000
     t = time.perf_counter()
     core.eri_quartet_list(mol, sample(n))
     dt = time.perf_counter() - t
-    n2 = int(max(200, min(200000, n * target_seconds / max(dt, 1e-3))))
+    n2 = int(max(5000, min(5000000, n * target_seconds / max(dt, 1e-3))))
     q = sample(n2)
     t = time.perf_counter()
     core.eri_quartet_list(mol, q)
@@ -92,6 +92,23 @@ def cpu_baseline(mol, target_seconds):
     return {"value": n2 / dt, "unit": "shell quartets/s", "cores": threads, "kind": "oracle",
             "sample": f"{n2} unique shell quartets of {mol.name} drawn uniformly (unscreened), "
                       f"FP64 McMurchie-Davidson oracle, {dt:.1f} s"}
+
+
+def recorded_traffic(class_name):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-scaled), or None when it
+    covers another class or its kernel sources have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_counters_dd_dp_water60.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("class") != class_name:
+        return None
+    h = hashlib.sha256()
+    for src in d["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return d["hbm_bytes_per_launch"] if h.hexdigest() == d["sources_sha256"] else None
 
 
 def lda_block(mess, mol, a, torch):
@@ -244,7 +261,8 @@ def main():
                       for c in sorted(per)},
         "roofline": {"kernel": f"ERI/JK class {CLASS_NAMES[dom]}", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None},
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": recorded_traffic(CLASS_NAMES[dom])},
         "cpu_baseline": None,
     }
     golden = os.path.join(ROOT, "tests", "golden", f"{mol.name.replace('/', '_')}_rhf.json")
