@@ -150,14 +150,16 @@ def lda_block(mess, mol, a, torch):
             "scf_s": t2 - t1, "scf_iterations": it, "scf_converged": bool(conv), "energy_hartree": e}
 
 
-def batch_block(mess, a, torch):
+def batch_block(mess, a, torch, jk_mode=0):
     """Batched SCF over many small molecules (seeds 1000...), one HIP graph
-    per step, a fixed number of steps."""
+    per step, a fixed number of steps; jk_mode 1 stores the integral blocks
+    at set-up and streams them in every step."""
     from mess_inputs import generators as G
     mols = G.batch_of_molecules(a.batch_molecules)
     t0 = time.perf_counter()
     B = mess.mess_batch_create(mols)
-    bs = mess.mess_batch_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, use_graph=True)
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, use_graph=True,
+                                    jk_mode=jk_mode)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     conv_hist = []
@@ -324,6 +326,9 @@ def main():
     if not a.no_batch:
         line["batch"] = batch_block(mess, a, torch)
         log(f"batch: {line['batch']}")
+        if not a.no_stored:
+            line["batch_stored_jk"] = batch_block(mess, a, torch, jk_mode=mess.MESS_JK_STORED)
+            log(f"batch (stored J/K): {line['batch_stored_jk']}")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a quartet sample")
         line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
