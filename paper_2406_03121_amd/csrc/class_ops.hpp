@@ -19,6 +19,10 @@ struct ClassLaunch {
     int64_t total;
     int N;
     hipStream_t stream;
+    // stored-block digestion by bra-row segments (NULL: one lane per quartet)
+    const int4 *segs = nullptr;  // {bra row, first quartet, end quartet, 0}
+    int nseg = 0;
+    int nmax = 0;                // largest molecule dimension (LDS rows)
 };
 
 template <int CB, int CK>

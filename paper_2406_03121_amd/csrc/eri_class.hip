@@ -1,6 +1,8 @@
 // One angular class of shell quartets.  This file is compiled once per
 // class with -DMESS_CB=<bra pair class> -DMESS_CK=<ket pair class>, so the
 // 21 fully unrolled class kernels build in parallel.
+#include <algorithm>
+
 #include "class_ops.hpp"
 #include "eri_kernels.hpp"
 
@@ -87,6 +89,20 @@ int ClassOps<MESS_CB, MESS_CK>::jk_stored(const ClassLaunch &L, const void *base
                                           double *Gj, double *Gk) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
+    const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
+    if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
+        const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
+        if (prec == MESS_FP32)
+            hipLaunchKernelGGL((k_jk_stored_rows<Dm, float>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
+                               L.ket_off, L.same_class, L.rowstart, L.rowket0, L.segs, L.nseg,
+                               static_cast<const float *>(base), L.total, D, Gj, Gk);
+        else
+            hipLaunchKernelGGL((k_jk_stored_rows<Dm, double>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
+                               L.ket_off, L.same_class, L.rowstart, L.rowket0, L.segs, L.nseg,
+                               static_cast<const double *>(base), L.total, D, Gj, Gk);
+        MESS_LAUNCH_CHECK();
+        return MESS_OK;
+    }
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_jk_stored<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
                            L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, static_cast<const float *>(base),

@@ -206,4 +206,117 @@ __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ 
     }
 }
 
+// J/K from stored blocks, one 256-thread block per segment of one bra row
+// (at most a few thousand quartets sharing the bra pair (ab)).  Every
+// exchange family and J[a,b] index rows of the bra pair's functions, so they
+// are accumulated in LDS (K rows of a and b, NA + NB rows of the molecule's
+// N columns) and in registers (J[a,b], reduced over the wave), and flushed
+// to the half-matrices once per segment; only J[c,d] goes to global memory
+// per quartet.  This cuts the FP64 global atomics, which bound the
+// streaming digestion, by a factor of up to six for the low classes.
+template <class Dm, typename Real>
+__global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                        int same_class, const int64_t *__restrict__ rowstart,
+                                                        const int *__restrict__ rowket0, const int4 *__restrict__ segs,
+                                                        int nseg, const Real *__restrict__ base, int64_t total,
+                                                        const double *__restrict__ Dall, double *__restrict__ Gjall,
+                                                        double *__restrict__ Gkall) {
+    constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND;
+    extern __shared__ double lds[];
+    for (int sidx = blockIdx.x; sidx < nseg; sidx += gridDim.x) {
+        const int4 sg = segs[sidx];
+        const int i = sg.x;
+        const PairInfo bra = pairs[bra_off + i];
+        const int N = bra.mN, a0 = bra.bfa, b0 = bra.bfb;
+        const double *D = Dall + bra.moff;
+        double *Gj = Gjall ? Gjall + bra.moff : nullptr;
+        double *Gk = Gkall ? Gkall + bra.moff : nullptr;
+        double *Ka = lds, *Kb = lds + NA * N, *Jab = lds + (NA + NB) * N;
+        const int nl = (NA + NB) * N + NA * NB;
+        for (int e = threadIdx.x; e < nl; e += 256) lds[e] = 0.0;
+        __syncthreads();
+        auto Dv = [&](int r, int c) -> Real { return Real(D[(int64_t)r * N + c]); };
+        Real Dab[NA][NB];
+        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { Dab[A][B] = Dv(a0 + A, b0 + B); }); });
+        Real jab[NA][NB];
+        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { jab[A][B] = Real(0); }); });
+        const int kb0 = rowket0 ? rowket0[i] : 0;
+        const int64_t r0 = rowstart[i];
+        for (int64_t q = sg.y + threadIdx.x; q < sg.z; q += 256) {
+            const int j = kb0 + (int)(q - r0);
+            const PairInfo ket = pairs[ket_off + j];
+            const int c0 = ket.bfa, d0 = ket.bfb;
+            Real out[Dm::NOUT];
+            static_for<0, Dm::NOUT>([&](auto I) { out[I] = base[(int64_t)decltype(I)::value * total + q]; });
+            double fac = 1.0;
+            if (bra.sa == bra.sb) fac *= 0.5;
+            if (ket.sa == ket.sb) fac *= 0.5;
+            if (same_class && i == j) fac *= 0.5;
+            auto O = [&](int a, int b, int c, int d) -> Real { return out[((a * NB + b) * NC + c) * ND + d]; };
+            if (Gj) {
+                Real Dcd[NC][ND];
+                static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) { Dcd[C][Dd] = Dv(c0 + C, d0 + Dd); }); });
+                static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                    Real s = Real(0);
+                    static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dcd[C][Dd]; }); });
+                    jab[A][B] += Real(fac) * s;
+                }); });
+                static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+                    Real s = Real(0);
+                    static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { s += O(A, B, C, Dd) * Dab[A][B]; }); });
+                    unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * fac * (double)s);
+                }); });
+            }
+            if (Gk) {
+                Real Dbd[NB][ND], Dad[NA][ND], Dbc[NB][NC], Dac[NA][NC];
+                static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { Dbd[B][Dd] = Dv(b0 + B, d0 + Dd); }); });
+                static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { Dad[A][Dd] = Dv(a0 + A, d0 + Dd); }); });
+                static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { Dbc[B][C] = Dv(b0 + B, c0 + C); }); });
+                static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { Dac[A][C] = Dv(a0 + A, c0 + C); }); });
+                static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) {
+                    Real s = Real(0);
+                    static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dbd[B][Dd]; }); });
+                    __hip_atomic_fetch_add(&Ka[A * N + c0 + C], fac * (double)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }); });
+                static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) {
+                    Real s = Real(0);
+                    static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dad[A][Dd]; }); });
+                    __hip_atomic_fetch_add(&Kb[B * N + c0 + C], fac * (double)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }); });
+                static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) {
+                    Real s = Real(0);
+                    static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dbc[B][C]; }); });
+                    __hip_atomic_fetch_add(&Ka[A * N + d0 + Dd], fac * (double)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }); });
+                static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) {
+                    Real s = Real(0);
+                    static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dac[A][C]; }); });
+                    __hip_atomic_fetch_add(&Kb[B * N + d0 + Dd], fac * (double)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }); });
+            }
+        }
+        if (Gj) {
+            // J[a,b]: sum over the wave, then the waves' sums in LDS
+            static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                double v = (double)jab[A][B];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if ((threadIdx.x & 63) == 0)
+                    __hip_atomic_fetch_add(&Jab[A * NB + B], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }); });
+        }
+        __syncthreads();
+        if (Gk)
+            for (int e = threadIdx.x; e < (NA + NB) * N; e += 256) {
+                const double v = lds[e];
+                if (v == 0.0) continue;
+                const int row = e < NA * N ? a0 + e / N : b0 + (e - NA * N) / N;
+                unsafeAtomicAdd(&Gk[(int64_t)row * N + e % N], v);
+            }
+        if (Gj)
+            for (int e = threadIdx.x; e < NA * NB; e += 256)
+                unsafeAtomicAdd(&Gj[(int64_t)(a0 + e / NB) * N + b0 + e % NB], 2.0 * Jab[e]);
+        __syncthreads();  // LDS reused by the next segment
+    }
+}
+
 }  // namespace mess
