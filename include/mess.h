@@ -84,7 +84,12 @@ typedef struct mess_scf_opts {
  *   exps[sum nprim] > 0, coefs[sum nprim] (raw contraction coefficients)
  *   charge: molecular charge (electrons = sum Z - charge)
  * Normalises the basis, builds primitive-pair tables, Schwarz factors of
- * every shell pair and nuclear repulsion, on the device.
+ * every shell pair and nuclear repulsion, on the device.  Primitive pairs
+ * whose Coulomb bound U_uv (a Gaussian majorant of the primitive product;
+ * |(uv|wx)| <= U_uv U_wx for every component) times the largest bound is
+ * below 1e-14 / (2 npp_max^2) are left out (npp_max: the most primitive
+ * pairs of one shell pair), so no contracted integral moves by more than
+ * 1e-14; every shell pair keeps at least its largest term.
  * Errors: MESS_E_ARG (NULL, index out of range, exponent <= 0 or not
  * finite, nprim < 1 or > 16), MESS_E_UNSUPPORTED (l > 2), MESS_E_NOMEM. */
 int mess_basis_create(int32_t n_atoms, const int32_t *Z, const double *xyz_bohr,
@@ -326,6 +331,9 @@ int mess_guess_judge(const mess_basis *basis, const mess_scf_opts *opts, double 
  * the recorded events. */
 int mess_work_stats(const mess_basis *basis, double schwarz_tol, int32_t cls, int64_t *quartets,
                     int64_t *prim_quartets, double *alg_flops_jk);
+/* Primitive pairs of the basis kept by the screening of mess_basis_create,
+ * and the count before it.  Host outputs, either may be NULL. */
+int mess_prim_pairs(const mess_basis *basis, int64_t *kept, int64_t *full);
 int mess_prof_enable(int32_t on);
 int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops, int64_t *quartets,
                    int64_t *prim_quartets);

@@ -74,6 +74,83 @@ static void normalise(const int l, const int np, const double *a, const double *
                  sqrt(dfact_odd(2 * l - 1));
 }
 
+// Primitive-pair screening.  For a primitive of exponent a and angular
+// momentum l, every normalised Cartesian component obeys
+//   |x^lx y^ly z^lz| e^{-a r^2} <= r^l e^{-a r^2} <= m e^{-(1-t) a r^2},
+//   m = (l / (2 t a e))^{l/2}  (t = 0 and m = 1 for l = 0, t = 1/10 otherwise),
+// times |c~| and the largest component scale (sqrt 3 for the mixed d).  The
+// product of two such bounds is a single Gaussian of exponent p' = a' + b'
+// with prefactor exp(-a'b'/p' |AB|^2); the Coulomb integral of two such
+// non-negative Gaussians is at most 2 pi^{5/2} / (p' q' sqrt(p' + q')) (F_0 <= 1),
+// and sqrt(p' + q') >= sqrt 2 (p' q')^{1/4}, so every primitive-quartet
+// contribution |(uv|wx)| <= U_uv U_wx with
+//   U_uv = w_u w_v exp(-a'b'/p' |AB|^2) 2^{1/4} pi^{5/4} p'^{-5/4}.
+// A primitive pair with U_uv max(U) below eps is dropped, eps chosen so that
+// all dropped quartets of one contracted integral together stay below
+// 1e-14 (each pair keeps at least its largest term).
+struct PrimScreen {
+    std::vector<int> pp0, npp;
+    std::vector<ushort2> uv;
+    int64_t full = 0;  // unscreened primitive pairs
+};
+
+static PrimScreen screen_prim_pairs(const std::vector<int2> &pairs_ab, const double *xyz, const std::vector<int> &sh_atom,
+                                    const std::vector<int> &sh_l, const std::vector<int> &sh_np,
+                                    const std::vector<int> &sh_prim0, const double *alpha,
+                                    const std::vector<double> &ct) {
+    const double kE = 2.718281828459045, kPi = 3.141592653589793;
+    const int nprim = (int)ct.size();
+    std::vector<double> w(nprim), ap(nprim);
+    for (size_t s = 0; s < sh_l.size(); ++s) {
+        const int l = sh_l[s];
+        const double t = l == 0 ? 0.0 : 0.1, smax = l == 2 ? std::sqrt(3.0) : 1.0;
+        for (int u = sh_prim0[s]; u < sh_prim0[s] + sh_np[s]; ++u) {
+            const double m = l == 0 ? 1.0 : std::pow(l / (2.0 * t * alpha[u] * kE), 0.5 * l);
+            w[u] = std::fabs(ct[u]) * smax * m;
+            ap[u] = (1.0 - t) * alpha[u];
+        }
+    }
+    const double c0 = std::pow(2.0, 0.25) * std::pow(kPi, 1.25);
+    auto bound = [&](int sa, int sb, int u, int v) {
+        const double *A = xyz + 3 * sh_atom[sa], *B = xyz + 3 * sh_atom[sb];
+        const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+        const int pu = sh_prim0[sa] + u, pv = sh_prim0[sb] + v;
+        const double p = ap[pu] + ap[pv];
+        return w[pu] * w[pv] * std::exp(-ap[pu] * ap[pv] / p * r2) * c0 * std::pow(p, -1.25);
+    };
+    double umax = 0.0;
+    int nppmax = 1;
+    for (const int2 &q : pairs_ab) {
+        nppmax = std::max(nppmax, sh_np[q.x] * sh_np[q.y]);
+        for (int u = 0; u < sh_np[q.x]; ++u)
+            for (int v = 0; v < sh_np[q.y]; ++v) umax = std::max(umax, bound(q.x, q.y, u, v));
+    }
+    const double eps = 1e-14 / (2.0 * (double)nppmax * (double)nppmax);
+    PrimScreen S;
+    S.pp0.reserve(pairs_ab.size());
+    S.npp.reserve(pairs_ab.size());
+    for (const int2 &q : pairs_ab) {
+        const int k0 = (int)S.uv.size();
+        S.pp0.push_back(k0);
+        double best = -1.0;
+        int bu = 0, bv = 0;
+        for (int u = 0; u < sh_np[q.x]; ++u)
+            for (int v = 0; v < sh_np[q.y]; ++v) {
+                const double b = bound(q.x, q.y, u, v);
+                if (b * umax >= eps) S.uv.push_back(make_ushort2((unsigned short)u, (unsigned short)v));
+                if (b > best) {
+                    best = b;
+                    bu = u;
+                    bv = v;
+                }
+            }
+        if ((int)S.uv.size() == k0) S.uv.push_back(make_ushort2((unsigned short)bu, (unsigned short)bv));
+        S.npp.push_back((int)S.uv.size() - k0);
+        S.full += (int64_t)sh_np[q.x] * sh_np[q.y];
+    }
+    return S;
+}
+
 // ------------------------------------------------------ device kernels
 
 struct ShellDev {
@@ -83,6 +160,7 @@ struct ShellDev {
 };
 
 __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__restrict__ pp0,
+                              const int *__restrict__ npp, const ushort2 *__restrict__ uv,
                               const ShellDev *__restrict__ sh, const double *__restrict__ alpha,
                               const double *__restrict__ ct, PairInfo *__restrict__ pairs,
                               PrimPair *__restrict__ pp) {
@@ -94,28 +172,26 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
     pi.Ax = A.x; pi.Ay = A.y; pi.Az = A.z;
     pi.ABx = A.x - B.x; pi.ABy = A.y - B.y; pi.ABz = A.z - B.z;
     pi.pp0 = pp0[i];
-    pi.npp = A.nprim * B.nprim;
+    pi.npp = npp[i];
     pi.sa = sa; pi.sb = sb;
     pi.bfa = A.bf0; pi.bfb = B.bf0;
     pi.moff = A.moff; pi.mN = A.mN;
     pairs[i] = pi;
     const double ab2 = pi.ABx * pi.ABx + pi.ABy * pi.ABy + pi.ABz * pi.ABz;
-    int k = pi.pp0;
-    for (int u = 0; u < A.nprim; ++u) {
+    for (int k = pi.pp0; k < pi.pp0 + pi.npp; ++k) {
+        const int u = uv[k].x, v = uv[k].y;
         const double a = alpha[A.prim0 + u], ca = ct[A.prim0 + u];
-        for (int v = 0; v < B.nprim; ++v, ++k) {
-            const double b = alpha[B.prim0 + v], cb = ct[B.prim0 + v];
-            const double p = a + b, rp = 1.0 / p;
-            PrimPair q;
-            q.PAx = -b * rp * pi.ABx;
-            q.PAy = -b * rp * pi.ABy;
-            q.PAz = -b * rp * pi.ABz;
-            q.p = p;
-            q.K = ca * cb * exp(-a * b * rp * ab2);
-            q.rp = rp;
-            q.pad0 = q.pad1 = 0.0;
-            pp[k] = q;
-        }
+        const double b = alpha[B.prim0 + v], cb = ct[B.prim0 + v];
+        const double p = a + b, rp = 1.0 / p;
+        PrimPair q;
+        q.PAx = -b * rp * pi.ABx;
+        q.PAy = -b * rp * pi.ABy;
+        q.PAz = -b * rp * pi.ABz;
+        q.p = p;
+        q.K = ca * cb * exp(-a * b * rp * ab2);
+        q.rp = rp;
+        q.pad0 = q.pad1 = 0.0;
+        pp[k] = q;
     }
 }
 
@@ -531,9 +607,7 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     // shell pairs (a, b) of one molecule with l_a > l_b, or l_a == l_b and
     // a >= b, grouped by class, then by molecule
     std::vector<int2> pairs_ab;
-    std::vector<int> pp0;
     std::vector<int> seg_lo, seg_hi;  // per pair: its (class, molecule) segment, relative to the class
-    int npp = 0;
     for (int c = 0; c < kNumPairClasses; ++c) {
         B->pair_class_off[c] = (int)pairs_ab.size();
         B->seg_off[c].assign(n_mol, 0);
@@ -546,8 +620,6 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
                     const int la = B->sh_l[a], lb = B->sh_l[b];
                     if (!(la > lb || (la == lb && a >= b)) || pair_class_of(la, lb) != c) continue;
                     pairs_ab.push_back(make_int2(a, b));
-                    pp0.push_back(npp);
-                    npp += B->sh_np[a] * B->sh_np[b];
                 }
             const int hi = (int)pairs_ab.size() - B->pair_class_off[c];
             B->seg_off[c][m] = lo;
@@ -560,7 +632,11 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     }
     B->pair_class_off[kNumPairClasses] = (int)pairs_ab.size();
     B->npair = (int)pairs_ab.size();
+    const PrimScreen screen =
+        screen_prim_pairs(pairs_ab, xyz, B->sh_atom, B->sh_l, B->sh_np, B->sh_prim0, exps, B->ctilde);
+    const int npp = (int)screen.uv.size();
     B->npp = npp;
+    B->npp_full = screen.full;
     std::vector<ShellDev> shd(n_shells);
     for (int s = 0; s < n_shells; ++s) {
         const int a = B->sh_atom[s], m = shell_mol[s];
@@ -569,13 +645,14 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     }
 
     int2 *d_ab = nullptr;
-    int *d_pp0 = nullptr, *d_perm = nullptr, *d_seglo = nullptr, *d_seghi = nullptr;
+    int *d_pp0 = nullptr, *d_npp = nullptr, *d_perm = nullptr, *d_seglo = nullptr, *d_seghi = nullptr;
+    ushort2 *d_uv = nullptr;
     ShellDev *d_sh = nullptr;
     double *d_alpha = nullptr, *d_ct = nullptr, *d_Qraw = nullptr;
     PairInfo *d_pairs_raw = nullptr;
     int rc = MESS_OK;
     auto cleanup = [&]() {
-        hipFree(d_ab); hipFree(d_pp0); hipFree(d_seglo); hipFree(d_seghi); hipFree(d_perm); hipFree(d_sh);
+        hipFree(d_ab); hipFree(d_pp0); hipFree(d_npp); hipFree(d_uv); hipFree(d_seglo); hipFree(d_seghi); hipFree(d_perm); hipFree(d_sh);
         hipFree(d_alpha); hipFree(d_ct); hipFree(d_Qraw); hipFree(d_pairs_raw);
     };
 #define MESS_HIPC(call)                                                                         \
@@ -590,6 +667,8 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     const int np_ = B->npair;
     MESS_HIPC(hipMalloc(&d_ab, sizeof(int2) * np_));
     MESS_HIPC(hipMalloc(&d_pp0, sizeof(int) * np_));
+    MESS_HIPC(hipMalloc(&d_npp, sizeof(int) * np_));
+    MESS_HIPC(hipMalloc(&d_uv, sizeof(ushort2) * npp));
     MESS_HIPC(hipMalloc(&d_seglo, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_seghi, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_perm, sizeof(int) * np_));
@@ -602,14 +681,16 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     MESS_HIPC(hipMalloc(&B->d_pairQ, sizeof(double) * np_));
     MESS_HIPC(hipMalloc(&B->d_pp, sizeof(PrimPair) * npp));
     MESS_HIPC(hipMemcpy(d_ab, pairs_ab.data(), sizeof(int2) * np_, hipMemcpyHostToDevice));
-    MESS_HIPC(hipMemcpy(d_pp0, pp0.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
+    MESS_HIPC(hipMemcpy(d_pp0, screen.pp0.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
+    MESS_HIPC(hipMemcpy(d_npp, screen.npp.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
+    MESS_HIPC(hipMemcpy(d_uv, screen.uv.data(), sizeof(ushort2) * npp, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_seglo, seg_lo.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_seghi, seg_hi.data(), sizeof(int) * np_, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_sh, shd.data(), sizeof(ShellDev) * n_shells, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_alpha, exps, sizeof(double) * nprim, hipMemcpyHostToDevice));
     MESS_HIPC(hipMemcpy(d_ct, B->ctilde.data(), sizeof(double) * nprim, hipMemcpyHostToDevice));
     hipStream_t s = nullptr;
-    hipLaunchKernelGGL(k_build_pairs, dim3((np_ + 127) / 128), dim3(128), 0, s, np_, d_ab, d_pp0, d_sh, d_alpha,
+    hipLaunchKernelGGL(k_build_pairs, dim3((np_ + 127) / 128), dim3(128), 0, s, np_, d_ab, d_pp0, d_npp, d_uv, d_sh, d_alpha,
                        d_ct, d_pairs_raw, B->d_pp);
     MESS_HIPC(hipGetLastError());
 
@@ -752,6 +833,16 @@ int mess_batch_info(const mess_basis *B, int32_t *n_mol, int32_t *nbf, int64_t *
 }
 
 void mess_basis_destroy(mess_basis *basis) { free_basis(basis); }
+
+int mess_prim_pairs(const mess_basis *basis, int64_t *kept, int64_t *full) {
+    if (!basis) {
+        set_error("mess_prim_pairs: NULL basis");
+        return MESS_E_ARG;
+    }
+    if (kept) *kept = basis->npp;
+    if (full) *full = basis->npp_full;
+    return MESS_OK;
+}
 
 int mess_work_stats(const mess_basis *basis, double schwarz_tol, int32_t cls, int64_t *quartets,
                     int64_t *prim_quartets, double *alg_flops_jk) {

@@ -218,7 +218,8 @@ struct mess_basis {
     double *d_pairQ = nullptr;             // Schwarz factor per sorted pair
     mess::PrimPair *d_pp = nullptr;        // primitive pairs (unsorted)
     mess::PrimPairF *d_ppf = nullptr;      // FP32 copy
-    int npp = 0;
+    int npp = 0;            // primitive pairs kept after screening
+    int64_t npp_full = 0;   // before screening
     std::vector<double> pairQ_host;        // for diagnostics
     std::vector<mess::PairInfo> pairs_host;  // sorted pairs (host copy)
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "mess_basis_create", "mess_basis_destroy", "mess_basis_info", "mess_one_electron",
     "mess_eri", "mess_jk", "mess_scf_create", "mess_scf_step", "mess_scf_density",
     "mess_scf_fock", "mess_scf_destroy", "mess_last_error",
-    "mess_work_stats", "mess_prof_enable", "mess_prof_read",
+    "mess_work_stats", "mess_prim_pairs", "mess_prof_enable", "mess_prof_read",
     "mess_batch_create", "mess_batch_info", "mess_batch_scf_create", "mess_batch_scf_step",
     "mess_batch_scf_status", "mess_batch_scf_density", "mess_batch_scf_destroy",
     "mess_lda_x", "mess_grid",
@@ -101,6 +101,7 @@ def lib():
         L.mess_batch_scf_destroy.argtypes = [vp]
         L.mess_batch_scf_destroy.restype = None
         L.mess_work_stats.argtypes = [vp, f64, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(f64)]
+        L.mess_prim_pairs.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.mess_prof_enable.argtypes = [i32]
         L.mess_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64),
                                      ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -428,6 +429,13 @@ def mess_work_stats(basis: Basis, schwarz_tol, cls):
     _check(lib().mess_work_stats(basis.handle, float(schwarz_tol), int(cls), ctypes.byref(q), ctypes.byref(p),
                                  ctypes.byref(f)), "mess_work_stats")
     return q.value, p.value, f.value
+
+
+def mess_prim_pairs(basis: Basis):
+    """(primitive pairs kept by the basis's screening, primitive pairs before it)."""
+    k, f = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mess_prim_pairs(basis.handle, ctypes.byref(k), ctypes.byref(f)), "mess_prim_pairs")
+    return k.value, f.value
 
 
 def mess_prof_enable(on=True):
