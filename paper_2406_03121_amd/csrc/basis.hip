@@ -195,18 +195,21 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
     }
 }
 
-// Rank of each pair within its (class, molecule) segment by descending Q
-// (ties by index); perm[off + seg_lo + rank] = local index.
-__global__ void k_rank_desc(const double *__restrict__ Q, int off, int n, const int *__restrict__ seg_lo,
-                            const int *__restrict__ seg_hi, int *__restrict__ perm) {
+// Rank of each pair within its (class, molecule) segment by descending
+// primitive-pair count, then descending Q (ties by index);
+// perm[off + seg_lo + rank] = local index.
+__global__ void k_rank_desc(const double *__restrict__ Q, const PairInfo *__restrict__ pairs, int off, int n,
+                            const int *__restrict__ seg_lo, const int *__restrict__ seg_hi, int *__restrict__ perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double qi = Q[off + i];
+    const int ni = pairs[off + i].npp;
     const int lo = seg_lo[off + i], hi = seg_hi[off + i];
     int rank = 0;
     for (int j = lo; j < hi; ++j) {
         const double qj = Q[off + j];
-        rank += (qj > qi) || (qj == qi && j < i);
+        const int nj = pairs[off + j].npp;
+        rank += (nj > ni) || (nj == ni && ((qj > qi) || (qj == qi && j < i)));
     }
     perm[off + lo + rank] = i;
 }
@@ -219,54 +222,6 @@ __global__ void k_gather_pairs(int off, int n, const int *__restrict__ perm,
     const int i = perm[off + r];
     dst[off + r] = src[off + i];
     Qdst[off + r] = Qsrc[off + i];
-}
-
-// Kets of bra row i: the kets of its molecule's segment [k0, k0 + nk)
-// (sorted descending) with Q_i Q_j >= tau; for a same-class list only kets
-// up to the bra itself.
-__global__ void k_row_counts(const double *__restrict__ Q, int bra_off, int nbra, int ket_off, int nket,
-                             const int *__restrict__ rowket0, const int *__restrict__ rownket, int same_class,
-                             double tau, int64_t *__restrict__ counts) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nbra) return;
-    const int k0 = rowket0 ? rowket0[i] : 0, nk = rownket ? rownket[i] : nket;
-    int cnt = nk;
-    if (tau > 0.0) {
-        const double qi = Q[bra_off + i];
-        int lo = 0, hi = nk;  // first j with qi*Q_j < tau
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (qi * Q[ket_off + k0 + mid] >= tau) lo = mid + 1; else hi = mid;
-        }
-        cnt = lo;
-    }
-    if (same_class) cnt = min(cnt, i - k0 + 1);
-    counts[i] = cnt;
-}
-
-// Exclusive scan of n counts into out[0..n] with one block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_counts(const int64_t *__restrict__ counts, int n,
-                                                      int64_t *__restrict__ out) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b = t * per, e = min(n, b + per);
-    int64_t s = 0;
-    for (int i = b; i < e; ++i) s += counts[i];
-    part[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int64_t v = t >= d ? part[t - d] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - s;  // exclusive prefix of this thread's segment
-    for (int i = b; i < e; ++i) {
-        out[i] = run;
-        run += counts[i];
-    }
-    if (t == 1023) out[n] = part[1023];
 }
 
 // ------------------------------------------------------- host helpers
@@ -282,7 +237,7 @@ static int make_class_launch(const mess_basis *B, ClassLaunch &L, hipStream_t s)
     L.N = B->nbf;
     L.stream = s;
     L.rowstart = nullptr;
-    L.rowket0 = nullptr;
+    L.rowmap = nullptr;
     L.total = 0;
     L.bra_off = L.ket_off = L.nbra = L.same_class = 0;
     return MESS_OK;
@@ -292,15 +247,16 @@ int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, C
     make_class_launch(B, L, s);
     L.bra_off = B->pair_class_off[cl.cb];
     L.ket_off = B->pair_class_off[cl.ck];
-    L.nbra = cl.nbra;
+    L.nbra = cl.nrow;
     L.same_class = cl.cb == cl.ck;
     L.rowstart = cl.d_rowstart;
-    L.rowket0 = cl.d_rowket0;
+    L.rowmap = cl.d_rowmap;
     L.total = cl.total;
     return MESS_OK;
 }
 
 int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
+    (void)s;
     if (!(tau > 0.0)) tau = 0.0;
     auto it = B->lists.find(tau);
     if (it != B->lists.end()) {
@@ -309,16 +265,8 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
     }
     auto *W = new WorkLists();
     W->tau = tau;
-    int64_t *d_counts = nullptr;
-    int maxn = 1;
-    for (int c = 0; c < kNumPairClasses; ++c)
-        maxn = std::max(maxn, B->pair_class_off[c + 1] - B->pair_class_off[c]);
-    hipError_t e = hipMalloc(&d_counts, sizeof(int64_t) * maxn);
-    if (e != hipSuccess) {
-        delete W;
-        set_error("hipMalloc(work-list counts) failed: %s", hipGetErrorString(e));
-        return MESS_E_NOMEM;
-    }
+    const std::vector<PairInfo> &P = B->pairs_host;
+    const std::vector<double> &Q = B->pairQ_host;
     int rc = MESS_OK;
     for (int cb = 0; cb < kNumPairClasses && rc == MESS_OK; ++cb)
         for (int ck = 0; ck <= cb && rc == MESS_OK; ++ck) {
@@ -326,78 +274,63 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
             cl.cb = cb;
             cl.ck = ck;
             cl.nbra = B->pair_class_off[cb + 1] - B->pair_class_off[cb];
-            const int nket = B->pair_class_off[ck + 1] - B->pair_class_off[ck];
-            if (cl.nbra == 0 || nket == 0) {
-                cl.total = 0;
-                W->classes.push_back(cl);
-                continue;
-            }
-            if (hipMalloc(&cl.d_rowstart, sizeof(int64_t) * (cl.nbra + 1)) != hipSuccess) {
-                set_error("hipMalloc(work list) failed");
-                rc = MESS_E_NOMEM;
-                break;
-            }
-            // per bra row: its molecule's ket segment
-            std::vector<int> rk0, rnk;
-            int *d_rnk = nullptr;
-            if (B->n_mol > 1) {
-                rk0.resize(cl.nbra);
-                rnk.resize(cl.nbra);
-                for (int m = 0; m < B->n_mol; ++m)
-                    for (int r = 0; r < B->seg_cnt[cb][m]; ++r) {
-                        rk0[B->seg_off[cb][m] + r] = B->seg_off[ck][m];
-                        rnk[B->seg_off[cb][m] + r] = B->seg_cnt[ck][m];
+            const int boff = B->pair_class_off[cb], koff = B->pair_class_off[ck];
+            const bool same = cb == ck;
+            cl.h_rowstart.assign(1, 0);
+            for (int m = 0; m < B->n_mol; ++m) {
+                // buckets of equal primitive count in the molecule's ket segment
+                std::vector<int2> bk;
+                const int k0 = B->seg_off[ck][m], k1 = k0 + B->seg_cnt[ck][m];
+                for (int k = k0; k < k1;) {
+                    int e = k + 1;
+                    while (e < k1 && P[koff + e].npp == P[koff + k].npp) ++e;
+                    bk.push_back(make_int2(k, e));
+                    k = e;
+                }
+                const int i0 = B->seg_off[cb][m], i1 = i0 + B->seg_cnt[cb][m];
+                for (int i = i0; i < i1; ++i) {
+                    const double qi = Q[boff + i];
+                    const int64_t nbp = P[boff + i].npp;
+                    for (const int2 &b : bk) {
+                        int cnt = b.y - b.x;
+                        if (tau > 0.0) {
+                            int lo = 0, hi = cnt;  // first ket with qi Q_j < tau
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (qi * Q[koff + b.x + mid] >= tau) lo = mid + 1; else hi = mid;
+                            }
+                            cnt = lo;
+                        }
+                        if (same) cnt = std::min(cnt, std::max(0, i - b.x + 1));
+                        if (cnt <= 0) continue;
+                        cl.h_rowmap.push_back(make_int2(i, b.x));
+                        cl.h_rowstart.push_back(cl.h_rowstart.back() + cnt);
+                        cl.prim_quartets += nbp * cnt * P[koff + b.x].npp;
                     }
-                if (hipMalloc(&cl.d_rowket0, sizeof(int) * cl.nbra) != hipSuccess ||
-                    hipMalloc(&d_rnk, sizeof(int) * cl.nbra) != hipSuccess ||
-                    hipMemcpy(cl.d_rowket0, rk0.data(), sizeof(int) * cl.nbra, hipMemcpyHostToDevice) != hipSuccess ||
-                    hipMemcpy(d_rnk, rnk.data(), sizeof(int) * cl.nbra, hipMemcpyHostToDevice) != hipSuccess) {
+                }
+            }
+            cl.nrow = (int)cl.h_rowmap.size();
+            cl.total = cl.h_rowstart.back();
+            if (cl.nrow > 0) {
+                if (hipMalloc(&cl.d_rowstart, sizeof(int64_t) * (cl.nrow + 1)) != hipSuccess ||
+                    hipMalloc(&cl.d_rowmap, sizeof(int2) * cl.nrow) != hipSuccess ||
+                    hipMemcpy(cl.d_rowstart, cl.h_rowstart.data(), sizeof(int64_t) * (cl.nrow + 1),
+                              hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(cl.d_rowmap, cl.h_rowmap.data(), sizeof(int2) * cl.nrow, hipMemcpyHostToDevice) !=
+                        hipSuccess) {
                     hipFree(cl.d_rowstart);
-                    hipFree(cl.d_rowket0);
-                    hipFree(d_rnk);
+                    hipFree(cl.d_rowmap);
                     set_error("hipMalloc(work list) failed");
                     rc = MESS_E_NOMEM;
                     break;
                 }
             }
-            hipLaunchKernelGGL(k_row_counts, dim3((cl.nbra + 255) / 256), dim3(256), 0, s, B->d_pairQ,
-                               B->pair_class_off[cb], cl.nbra, B->pair_class_off[ck], nket, cl.d_rowket0, d_rnk,
-                               cb == ck ? 1 : 0, tau, d_counts);
-            hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, d_counts, cl.nbra, cl.d_rowstart);
-            cl.h_rowstart.resize(cl.nbra + 1);
-            if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(cl.h_rowstart.data(), cl.d_rowstart, sizeof(int64_t) * (cl.nbra + 1),
-                               hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                hipFree(cl.d_rowstart);
-                hipFree(cl.d_rowket0);
-                hipFree(d_rnk);
-                set_error("work-list construction failed on the device");
-                rc = MESS_E_DEVICE;
-                break;
-            }
-            hipFree(d_rnk);
-            cl.total = cl.h_rowstart[cl.nbra];
-            {
-                // primitive quartets: sum_i npp(bra_i) * sum_{j < count_i} npp(ket_j)
-                const int boff = B->pair_class_off[cb], koff = B->pair_class_off[ck];
-                std::vector<int64_t> kpre(nket + 1, 0);
-                for (int j = 0; j < nket; ++j) kpre[j + 1] = kpre[j] + B->pairs_host[koff + j].npp;
-                int64_t tot = 0;
-                for (int i = 0; i < cl.nbra; ++i) {
-                    const int64_t cnt = cl.h_rowstart[i + 1] - cl.h_rowstart[i];
-                    const int k0 = rk0.empty() ? 0 : rk0[i];
-                    tot += (int64_t)B->pairs_host[boff + i].npp * (kpre[k0 + cnt] - kpre[k0]);
-                }
-                cl.prim_quartets = tot;
-            }
             W->classes.push_back(cl);
         }
-    hipFree(d_counts);
     if (rc != MESS_OK) {
         for (auto &cl : W->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
-            if (cl.d_rowket0) hipFree(cl.d_rowket0);
+            if (cl.d_rowmap) hipFree(cl.d_rowmap);
         }
         delete W;
         return rc;
@@ -412,7 +345,7 @@ static void free_basis(mess_basis *B) {
     for (auto &kv : B->lists) {
         for (auto &cl : kv.second->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
-            if (cl.d_rowket0) hipFree(cl.d_rowket0);
+            if (cl.d_rowmap) hipFree(cl.d_rowmap);
         }
         delete kv.second;
     }
@@ -712,8 +645,8 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     for (int c = 0; c < kNumPairClasses; ++c) {
         const int off = B->pair_class_off[c], n = B->pair_class_off[c + 1] - off;
         if (n == 0) continue;
-        hipLaunchKernelGGL(k_rank_desc, dim3((n + 255) / 256), dim3(256), 0, s, d_Qraw, off, n, d_seglo, d_seghi,
-                           d_perm);
+        hipLaunchKernelGGL(k_rank_desc, dim3((n + 255) / 256), dim3(256), 0, s, d_Qraw, d_pairs_raw, off, n, d_seglo,
+                           d_seghi, d_perm);
         hipLaunchKernelGGL(k_gather_pairs, dim3((n + 255) / 256), dim3(256), 0, s, off, n, d_perm, d_pairs_raw,
                            d_Qraw, B->d_pairs, B->d_pairQ);
     }

@@ -13,14 +13,14 @@ struct ClassLaunch {
     const PrimPairF *ppf;
     const double *tab, *etab;
     const float *tabf, *etabf;
-    int bra_off, ket_off, nbra, same_class;
+    int bra_off, ket_off, nbra, same_class;  // nbra: rows of the work list
     const int64_t *rowstart;
-    const int *rowket0;  // per bra row: offset of its molecule's kets (NULL: 0)
+    const int2 *rowmap;  // per row: {bra index, first ket index}
     int64_t total;
     int N;
     hipStream_t stream;
     // stored-block digestion by bra-row segments (NULL: one lane per quartet)
-    const int4 *segs = nullptr;  // {bra row, first quartet, end quartet, 0}
+    const int4 *segs = nullptr;  // {row, first quartet, end quartet, 0}
     int nseg = 0;
     int nmax = 0;                // largest molecule dimension (LDS rows)
 };

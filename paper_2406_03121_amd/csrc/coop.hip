@@ -553,7 +553,7 @@ __device__ __forceinline__ Real coop_boys_r(int m, Real T, const BoysTabs &bt) {
 template <int MODE, typename Real, int NT, int NP>
 __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride, const PairInfo *__restrict__ pairs,
                                              int bra_off, int ket_off, int nbra, int same_class,
-                                             const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0, int64_t total,
+                                             const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap, int64_t total,
                                              const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                              const double *__restrict__ D, int N, double *__restrict__ out0,
                                              double *__restrict__ out1) {
@@ -574,8 +574,9 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
         if (MODE == kModeSchwarz) {
             i = j = (int)q;
         } else {
-            i = find_row(rowstart, nbra, q);
-            j = (rowket0 ? rowket0[i] : 0) + (int)(q - rowstart[i]);
+            const int2 ij = quartet_pairs(rowstart, rowmap, nbra, q);
+            i = ij.x;
+            j = ij.y;
         }
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
@@ -686,7 +687,7 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
 #define MESS_COOP_GO(MODE, R, PP, NPV)                                                                            \
     hipLaunchKernelGGL((k_coop<MODE, R, 256, NPV>), dim3((unsigned)g), dim3(256), lds, L.stream, A, region,      \
-                       vstride, L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, \
+                       vstride, L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, \
                        PP, bt, D, L.N, out0, out1)
 #define MESS_COOP_M(MODE)                                                            \
     do {                                                                             \
@@ -738,14 +739,14 @@ namespace mess {
 // structure-of-arrays store.
 template <typename Real>
 __global__ void __launch_bounds__(64) k_jk_stored_wave(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
-                                                      int nbra, int same_class, const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
+                                                      int nbra, int same_class, const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
                                                       int64_t total, int NA, int NB, int NC, int ND,
                                                       const Real *__restrict__ base, const double *__restrict__ D, int N,
                                                       double *__restrict__ Gj, double *__restrict__ Gk) {
     const int lane = threadIdx.x;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
-        const int i = find_row(rowstart, nbra, q);
-        const int j = (rowket0 ? rowket0[i] : 0) + (int)(q - rowstart[i]);
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, q);
+        const int i = ij.x, j = ij.y;
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         double fac = 1.0;
@@ -774,11 +775,11 @@ int coop_jk_stored(int cb, int ck, const ClassLaunch &L, const void *base, int p
               ND = ncart(pair_class_lb(ck));
     if (prec == MESS_FP32)
         hipLaunchKernelGGL(k_jk_stored_wave<float>, dim3((unsigned)g), dim3(64), 0, L.stream, L.pairs, L.bra_off,
-                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, L.total, NA, NB, NC, ND,
+                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.total, NA, NB, NC, ND,
                            static_cast<const float *>(base), D, L.N, Gj, Gk);
     else
         hipLaunchKernelGGL(k_jk_stored_wave<double>, dim3((unsigned)g), dim3(64), 0, L.stream, L.pairs, L.bra_off,
-                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, L.total, NA, NB, NC, ND,
+                           L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.total, NA, NB, NC, ND,
                            static_cast<const double *>(base), D, L.N, Gj, Gk);
     MESS_LAUNCH_CHECK();
     return MESS_OK;

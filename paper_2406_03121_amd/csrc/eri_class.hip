@@ -43,10 +43,10 @@ int ClassOps<MESS_CB, MESS_CK>::dense(const ClassLaunch &L, double *eri, int pre
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_eri_dense<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
-                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowket0, L.ppf, bt, (int64_t)L.N, eri);
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.ppf, bt, (int64_t)L.N, eri);
     else
         hipLaunchKernelGGL((k_eri_dense<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
-                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowket0, L.pp, bt, (int64_t)L.N, eri);
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.pp, bt, (int64_t)L.N, eri);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
@@ -59,11 +59,11 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_jk_direct<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
-                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, L.ppf, bt, D, L.N, Gj,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.ppf, bt, D, L.N, Gj,
                            Gk);
     else
         hipLaunchKernelGGL((k_jk_direct<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
-                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, L.pp, bt, D, L.N, Gj,
+                           L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.pp, bt, D, L.N, Gj,
                            Gk);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
@@ -76,10 +76,10 @@ int ClassOps<MESS_CB, MESS_CK>::store(const ClassLaunch &L, void *base, int prec
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_eri_store<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowket0, L.ppf, bt, static_cast<float *>(base));
+                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.ppf, bt, static_cast<float *>(base));
     else
         hipLaunchKernelGGL((k_eri_store<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowket0, L.pp, bt, static_cast<double *>(base));
+                           L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.pp, bt, static_cast<double *>(base));
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
@@ -94,22 +94,22 @@ int ClassOps<MESS_CB, MESS_CK>::jk_stored(const ClassLaunch &L, const void *base
         const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
         if (prec == MESS_FP32)
             hipLaunchKernelGGL((k_jk_stored_rows<Dm, float>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
-                               L.ket_off, L.same_class, L.rowstart, L.rowket0, L.segs, L.nseg,
+                               L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                static_cast<const float *>(base), L.total, D, Gj, Gk);
         else
             hipLaunchKernelGGL((k_jk_stored_rows<Dm, double>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
-                               L.ket_off, L.same_class, L.rowstart, L.rowket0, L.segs, L.nseg,
+                               L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                static_cast<const double *>(base), L.total, D, Gj, Gk);
         MESS_LAUNCH_CHECK();
         return MESS_OK;
     }
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_jk_stored<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, static_cast<const float *>(base),
+                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, static_cast<const float *>(base),
                            D, L.N, Gj, Gk);
     else
         hipLaunchKernelGGL((k_jk_stored<Dm, double>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
-                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, static_cast<const double *>(base),
+                           L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, static_cast<const double *>(base),
                            D, L.N, Gj, Gk);
     MESS_LAUNCH_CHECK();
     return MESS_OK;

@@ -19,6 +19,14 @@ __device__ __forceinline__ int find_row(const int64_t *__restrict__ rowstart, in
     return lo;
 }
 
+// (bra, ket) pair indices, relative to their classes, of quartet t.
+__device__ __forceinline__ int2 quartet_pairs(const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
+                                              int nrow, int64_t t) {
+    const int r = find_row(rowstart, nrow, t);
+    const int2 m = rowmap[r];
+    return make_int2(m.x, m.y + static_cast<int>(t - rowstart[r]));
+}
+
 // Q = sqrt(max_{a in sa, b in sb} |(ab|ab)|) for every pair of one class.
 template <class Dm>
 __global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pairs, int off, int n,
@@ -44,14 +52,14 @@ __global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pai
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra,
-                                                   const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
+                                                   const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    int64_t N, double *__restrict__ eri) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = find_row(rowstart, nbra, t);
-        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, t);
+        const int i = ij.x, j = ij.y;
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -78,14 +86,14 @@ __global__ void __launch_bounds__(128) k_eri_dense(const PairInfo *__restrict__ 
 // (structure of arrays, so that consecutive lanes touch consecutive words).
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_eri_store(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
-                                                   int nbra, const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
+                                                   int nbra, const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    Real *__restrict__ base) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = find_row(rowstart, nbra, t);
-        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, t);
+        const int i = ij.x, j = ij.y;
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -160,15 +168,15 @@ __device__ __forceinline__ void digest_jk(const Real (&out)[Dm::NOUT], double fa
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ pairs, int bra_off,
                                                    int ket_off, int nbra, int same_class,
-                                                   const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
+                                                   const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
                                                    const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                                    const double *__restrict__ D, int N,
                                                    double *__restrict__ Gj, double *__restrict__ Gk) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = find_row(rowstart, nbra, t);
-        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, t);
+        const int i = ij.x, j = ij.y;
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -185,14 +193,14 @@ __global__ void __launch_bounds__(128) k_jk_direct(const PairInfo *__restrict__ 
 // J/K from stored blocks: one lane per quartet streams its NOUT values.
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
-                                                   int nbra, int same_class, const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0,
+                                                   int nbra, int same_class, const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap,
                                                    const Real *__restrict__ base, const double *__restrict__ D,
                                                    int N, double *__restrict__ Gj, double *__restrict__ Gk) {
     const int64_t total = rowstart[nbra];
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = find_row(rowstart, nbra, t);
-        const int j = (rowket0 ? rowket0[i] : 0) + static_cast<int>(t - rowstart[i]);
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, t);
+        const int i = ij.x, j = ij.y;
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[ket_off + j];
         Real out[Dm::NOUT];
@@ -217,7 +225,7 @@ __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ 
 template <class Dm, typename Real>
 __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
                                                         int same_class, const int64_t *__restrict__ rowstart,
-                                                        const int *__restrict__ rowket0, const int4 *__restrict__ segs,
+                                                        const int2 *__restrict__ rowmap, const int4 *__restrict__ segs,
                                                         int nseg, const Real *__restrict__ base, int64_t total,
                                                         const double *__restrict__ Dall, double *__restrict__ Gjall,
                                                         double *__restrict__ Gkall) {
@@ -225,7 +233,7 @@ __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restri
     extern __shared__ double lds[];
     for (int sidx = blockIdx.x; sidx < nseg; sidx += gridDim.x) {
         const int4 sg = segs[sidx];
-        const int i = sg.x;
+        const int i = rowmap[sg.x].x;
         const PairInfo bra = pairs[bra_off + i];
         const int N = bra.mN, a0 = bra.bfa, b0 = bra.bfb;
         const double *D = Dall + bra.moff;
@@ -240,10 +248,10 @@ __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restri
         static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { Dab[A][B] = Dv(a0 + A, b0 + B); }); });
         Real jab[NA][NB];
         static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { jab[A][B] = Real(0); }); });
-        const int kb0 = rowket0 ? rowket0[i] : 0;
-        const int64_t r0 = rowstart[i];
+        int r = sg.x;  // row of this thread's quartet q (rows of one bra, in order)
         for (int64_t q = sg.y + threadIdx.x; q < sg.z; q += 256) {
-            const int j = kb0 + (int)(q - r0);
+            while (r + 1 < sg.w && rowstart[r + 1] <= q) ++r;
+            const int j = rowmap[r].y + (int)(q - rowstart[r]);
             const PairInfo ket = pairs[ket_off + j];
             const int c0 = ket.bfa, d0 = ket.bfb;
             Real out[Dm::NOUT];

@@ -151,17 +151,26 @@ inline int pair_class_of(int la, int lb) {
 }
 
 // Unique shell-quartet work list of one class: bra pairs of class cb and
-// ket pairs of class ck (cb >= ck), both sorted by Schwarz factor
-// (descending).  Bra row i holds kets [0, count_i); rowstart is the
-// exclusive scan of the counts.
+// ket pairs of class ck (cb >= ck).  Within each (class, molecule) segment
+// the pairs are sorted by primitive-pair count (descending), then by
+// Schwarz factor (descending), so a segment is a run of buckets of equal
+// primitive count, each sorted by Q.  The kets of bra i that pass
+// screening form a prefix of every bucket; the list holds one row per
+// (bra, bucket) with a non-empty prefix: rowmap[r] = {bra index, first ket
+// index}, both relative to their class, and the row's quartets are
+// [rowstart[r], rowstart[r + 1]) with ket index = first ket + (t -
+// rowstart[r]).  Lanes of a wave taking consecutive quartets then see
+// kets of (nearly) equal primitive count.
 struct ClassList {
     int cb, ck;
-    int nbra;
-    int64_t total = 0;               // shell quartets
-    int64_t prim_quartets = 0;       // sum over quartets of (bra prim pairs) x (ket prim pairs)
-    int64_t *d_rowstart = nullptr;   // nbra + 1
-    int *d_rowket0 = nullptr;        // per bra row: first ket of its molecule (NULL: 0)
-    std::vector<int64_t> h_rowstart;  // host copy
+    int nbra;                         // bra pairs of the class
+    int nrow = 0;                     // rows of the list
+    int64_t total = 0;                // shell quartets
+    int64_t prim_quartets = 0;        // sum over quartets of (bra prim pairs) x (ket prim pairs)
+    int64_t *d_rowstart = nullptr;    // nrow + 1
+    int2 *d_rowmap = nullptr;         // nrow
+    std::vector<int64_t> h_rowstart;  // host copies
+    std::vector<int2> h_rowmap;
 };
 
 // Index 0..20 of the class (cb >= ck).

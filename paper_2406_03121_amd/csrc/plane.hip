@@ -35,7 +35,7 @@ __device__ __forceinline__ void rs_step(Real (&v)[NP], const int lane) {
 template <class Dm, int MODE, typename Real>
 __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
                                               int ket_off, int nbra, int same_class,
-                                              const int64_t *__restrict__ rowstart, const int *__restrict__ rowket0, int64_t total,
+                                              const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap, int64_t total,
                                               const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
                                               const double *__restrict__ D, int N,
                                               double *__restrict__ out0, double *__restrict__ out1) {
@@ -50,8 +50,9 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
         if (MODE == kModeSchwarz) {
             i = j = (int)q;
         } else {
-            i = find_row(rowstart, nbra, q);
-            j = (rowket0 ? rowket0[i] : 0) + (int)(q - rowstart[i]);
+            const int2 ij = quartet_pairs(rowstart, rowmap, nbra, q);
+            i = ij.x;
+            j = ij.y;
         }
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
@@ -107,23 +108,23 @@ void PlaneOps<MESS_PCB, MESS_PCK, MESS_PREAL>::launch(int mode, const CoopArgs &
     switch (mode) {
         case kModeSchwarz:
             hipLaunchKernelGGL((k_plane<Dm, kModeSchwarz, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, pp, bt, D, L.N, out0, out1);
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, pp, bt, D, L.N, out0, out1);
             break;
         case kModeDense:
             hipLaunchKernelGGL((k_plane<Dm, kModeDense, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, pp, bt, D, L.N, out0, out1);
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, pp, bt, D, L.N, out0, out1);
             break;
         case kModeStore64:
             hipLaunchKernelGGL((k_plane<Dm, kModeStore64, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, pp, bt, D, L.N, out0, out1);
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, pp, bt, D, L.N, out0, out1);
             break;
         case kModeStore32:
             hipLaunchKernelGGL((k_plane<Dm, kModeStore32, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, pp, bt, D, L.N, out0, out1);
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, pp, bt, D, L.N, out0, out1);
             break;
         default:
             hipLaunchKernelGGL((k_plane<Dm, kModeJK, R>), dim3(g), dim3(64), lds, L.stream, A, L.pairs, L.bra_off,
-                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowket0, total, pp, bt, D, L.N, out0, out1);
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, pp, bt, D, L.N, out0, out1);
     }
 }
 

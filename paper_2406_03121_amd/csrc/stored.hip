@@ -33,16 +33,22 @@ void free_stored(mess_basis *B) {
     B->stored.clear();
 }
 
-// Quartets [rowstart[i], rowstart[i+1]) of every bra row i, cut into pieces
-// of at most kSegLen: {i, first, end, 0}.
+// Quartets of every bra (its consecutive rows [r0, r1) of the work list),
+// cut into pieces of at most kSegLen: {r0, first, end, r1}.
 constexpr int64_t kSegLen = 2048;
 static int build_segments(const ClassList &cl, int4 **out, int *n) {
     std::vector<int4> v;
-    for (int i = 0; i < cl.nbra; ++i)
-        for (int64_t q = cl.h_rowstart[i]; q < cl.h_rowstart[i + 1]; q += kSegLen) {
-            const int64_t e = std::min(q + kSegLen, cl.h_rowstart[i + 1]);
-            v.push_back(make_int4(i, (int)q, (int)e, 0));
+    for (int r0 = 0; r0 < cl.nrow;) {
+        int r1 = r0 + 1;
+        while (r1 < cl.nrow && cl.h_rowmap[r1].x == cl.h_rowmap[r0].x) ++r1;
+        for (int64_t q = cl.h_rowstart[r0]; q < cl.h_rowstart[r1]; q += kSegLen) {
+            const int64_t e = std::min(q + kSegLen, cl.h_rowstart[r1]);
+            int rq = r0;  // row holding quartet q
+            while (cl.h_rowstart[rq + 1] <= q) ++rq;
+            v.push_back(make_int4(rq, (int)q, (int)e, r1));
         }
+        r0 = r1;
+    }
     *n = (int)v.size();
     *out = nullptr;
     if (v.empty()) return MESS_OK;

@@ -25,6 +25,8 @@ CASES = {
     "hco6_sp/5": lambda: G.random_small_molecule(5),
     "water2_spd/0": lambda: G.water_cluster(0, n_waters=2, box=7.0),
     "mol3to20/1000-small": lambda: G.batched_molecule(1007),
+    # two waters far apart: most primitive pairs between them are screened
+    "water2_spd_far/3": lambda: G.water_cluster(3, n_waters=2, box=14.0),
 }
 
 
@@ -58,8 +60,9 @@ def test_eri_dense(case):
     mol = CASES[case]()
     if mol.n_bf > 60:
         pytest.skip("dense oracle tensor too large")
-    announce(f"eri_dense {case} nbf={mol.n_bf}")
     B = mess.basis_from_molecule(mol)
+    kept, full = mess.mess_prim_pairs(B)
+    announce(f"eri_dense {case} nbf={mol.n_bf} primitive pairs kept {kept}/{full}")
     N = B.nbf
     out = zeros(N, N, N, N)
     mess.mess_eri(B, out, schwarz_tol=0.0)
@@ -93,3 +96,19 @@ def test_jk(case, tau, mode):
         Jd, Kd = core.jk_from_dense(core.eri_dense(mol), D)
         assert _rel_err(host(J), Jd) < 1e-11
         assert _rel_err(host(K), Kd) < 1e-11
+
+
+def test_primitive_screening_drops_pairs():
+    """The screened cases above do exercise the primitive-pair screening:
+    pairs between distant atoms lose their tight primitives, same-atom
+    pairs keep all of theirs."""
+    mess = need_gpu()
+    mol = CASES["water2_spd_far/3"]()
+    B = mess.basis_from_molecule(mol)
+    kept, full = mess.mess_prim_pairs(B)
+    announce(f"water2_spd_far/3: primitive pairs kept {kept}/{full}")
+    nprim = np.asarray(mol.shell_nprim)
+    same_atom = sum(int(nprim[a]) * int(nprim[b]) for a in range(len(nprim)) for b in range(a + 1)
+                    if mol.shell_atom[a] == mol.shell_atom[b])
+    assert full == sum(int(nprim[a]) * int(nprim[b]) for a in range(len(nprim)) for b in range(a + 1))
+    assert same_atom <= kept < full
