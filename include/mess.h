@@ -70,7 +70,10 @@ typedef struct mess_scf_opts {
     int32_t prec;        /* MESS_FP64, or MESS_FP32: Fock builds of the density change
                             dD = D_k - D_{k-1} added to FP64 J/K, in FP32 arithmetic once the
                             previous |dE| < 1e-3 Ha (FP64 before); full FP64 build at the
-                            first iteration and every 8th */
+                            first iteration and every 8th.  With MESS_JK_DIRECT and
+                            schwarz_tol > 0 the dD builds also skip quartets with
+                            Q_ab Q_cd max|dD| < schwarz_tol (threshold rounded down to a
+                            power of ten) */
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
     int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X (F = H + J + V_x,
                             E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; FP64 only; see mess_lda_x) */

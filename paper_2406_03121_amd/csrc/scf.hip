@@ -35,6 +35,7 @@ struct ScfScalars {
     double emin, emax;
     double trX, trX2;
     double idem;          // tr(X) - tr(X^2) of the last purification step
+    double dmax;          // max |dD| of the last incremental build
     int sp2_iter, sp2_done, sp2_post;
     int pad;
     double diis_c[kMaxDiis + 1];
@@ -61,6 +62,8 @@ struct mess_scf {
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
     double *Vx = nullptr;                                // LDA exchange potential
     double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
+    double last_dmax = 0.0;  // max |dD| and screening threshold of the last incremental build
+    double last_tau = 0.0;
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
     int sp2_iters_last = 0;
@@ -139,6 +142,20 @@ __global__ void __launch_bounds__(1024) k_maxabs(int64_t n, const double *__rest
         __syncthreads();
     }
     if (threadIdx.x == 0) sc->resid = red[0];
+}
+
+// max |x| over n values -> *out (single block, 1024 threads)
+__global__ void __launch_bounds__(1024) k_maxabs_to(int64_t n, const double *__restrict__ x, double *__restrict__ out) {
+    __shared__ double red[1024];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, fabs(x[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // B[slot][k] = B[k][slot] = <E_slot, E_k> for the listed history slots.
@@ -594,12 +611,36 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
                 MESS_TRY(jk_stored(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
         } else {
             MESS_TRY(axpby(s, nn, 1.0, st->D, -1.0, st->Dprev, st->dD));
-            if (st->opts.jk_mode == MESS_JK_DIRECT)
-                MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, dprec, st->opts.schwarz_tol, s));
-            else
-                MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, dprec, st->opts.schwarz_tol, s));
-            MESS_TRY(axpby(s, nn, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
-            MESS_TRY(axpby(s, nn, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
+            // Direct builds screen the change by its size as well: a quartet
+            // with Q_ab Q_cd max|dD| < tol moves no element of J or K by more
+            // than a few tol, so the work list of tol / max|dD| (rounded down
+            // to a power of ten, so that lists are reused) leaves out only
+            // such quartets.  Stored blocks keep the list they were built for.
+            double tau = st->opts.schwarz_tol;
+            bool none = false;
+            if (st->opts.jk_mode == MESS_JK_DIRECT && tau > 0.0) {
+                hipLaunchKernelGGL(k_maxabs_to, dim3(1), dim3(1024), 0, s, nn, st->dD, &st->sc->dmax);
+                MESS_LAUNCH_CHECK();
+                double dmax = 0.0;
+                MESS_HIP(hipMemcpyAsync(&dmax, &st->sc->dmax, sizeof(double), hipMemcpyDeviceToHost, s));
+                MESS_HIP(hipStreamSynchronize(s));
+                if (!std::isfinite(dmax)) {
+                    set_error("mess_scf_step: non-finite density change");
+                    return MESS_E_NUMERIC;
+                }
+                if (dmax == 0.0) none = true;
+                else tau = std::pow(10.0, std::floor(std::log10(tau / dmax)));
+                st->last_dmax = dmax;
+                st->last_tau = none ? 0.0 : tau;
+            }
+            if (!none) {
+                if (st->opts.jk_mode == MESS_JK_DIRECT)
+                    MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, dprec, tau, s));
+                else
+                    MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, dprec, tau, s));
+                MESS_TRY(axpby(s, nn, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
+                MESS_TRY(axpby(s, nn, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
+            }
         }
         MESS_HIP(hipMemcpyAsync(st->Dprev, st->D, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
         MESS_HIP(hipMemcpyAsync(st->Gj, st->Gja, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
