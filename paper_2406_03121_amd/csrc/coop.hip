@@ -773,6 +773,37 @@ int coop_jk_stored(int cb, int ck, const ClassLaunch &L, const void *base, int p
     if (g > (1 << 20)) g = 1 << 20;
     const int NA = ncart(pair_class_la(cb)), NB = ncart(pair_class_lb(cb)), NC = ncart(pair_class_la(ck)),
               ND = ncart(pair_class_lb(ck));
+    // bra-row segments with K and density rows in LDS when they fit; (dd|dd)
+    // keeps the wave-per-quartet form (measured faster: the streamed form
+    // needs more registers than a lane has for its 36-element J and density
+    // blocks)
+    const size_t lds = sizeof(double) * (2 * (size_t)(NA + NB) * L.nmax + NA * NB);
+    if (L.segs && L.nseg > 0 && lds <= 64 * 1024 && !(cb == 5 && ck == 5)) {
+        const unsigned gs = (unsigned)std::min(L.nseg, 1 << 20);
+        bool done = false;
+#define MESS_STREAM(B, K)                                                                                         \
+        if (cb == B && ck == K) {                                                                                 \
+            if (prec == MESS_FP32)                                                                                \
+                hipLaunchKernelGGL((k_jk_stored_stream<ClassOf<B, K>, float>), dim3(gs), dim3(256), lds, L.stream, \
+                                   L.pairs, L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs,      \
+                                   L.nseg, static_cast<const float *>(base), L.total, D, Gj, Gk);                   \
+            else                                                                                                  \
+                hipLaunchKernelGGL((k_jk_stored_stream<ClassOf<B, K>, double>), dim3(gs), dim3(256), lds,         \
+                                   L.stream, L.pairs, L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap,    \
+                                   L.segs, L.nseg, static_cast<const double *>(base), L.total, D, Gj, Gk);          \
+            done = true;                                                                                          \
+        }
+        MESS_STREAM(4, 2)
+        MESS_STREAM(4, 4)
+        MESS_STREAM(5, 2)
+        MESS_STREAM(5, 3)
+        MESS_STREAM(5, 4)
+#undef MESS_STREAM
+        if (done) {
+            MESS_LAUNCH_CHECK();
+            return MESS_OK;
+        }
+    }
     if (prec == MESS_FP32)
         hipLaunchKernelGGL(k_jk_stored_wave<float>, dim3((unsigned)g), dim3(64), 0, L.stream, L.pairs, L.bra_off,
                            L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.total, NA, NB, NC, ND,

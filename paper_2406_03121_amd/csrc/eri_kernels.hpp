@@ -327,4 +327,128 @@ __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restri
     }
 }
 
+// J/K from stored blocks for classes whose block is too large to hold in
+// registers: the same bra-row segments (K rows of the bra functions in
+// LDS, J[a,b] in registers, one flush per segment), with the block of each
+// quartet streamed element by element in (a, b, c, d) order; the density
+// rows of the bra functions are staged in LDS next to the K rows.  Per
+// element six FMAs; K partial sums are flushed to LDS per (a, b) and per a,
+// J[c,d] to global memory per quartet.
+template <class Dm, typename Real>
+__global__ void __launch_bounds__(256) k_jk_stored_stream(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                          int same_class, const int64_t *__restrict__ rowstart,
+                                                          const int2 *__restrict__ rowmap, const int4 *__restrict__ segs,
+                                                          int nseg, const Real *__restrict__ base, int64_t total,
+                                                          const double *__restrict__ Dall, double *__restrict__ Gjall,
+                                                          double *__restrict__ Gkall) {
+    constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND;
+    extern __shared__ double lds[];
+    auto lds_add = [](double *p, double v) {
+        __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    for (int sidx = blockIdx.x; sidx < nseg; sidx += gridDim.x) {
+        const int4 sg = segs[sidx];
+        const int i = rowmap[sg.x].x;
+        const PairInfo bra = pairs[bra_off + i];
+        const int N = bra.mN, a0 = bra.bfa, b0 = bra.bfb;
+        const double *D = Dall + bra.moff;
+        double *Gj = Gjall ? Gjall + bra.moff : nullptr;
+        double *Gk = Gkall ? Gkall + bra.moff : nullptr;
+        double *Ka = lds, *Kb = lds + NA * N, *Da = lds + (NA + NB) * N, *Db = Da + NA * N;
+        double *Jab = Db + NB * N;
+        // K rows zeroed, density rows (same layout) copied, J[a,b] zeroed
+        for (int e = threadIdx.x; e < (NA + NB) * N; e += 256) {
+            const int row = e < NA * N ? a0 + e / N : b0 + (e - NA * N) / N;
+            lds[e] = 0.0;
+            Da[e] = D[(int64_t)row * N + e % N];
+        }
+        if (threadIdx.x < NA * NB) Jab[threadIdx.x] = 0.0;
+        __syncthreads();
+        Real jab[NA][NB];
+        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { jab[A][B] = Real(0); }); });
+        int r = sg.x;
+        for (int64_t q = sg.y + threadIdx.x; q < sg.z; q += 256) {
+            while (r + 1 < sg.w && rowstart[r + 1] <= q) ++r;
+            const int j = rowmap[r].y + (int)(q - rowstart[r]);
+            const PairInfo ket = pairs[ket_off + j];
+            const int c0 = ket.bfa, d0 = ket.bfb;
+            double fac = 1.0;
+            if (bra.sa == bra.sb) fac *= 0.5;
+            if (ket.sa == ket.sb) fac *= 0.5;
+            if (same_class && i == j) fac *= 0.5;
+            Real Dcd[NC][ND], jcd[NC][ND];
+            static_for<0, NC>([&](auto C) {
+                static_for<0, ND>([&](auto Dd) {
+                    Dcd[C][Dd] = Real(D[(int64_t)(c0 + C) * N + d0 + Dd]);
+                    jcd[C][Dd] = Real(0);
+                });
+            });
+            static_for<0, NA>([&](auto A) {
+                Real kac[NC], kad[ND];
+                static_for<0, NC>([&](auto C) { kac[C] = Real(0); });
+                static_for<0, ND>([&](auto Dd) { kad[Dd] = Real(0); });
+                static_for<0, NB>([&](auto B) {
+                    const Real dab = Real(Da[A * N + b0 + B]);
+                    Real dad[ND], dbd[ND], kbd[ND], kbc[NC];
+                    static_for<0, ND>([&](auto Dd) {
+                        dad[Dd] = Real(Da[A * N + d0 + Dd]);
+                        dbd[Dd] = Real(Db[B * N + d0 + Dd]);
+                        kbd[Dd] = Real(0);
+                    });
+                    Real s = Real(0);
+                    static_for<0, NC>([&](auto C) {
+                        const Real dac = Real(Da[A * N + c0 + C]), dbc = Real(Db[B * N + c0 + C]);
+                        kbc[C] = Real(0);
+                        static_for<0, ND>([&](auto Dd) {
+                            constexpr int e = ((decltype(A)::value * NB + decltype(B)::value) * NC + decltype(C)::value) * ND +
+                                              decltype(Dd)::value;
+                            const Real o = base[(int64_t)e * total + q];
+                            s += o * Dcd[C][Dd];
+                            jcd[C][Dd] += o * dab;
+                            kac[C] += o * dbd[Dd];
+                            kbc[C] += o * dad[Dd];
+                            kad[Dd] += o * dbc;
+                            kbd[Dd] += o * dac;
+                        });
+                    });
+                    jab[A][B] += Real(fac) * s;
+                    if (Gk) {
+                        static_for<0, NC>([&](auto C) { lds_add(&Kb[B * N + c0 + C], fac * (double)kbc[C]); });
+                        static_for<0, ND>([&](auto Dd) { lds_add(&Kb[B * N + d0 + Dd], fac * (double)kbd[Dd]); });
+                    }
+                });
+                if (Gk) {
+                    static_for<0, NC>([&](auto C) { lds_add(&Ka[A * N + c0 + C], fac * (double)kac[C]); });
+                    static_for<0, ND>([&](auto Dd) { lds_add(&Ka[A * N + d0 + Dd], fac * (double)kad[Dd]); });
+                }
+            });
+            if (Gj)
+                static_for<0, NC>([&](auto C) {
+                    static_for<0, ND>([&](auto Dd) {
+                        unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * fac * (double)jcd[C][Dd]);
+                    });
+                });
+        }
+        if (Gj) {
+            static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                double v = (double)jab[A][B];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if ((threadIdx.x & 63) == 0) lds_add(&Jab[A * NB + B], v);
+            }); });
+        }
+        __syncthreads();
+        if (Gk)
+            for (int e = threadIdx.x; e < (NA + NB) * N; e += 256) {
+                const double v = lds[e];
+                if (v == 0.0) continue;
+                const int row = e < NA * N ? a0 + e / N : b0 + (e - NA * N) / N;
+                unsafeAtomicAdd(&Gk[(int64_t)row * N + e % N], v);
+            }
+        if (Gj)
+            for (int e = threadIdx.x; e < NA * NB; e += 256)
+                unsafeAtomicAdd(&Gj[(int64_t)(a0 + e / NB) * N + b0 + e % NB], 2.0 * Jab[e]);
+        __syncthreads();  // LDS reused by the next segment
+    }
+}
+
 }  // namespace mess
