@@ -12,19 +12,23 @@ namespace mess {
 // 64 x 64 output tile per 256-thread block, 4 x 4 per thread, K in steps of
 // 16 staged through LDS.  FP64 vector FMA: on gfx950 the FP64 matrix cores
 // have the same peak rate as the vector units, and these products are small
-// (N <= ~1000), so the tile is sized for latency, not for MFMA.
+// (N <= ~1000), so the tile is sized for latency, not for MFMA.  Below
+// 512 x 512 outputs a 32 x 32 tile (2 x 2 per thread) gives four times as
+// many blocks; every output is the same k-ordered FMA chain in both.
 
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
-// One output tile (rows row0.., columns col0..) of C = alpha op(A) op(B) + beta C.
-template <bool TA, bool TB>
+// One output tile (rows row0.., columns col0..) of C = alpha op(A) op(B) + beta C,
+// TM x TM outputs per 256-thread block.
+template <bool TA, bool TB, int TM = kTM>
 __device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, const double *__restrict__ A, int lda,
                                           const double *__restrict__ B, int ldb, double beta,
                                           double *__restrict__ C, int ldc, int row0, int col0) {
+    constexpr int kTM = TM, kTN = TM, R = TM / 16;
     __shared__ double As[kTK][kTM + 1];
     __shared__ double Bs[kTK][kTN + 1];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
+    double acc[R][R] = {};
     for (int k0 = 0; k0 < K; k0 += kTK) {
         for (int t = threadIdx.x; t < kTK * kTM; t += 256) {
             const int kk = t / kTM, mm = t % kTM;
@@ -43,24 +47,24 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, con
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kTK; ++kk) {
-            double a[4], b[4];
+            double a[R], b[R];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < R; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < R; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < R; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < R; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < R; ++i) {
         const int r = row0 + ty + 16 * i;
         if (r >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < R; ++j) {
             const int c = col0 + tx + 16 * j;
             if (c >= N) continue;
             double v = alpha * acc[i][j];
@@ -70,11 +74,11 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, con
     }
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, int TM>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                               int lda, const double *__restrict__ B, int ldb, double beta,
                                               double *__restrict__ C, int ldc) {
-    gemm_tile<TA, TB>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.y * kTM, blockIdx.x * kTN);
+    gemm_tile<TA, TB, TM>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.y * TM, blockIdx.x * TM);
 }
 
 // Batched square products over a packed block-diagonal layout: block m is
@@ -97,15 +101,23 @@ __global__ void __launch_bounds__(256) k_gemm_blocks(int nmol, const int64_t *__
 int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
          const double *B, int ldb, double beta, double *C, int ldc) {
     if (M <= 0 || N <= 0) return MESS_OK;
-    dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM), blk(256);
-    if (!ta && !tb)
-        hipLaunchKernelGGL((k_gemm<false, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else if (ta && !tb)
-        hipLaunchKernelGGL((k_gemm<true, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else if (!ta && tb)
-        hipLaunchKernelGGL((k_gemm<false, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
-    else
-        hipLaunchKernelGGL((k_gemm<true, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    const bool small = (int64_t)M * N <= 512 * 512;
+    const int tm = small ? 32 : kTM;
+    dim3 grid((N + tm - 1) / tm, (M + tm - 1) / tm), blk(256);
+#define MESS_GEMM(TA_, TB_)                                                                                     \
+    do {                                                                                                        \
+        if (small)                                                                                              \
+            hipLaunchKernelGGL((k_gemm<TA_, TB_, 32>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, \
+                               ldc);                                                                            \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_gemm<TA_, TB_, kTM>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta,  \
+                               C, ldc);                                                                         \
+    } while (0)
+    if (!ta && !tb) MESS_GEMM(false, false);
+    else if (ta && !tb) MESS_GEMM(true, false);
+    else if (!ta && tb) MESS_GEMM(false, true);
+    else MESS_GEMM(true, true);
+#undef MESS_GEMM
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
