@@ -451,10 +451,12 @@ void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk) {
     *per_quartet_jk = it->second.second;
 }
 
-// Classes evaluated by the cooperative kernel (the per-lane unrolled form
-// of these needs far more than the 512 registers a lane can hold).
+// Classes evaluated through the cooperative tables (the per-lane unrolled
+// form of these needs far more than the 512 registers a lane can hold), and
+// (pp|pp), whose few quartets leave the lane-per-quartet launch with too few
+// waves to fill the chip.
 bool coop_class(int cb, int ck) {
-    return (cb == 5 && ck >= 2) || (cb == 4 && (ck == 2 || ck == 4));
+    return (cb == 5 && ck >= 2) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
 }
 
 static const CoopProgram *coop_program(int cb, int ck) {
@@ -633,7 +635,9 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
 // the table-driven kernel; for (dd|dp) and (dd|dd) the unrolled recursion
 // spills too much and the table-driven kernel wins).  In FP32 the
 // primitive-lane mapping serves every high class except (dd|dp), (dd|dd).
-static bool plane_class(int cb, int ck) { return (cb == 5 && (ck == 2 || ck == 3)) || (cb == 4 && (ck == 2 || ck == 4)); }
+static bool plane_class(int cb, int ck) {
+    return (cb == 5 && (ck == 2 || ck == 3)) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
+}
 
 static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, const ClassLaunch &L, int64_t total,
                          unsigned g, size_t lds, const double *D, double *out0, double *out1) {
@@ -646,6 +650,7 @@ static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, 
     MESS_PL(5, 2)
     MESS_PL(4, 4)
     MESS_PL(4, 2)
+    MESS_PL(2, 2)
 #undef MESS_PL
 }
 
@@ -793,6 +798,7 @@ int coop_jk_stored(int cb, int ck, const ClassLaunch &L, const void *base, int p
                                    L.segs, L.nseg, static_cast<const double *>(base), L.total, D, Gj, Gk);          \
             done = true;                                                                                          \
         }
+        MESS_STREAM(2, 2)
         MESS_STREAM(4, 2)
         MESS_STREAM(4, 4)
         MESS_STREAM(5, 2)
@@ -847,6 +853,7 @@ namespace mess {
                                   double *Gj, double *Gk) {                                            \
         return coop_jk_stored(B, K, L, base, prec, D, Gj, Gk);                                         \
     }
+MESS_COOP_CLASS(2, 2)
 MESS_COOP_CLASS(4, 2)
 MESS_COOP_CLASS(4, 4)
 MESS_COOP_CLASS(5, 2)
