@@ -99,7 +99,8 @@ def recorded_traffic(class_name):
     summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-scaled), or None when it
     covers another class or its kernel sources have changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_counters_dd_dp_water60.json")
+    slug = class_name.strip("()").replace("|", "_")
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{slug}_water60.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
