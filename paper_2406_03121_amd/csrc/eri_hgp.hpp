@@ -250,6 +250,131 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
     });
 }
 
+// Depth-first order of the ket components |f| <= LCD for the variant below:
+// each f != 0 is built from its parent f - 1_j along its LAST non-zero
+// direction j, and the components are visited in pre-order of that tree
+// (px, dxx, dxy, dxz, py, dyy, dyz, pz, dzz for LCD = 2), so the
+// intermediates of one branch die before the next branch starts.
+__host__ __device__ constexpr int last_dir(const Cart c) { return c.z > 0 ? 2 : (c.y > 0 ? 1 : 0); }
+
+template <int LCD>
+struct KetDfs {
+    static constexpr int NF = cart_off(LCD + 1);
+    int seq[NF];   // visiting order
+    int rank[NF];  // position of f among the output components (|f| >= LC) in that order
+};
+
+template <int LC, int LCD>
+__host__ __device__ constexpr KetDfs<LCD> make_ket_dfs() {
+    KetDfs<LCD> r{};
+    int stack[KetDfs<LCD>::NF + 3] = {};
+    int sp = 0, n = 0, nout = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const int f = stack[--sp];
+        r.seq[n++] = f;
+        const Cart c = cart_of(f);
+        if (c.l() >= LC) r.rank[f] = nout++;
+        if (c.l() < LCD)
+            for (int j = 2; j >= last_dir(c); --j) stack[sp++] = c.plus(j).idx();
+    }
+    return r;
+}
+
+// The same primitive-quartet recursion as prim_quartet, with the ket
+// components in the depth-first order above; every output [e0|f0]
+// (la <= |e| <= la+lb, lc <= |f| <= lc+ld) is handed to
+// out(integral_constant<x>, value) as soon as it is final, in the order
+// x_pos = rank(f) * NEA + (e - E0), where x = (f - F0) * NEA + (e - E0).
+template <class Dm, typename Real, class Out>
+__device__ __forceinline__ void prim_quartet_dfs(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
+                                                 const Real (&AC)[3], const BoysTabs &bt, Out &&out) {
+    constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LC = Dm::LC, LCD = Dm::LCD;
+    const Real p = P.p, q = Q.p;
+    const Real pq = p + q;
+    const Real spq = rsqrt_nr(pq);
+    const Real rpq = spq * spq;
+    const Real rho = p * q * rpq;
+    const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
+    const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
+
+    Real F[L + 1];
+    boys_eval<L, Real>(T, bt, F);
+
+    Real V[NF][NE][L + 1];
+    static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pref * F[decltype(M)::value]; });
+
+    if constexpr (Dm::LAB > 0) {
+        const Real PA[3] = {P.PAx, P.PAy, P.PAz};
+        const Real WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
+        const Real oo2p = Real(0.5) * P.rp, rho_p = q * rpq;
+        static_for<1, NE>([&](auto EI) {
+            constexpr int e = decltype(EI)::value;
+            constexpr Cart c = cart_of(e);
+            constexpr int i = c.dir();
+            constexpr int ei = c.get(i);
+            constexpr int e1 = c.minus(i).idx();
+            static_for<0, L - c.l() + 1>([&](auto MI) {
+                constexpr int m = decltype(MI)::value;
+                Real v = PA[i] * V[0][e1][m] + WP[i] * V[0][e1][m + 1];
+                if constexpr (ei >= 2) {
+                    constexpr int e2 = c.minus(i, 2).idx();
+                    v += Real(ei - 1) * oo2p * (V[0][e2][m] - rho_p * V[0][e2][m + 1]);
+                }
+                V[0][e][m] = v;
+            });
+        });
+    }
+    constexpr KetDfs<LCD> kd = make_ket_dfs<LC, LCD>();
+    auto emit_f = [&](auto FI) {
+        constexpr int f = decltype(FI)::value;
+        if constexpr (cart_of(f).l() >= LC) {
+            static_for<Dm::E0, NE>([&](auto EI) {
+                constexpr int e = decltype(EI)::value;
+                out(std::integral_constant<int, (f - Dm::F0) * Dm::NEA + (e - Dm::E0)>{}, V[f][e][0]);
+            });
+        }
+    };
+    if constexpr (LCD == 0) {
+        emit_f(std::integral_constant<int, 0>{});
+    } else {
+        const Real QC[3] = {Q.PAx, Q.PAy, Q.PAz};
+        const Real WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
+        const Real oo2q = Real(0.5) * Q.rp, rho_q = p * rpq, oo2pq = Real(0.5) * rpq;
+        static_for<0, NF>([&](auto SI) {
+            constexpr int f = kd.seq[decltype(SI)::value];
+            if constexpr (f > 0) {
+                constexpr Cart cf = cart_of(f);
+                constexpr int nf = cf.l();
+                constexpr int j = last_dir(cf);
+                constexpr int fj = cf.get(j);
+                constexpr int f1 = cf.minus(j).idx();
+                constexpr int emin = cart_off(cmax(0, LA - (LCD - nf)));
+                static_for<emin, NE>([&](auto EI) {
+                    constexpr int e = decltype(EI)::value;
+                    constexpr Cart ce = cart_of(e);
+                    constexpr int ej = ce.get(j);
+                    static_for<0, L - ce.l() - nf + 1>([&](auto MI) {
+                        constexpr int m = decltype(MI)::value;
+                        Real v = QC[j] * V[f1][e][m] + WQ[j] * V[f1][e][m + 1];
+                        if constexpr (fj >= 2) {
+                            constexpr int f2 = cf.minus(j, 2).idx();
+                            v += Real(fj - 1) * oo2q * (V[f2][e][m] - rho_q * V[f2][e][m + 1]);
+                        }
+                        if constexpr (ej >= 1) {
+                            constexpr int e1 = ce.minus(j).idx();
+                            v += Real(ej) * oo2pq * V[f1][e1][m + 1];
+                        }
+                        V[f][e][m] = v;
+                    });
+                });
+            }
+            emit_f(std::integral_constant<int, f>{});
+        });
+    }
+}
+
 // FP64 form used by the existing call sites.
 template <class Dm>
 __device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPair &Q, const double (&AC)[3],

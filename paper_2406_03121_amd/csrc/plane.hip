@@ -15,9 +15,9 @@ namespace mess {
 // lane's registers but whose contracted intermediates do not: one wave per
 // shell quartet, lane k evaluating primitive quartet k (then k + 64, ...)
 // with the fully unrolled recursion; after each round of 64 the wave sums
-// the intermediates with a butterfly reduce-scatter (six exchange steps,
-// each lane keeping half of what it holds), so lane l ends with the sums of
-// intermediates [l*NPER, (l+1)*NPER).  The horizontal recursion and output
+// the intermediates with butterfly reduce-scatters over blocks of 64 (six
+// exchange steps, each lane keeping half of what it holds), so lane l ends
+// with the sums of intermediates 64 b + l.  The horizontal recursion and output
 // then run table-driven as in k_coop.
 
 template <int NP, int C, int O, typename Real>
@@ -30,6 +30,20 @@ __device__ __forceinline__ void rs_step(Real (&v)[NP], const int lane) {
         const Real keep = up ? hi : lo;
         v[k] = keep + __shfl_xor(send, O, 64);
     });
+}
+
+// Position of intermediate x = (f - F0) NEA + (e - E0) in the order
+// prim_quartet_dfs hands them out, and the last position of block b.
+template <class Dm>
+__host__ __device__ constexpr int plane_out_pos(int x) {
+    constexpr KetDfs<Dm::LCD> kd = make_ket_dfs<Dm::LC, Dm::LCD>();
+    return kd.rank[Dm::F0 + x / Dm::NEA] * Dm::NEA + x % Dm::NEA;
+}
+template <class Dm, int NACC>
+__host__ __device__ constexpr int plane_block_last(int b) {
+    int m = -1;
+    for (int x = 64 * b; x < 64 * b + 64 && x < NACC; ++x) m = plane_out_pos<Dm>(x) > m ? plane_out_pos<Dm>(x) : m;
+    return m;
 }
 
 template <class Dm, int MODE, typename Real>
@@ -62,31 +76,39 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
         const int nprim = bra.npp * ket.npp;
         for (int k0 = 0; k0 < nprim; k0 += 64) {
             const int k = k0 + lane;
-            Real a[Dm::NFA][Dm::NEA];
-            static_for<0, Dm::NFA>([&](auto F) {
-                static_for<0, Dm::NEA>([&](auto E) { a[decltype(F)::value][decltype(E)::value] = Real(0); });
+            // lanes past the end evaluate primitive quartet 0 with zero
+            // weight, so the recursion and the reductions stay one
+            // straight-line block
+            const int kk = k < nprim ? k : 0;
+            PrimPairT<Real> P = pp[bra.pp0 + kk / ket.npp];
+            const PrimPairT<Real> Q = pp[ket.pp0 + kk % ket.npp];
+            if (k >= nprim) P.K = Real(0);
+            // intermediates in blocks of 64; each block is reduce-scattered
+            // over the wave (lane l keeps entry 64 b + l) as soon as its last
+            // entry is final, so finished outputs do not stay live through
+            // the rest of the recursion
+            Real vb[NPER][64];
+            static_for<NACC, NP>([&](auto X) {
+                constexpr int x = decltype(X)::value;
+                vb[x / 64][x % 64] = Real(0);
             });
-            if (k < nprim) {
-                const PrimPairT<Real> P = pp[bra.pp0 + k / ket.npp];
-                const PrimPairT<Real> Q = pp[ket.pp0 + k % ket.npp];
-                prim_quartet<Dm, Real>(P, Q, AC, bt, a);
-            }
-            Real v[NP];
-            static_for<0, NP>([&](auto I) {
-                constexpr int x = decltype(I)::value;
-                if constexpr (x < NACC) v[x] = a[x / Dm::NEA][x % Dm::NEA];
-                else v[x] = Real(0);
+            prim_quartet_dfs<Dm, Real>(P, Q, AC, bt, [&](auto X, Real val) {
+                constexpr int x = decltype(X)::value;
+                constexpr int b = x / 64;
+                vb[b][x % 64] = val;
+                if constexpr (plane_block_last<Dm, NACC>(b) == plane_out_pos<Dm>(x)) {
+                    rs_step<64, 64, 32>(vb[b], lane);
+                    rs_step<64, 32, 16>(vb[b], lane);
+                    rs_step<64, 16, 8>(vb[b], lane);
+                    rs_step<64, 8, 4>(vb[b], lane);
+                    rs_step<64, 4, 2>(vb[b], lane);
+                    rs_step<64, 2, 1>(vb[b], lane);
+                    part[b] += vb[b][0];
+                }
             });
-            rs_step<NP, NP, 32>(v, lane);
-            rs_step<NP, NP / 2, 16>(v, lane);
-            rs_step<NP, NP / 4, 8>(v, lane);
-            rs_step<NP, NP / 8, 4>(v, lane);
-            rs_step<NP, NP / 16, 2>(v, lane);
-            rs_step<NP, NP / 32, 1>(v, lane);
-            static_for<0, NPER>([&](auto I) { part[I] += v[I]; });
         }
         static_for<0, NPER>([&](auto I) {
-            const int idx = lane * NPER + decltype(I)::value;
+            const int idx = 64 * decltype(I)::value + lane;
             if (idx < NACC) H[idx] = (double)part[I];
         });
         __syncthreads();
