@@ -153,8 +153,10 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // ---------------------------------------------------- primitive quartet
 //
-// Accumulates [e0|f0] for la <= |e| <= la+lb, lc <= |f| <= lc+ld of one
-// primitive quartet into acc[f - F0][e - E0].
+// [e0|f0] for la <= |e| <= la+lb, lc <= |f| <= lc+ld of one primitive
+// quartet (Obara-Saika vertical recursion; the bra direction i is the first
+// non-zero one of e + 1_i, the ket direction j the last non-zero one of
+// f + 1_j):
 //   bra VRR: [e+1_i|0]^(m) = PA_i [e]^(m) + WP_i [e]^(m+1)
 //                           + e_i/(2p) ([e-1_i]^(m) - rho/p [e-1_i]^(m+1))
 //   ket VRR: [e|f+1_j]^(m) = QC_j [e|f]^(m) + WQ_j [e|f]^(m+1)
@@ -162,95 +164,7 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 //                           + e_j/(2(p+q)) [e-1_j|f]^(m+1)
 //   base:    [0|0]^(m) = 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd F_m(rho |PQ|^2)
 
-// AC = A - C (bra and ket anchor centres); P - Q = AC + PA - QC is exact
-// zero when all four shells share one atom.
-template <class Dm, typename Real>
-__device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
-                                             const Real (&AC)[3], const BoysTabs &bt,
-                                             Real (&acc)[Dm::NFA][Dm::NEA]) {
-    constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LCD = Dm::LCD;
-    const Real p = P.p, q = Q.p;
-    const Real pq = p + q;
-    // one reciprocal square root serves 1/(p+q) and the prefactor
-    const Real spq = rsqrt_nr(pq);
-    const Real rpq = spq * spq;
-    const Real rho = p * q * rpq;
-    const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
-    const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    // 2 pi^{5/2} / (p q sqrt(p+q)) K_ab K_cd, 2 pi^{5/2} = 34.986836655249725
-    const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
-
-    Real F[L + 1];
-    boys_eval<L, Real>(T, bt, F);
-
-    Real V[NF][NE][L + 1];
-    static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pref * F[decltype(M)::value]; });
-
-    if constexpr (Dm::LAB > 0) {
-        const Real PA[3] = {P.PAx, P.PAy, P.PAz};
-        // W - P = q/(p+q) (Q - P)
-        const Real WP[3] = {-q * rpq * PQx, -q * rpq * PQy, -q * rpq * PQz};
-        const Real oo2p = Real(0.5) * P.rp, rho_p = q * rpq;  // rho/p = q/(p+q)
-        static_for<1, NE>([&](auto EI) {
-            constexpr int e = decltype(EI)::value;
-            constexpr Cart c = cart_of(e);
-            constexpr int i = c.dir();
-            constexpr int ei = c.get(i);
-            constexpr int e1 = c.minus(i).idx();
-            static_for<0, L - c.l() + 1>([&](auto MI) {
-                constexpr int m = decltype(MI)::value;
-                Real v = PA[i] * V[0][e1][m] + WP[i] * V[0][e1][m + 1];
-                if constexpr (ei >= 2) {
-                    constexpr int e2 = c.minus(i, 2).idx();
-                    v += Real(ei - 1) * oo2p * (V[0][e2][m] - rho_p * V[0][e2][m + 1]);
-                }
-                V[0][e][m] = v;
-            });
-        });
-    }
-    if constexpr (LCD > 0) {
-        const Real QC[3] = {Q.PAx, Q.PAy, Q.PAz};
-        // W - Q = p/(p+q) (P - Q)
-        const Real WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
-        const Real oo2q = Real(0.5) * Q.rp, rho_q = p * rpq, oo2pq = Real(0.5) * rpq;  // rho/q = p/(p+q)
-        static_for<1, NF>([&](auto FI) {
-            constexpr int f = decltype(FI)::value;
-            constexpr Cart cf = cart_of(f);
-            constexpr int nf = cf.l();
-            constexpr int j = cf.dir();
-            constexpr int fj = cf.get(j);
-            constexpr int f1 = cf.minus(j).idx();
-            constexpr int emin = cart_off(cmax(0, LA - (LCD - nf)));
-            static_for<emin, NE>([&](auto EI) {
-                constexpr int e = decltype(EI)::value;
-                constexpr Cart ce = cart_of(e);
-                constexpr int ej = ce.get(j);
-                static_for<0, L - ce.l() - nf + 1>([&](auto MI) {
-                    constexpr int m = decltype(MI)::value;
-                    Real v = QC[j] * V[f1][e][m] + WQ[j] * V[f1][e][m + 1];
-                    if constexpr (fj >= 2) {
-                        constexpr int f2 = cf.minus(j, 2).idx();
-                        v += Real(fj - 1) * oo2q * (V[f2][e][m] - rho_q * V[f2][e][m + 1]);
-                    }
-                    if constexpr (ej >= 1) {
-                        constexpr int e1 = ce.minus(j).idx();
-                        v += Real(ej) * oo2pq * V[f1][e1][m + 1];
-                    }
-                    V[f][e][m] = v;
-                });
-            });
-        });
-    }
-    static_for<Dm::F0, NF>([&](auto FI) {
-        constexpr int f = decltype(FI)::value;
-        static_for<Dm::E0, NE>([&](auto EI) {
-            constexpr int e = decltype(EI)::value;
-            acc[f - Dm::F0][e - Dm::E0] += V[f][e][0];
-        });
-    });
-}
-
-// Depth-first order of the ket components |f| <= LCD for the variant below:
+// Depth-first order of the ket components |f| <= LCD:
 // each f != 0 is built from its parent f - 1_j along its LAST non-zero
 // direction j, and the components are visited in pre-order of that tree
 // (px, dxx, dxy, dxz, py, dyy, dyz, pz, dzz for LCD = 2), so the
@@ -281,13 +195,17 @@ __host__ __device__ constexpr KetDfs<LCD> make_ket_dfs() {
     return r;
 }
 
-// The same primitive-quartet recursion as prim_quartet, with the ket
-// components in the depth-first order above; every output [e0|f0]
-// (la <= |e| <= la+lb, lc <= |f| <= lc+ld) is handed to
-// out(integral_constant<x>, value) as soon as it is final, in the order
-// x_pos = rank(f) * NEA + (e - E0), where x = (f - F0) * NEA + (e - E0).
+template <int LC, int LCD>
+inline constexpr KetDfs<LCD> kKetDfs = make_ket_dfs<LC, LCD>();
+
+// One primitive quartet: the recursions above with the ket components in
+// the depth-first order; every output [e0|f0] (la <= |e| <= la+lb,
+// lc <= |f| <= lc+ld) is handed to out(integral_constant<x>, value) as soon
+// as it is final, in the order rank(f) * NEA + (e - E0), where
+// x = (f - F0) * NEA + (e - E0).  AC = A - C (bra and ket anchor centres);
+// P - Q = AC + PA - QC is exact zero when all four shells share one atom.
 template <class Dm, typename Real, class Out>
-__device__ __forceinline__ void prim_quartet_dfs(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
+__device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
                                                  const Real (&AC)[3], const BoysTabs &bt, Out &&out) {
     constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LC = Dm::LC, LCD = Dm::LCD;
     const Real p = P.p, q = Q.p;
@@ -326,7 +244,6 @@ __device__ __forceinline__ void prim_quartet_dfs(const PrimPairT<Real> &P, const
             });
         });
     }
-    constexpr KetDfs<LCD> kd = make_ket_dfs<LC, LCD>();
     auto emit_f = [&](auto FI) {
         constexpr int f = decltype(FI)::value;
         if constexpr (cart_of(f).l() >= LC) {
@@ -343,7 +260,7 @@ __device__ __forceinline__ void prim_quartet_dfs(const PrimPairT<Real> &P, const
         const Real WQ[3] = {p * rpq * PQx, p * rpq * PQy, p * rpq * PQz};
         const Real oo2q = Real(0.5) * Q.rp, rho_q = p * rpq, oo2pq = Real(0.5) * rpq;
         static_for<0, NF>([&](auto SI) {
-            constexpr int f = kd.seq[decltype(SI)::value];
+            constexpr int f = kKetDfs<LC, LCD>.seq[decltype(SI)::value];
             if constexpr (f > 0) {
                 constexpr Cart cf = cart_of(f);
                 constexpr int nf = cf.l();
@@ -373,15 +290,6 @@ __device__ __forceinline__ void prim_quartet_dfs(const PrimPairT<Real> &P, const
             emit_f(std::integral_constant<int, f>{});
         });
     }
-}
-
-// FP64 form used by the existing call sites.
-template <class Dm>
-__device__ __forceinline__ void prim_quartet_f64(const PrimPair &P, const PrimPair &Q, const double (&AC)[3],
-                                                 const double *__restrict__ tab, const double *__restrict__ etab,
-                                                 double (&acc)[Dm::NFA][Dm::NEA]) {
-    const BoysTabs bt{tab, etab, nullptr, nullptr};
-    prim_quartet<Dm, double>(P, Q, AC, bt, acc);
 }
 
 // --------------------------------------------------------------- HRR
@@ -450,7 +358,10 @@ __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo 
         const PrimPairT<Real> Q = pp[ket.pp0 + ik];
         for (int ib = 0; ib < bra.npp; ++ib) {
             const PrimPairT<Real> P = pp[bra.pp0 + ib];
-            prim_quartet<Dm, Real>(P, Q, AC, bt, acc);
+            prim_quartet<Dm, Real>(P, Q, AC, bt, [&](auto X, Real v) {
+                constexpr int x = decltype(X)::value;
+                acc[x / Dm::NEA][x % Dm::NEA] += v;
+            });
         }
     }
     // bra HRR for every ket index f

@@ -33,18 +33,27 @@ __device__ __forceinline__ void rs_step(Real (&v)[NP], const int lane) {
 }
 
 // Position of intermediate x = (f - F0) NEA + (e - E0) in the order
-// prim_quartet_dfs hands them out, and the last position of block b.
-template <class Dm>
-__host__ __device__ constexpr int plane_out_pos(int x) {
-    constexpr KetDfs<Dm::LCD> kd = make_ket_dfs<Dm::LC, Dm::LCD>();
-    return kd.rank[Dm::F0 + x / Dm::NEA] * Dm::NEA + x % Dm::NEA;
+// prim_quartet hands them out, and the last such position of each block of
+// 64 (tables evaluated once per class at compile time).
+template <class Dm, int NACC>
+struct PlaneBlocks {
+    static constexpr int NB = (NACC + 63) / 64;
+    int pos[NB * 64];
+    int last[NB];
+};
+template <class Dm, int NACC>
+__host__ __device__ constexpr PlaneBlocks<Dm, NACC> make_plane_blocks() {
+    PlaneBlocks<Dm, NACC> r{};
+    const KetDfs<Dm::LCD> kd = make_ket_dfs<Dm::LC, Dm::LCD>();
+    for (int b = 0; b < PlaneBlocks<Dm, NACC>::NB; ++b) r.last[b] = -1;
+    for (int x = 0; x < NACC; ++x) {
+        r.pos[x] = kd.rank[Dm::F0 + x / Dm::NEA] * Dm::NEA + x % Dm::NEA;
+        if (r.pos[x] > r.last[x / 64]) r.last[x / 64] = r.pos[x];
+    }
+    return r;
 }
 template <class Dm, int NACC>
-__host__ __device__ constexpr int plane_block_last(int b) {
-    int m = -1;
-    for (int x = 64 * b; x < 64 * b + 64 && x < NACC; ++x) m = plane_out_pos<Dm>(x) > m ? plane_out_pos<Dm>(x) : m;
-    return m;
-}
+inline constexpr PlaneBlocks<Dm, NACC> kPlaneBlocks = make_plane_blocks<Dm, NACC>();
 
 template <class Dm, int MODE, typename Real>
 __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
@@ -92,11 +101,11 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
                 constexpr int x = decltype(X)::value;
                 vb[x / 64][x % 64] = Real(0);
             });
-            prim_quartet_dfs<Dm, Real>(P, Q, AC, bt, [&](auto X, Real val) {
+            prim_quartet<Dm, Real>(P, Q, AC, bt, [&](auto X, Real val) {
                 constexpr int x = decltype(X)::value;
                 constexpr int b = x / 64;
                 vb[b][x % 64] = val;
-                if constexpr (plane_block_last<Dm, NACC>(b) == plane_out_pos<Dm>(x)) {
+                if constexpr (kPlaneBlocks<Dm, NACC>.last[b] == kPlaneBlocks<Dm, NACC>.pos[x]) {
                     rs_step<64, 64, 32>(vb[b], lane);
                     rs_step<64, 32, 16>(vb[b], lane);
                     rs_step<64, 16, 8>(vb[b], lane);
