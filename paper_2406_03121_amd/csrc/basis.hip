@@ -190,7 +190,10 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
         q.p = p;
         q.K = ca * cb * exp(-a * b * rp * ab2);
         q.rp = rp;
-        q.pad0 = q.pad1 = 0.0;
+        // the primitive-quartet prefactor 2 pi^{5/2} K_P K_Q / (p q sqrt(p+q))
+        // is then Kr_P Kr_Q (p+q)^{-1/2}
+        q.Kr = 5.9149671727956129 * q.K * rp;
+        q.pad1 = 0.0;
         pp[k] = q;
     }
 }
@@ -668,7 +671,7 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
         std::vector<PrimPairF> hf(npp);
         for (int i = 0; i < npp; ++i)
             hf[i] = PrimPairF{(float)h[i].PAx, (float)h[i].PAy, (float)h[i].PAz, (float)h[i].p,
-                              (float)h[i].K, (float)h[i].rp, 0.0f, 0.0f};
+                              (float)h[i].K, (float)h[i].rp, (float)h[i].Kr, 0.0f};
         MESS_HIPC(hipMalloc(&B->d_ppf, sizeof(PrimPairF) * npp));
         MESS_HIPC(hipMemcpy(B->d_ppf, hf.data(), sizeof(PrimPairF) * npp, hipMemcpyHostToDevice));
     }

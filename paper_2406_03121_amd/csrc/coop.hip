@@ -597,7 +597,7 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
             const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
             __syncthreads();  // previous round fully consumed
             if (act && gl <= A.L) {
-                const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
+                const Real pref = P.Kr * Q.Kr * spq;
                 V[1 + gl] = pref * coop_boys_r<Real>(gl, T, bt);
             }
             VrrCoef<Real> cf;

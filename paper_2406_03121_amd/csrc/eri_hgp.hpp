@@ -215,7 +215,7 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
     const Real rho = p * q * rpq;
     const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
     const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    const Real pref = Real(34.986836655249725) * P.rp * Q.rp * spq * P.K * Q.K;
+    const Real pref = P.Kr * Q.Kr * spq;  // 2 pi^{5/2} K_P K_Q / (p q sqrt(p+q))
 
     Real F[L + 1];
     boys_eval<L, Real>(T, bt, F);

@@ -123,12 +123,12 @@ struct PairInfo {
 // The Gaussian product centre is P = A + PA.
 struct PrimPair {
     double PAx, PAy, PAz, p;
-    double K, rp, pad0, pad1;  // rp = 1/p
+    double K, rp, Kr, pad1;  // rp = 1/p, Kr = sqrt(2 pi^{5/2}) K / p
 };
 
 struct PrimPairF {
     float PAx, PAy, PAz, p;
-    float K, rp, pad0, pad1;
+    float K, rp, Kr, pad1;
 };
 
 // Boys table: F_n(T_k), n = 0..kBoysN-1, T_k = k / kBoysInvStep, T_k <= kBoysTmax.

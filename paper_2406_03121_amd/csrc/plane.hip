@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
             const int kk = k < nprim ? k : 0;
             PrimPairT<Real> P = pp[bra.pp0 + kk / ket.npp];
             const PrimPairT<Real> Q = pp[ket.pp0 + kk % ket.npp];
-            if (k >= nprim) P.K = Real(0);
+            if (k >= nprim) P.Kr = Real(0);
             // intermediates in blocks of 64; each block is reduce-scattered
             // over the wave (lane l keeps entry 64 b + l) as soon as its last
             // entry is final, so finished outputs do not stay live through
