@@ -678,10 +678,11 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
         return MESS_OK;
     }
     const size_t rsz = prec == MESS_FP32 ? sizeof(float) : sizeof(double);
-    // primitive quartets in flight per block: two for (dd|dp), whose levels
-    // are too small to keep 256 threads busy on one (measured: four for
-    // (dd|dp) and two for (dd|dd) are slower)
-    const int np = (cb == 5 && ck == 4) ? 2 : 1;
+    // two primitive quartets in flight per block (two slot regions, 128
+    // threads each): the levels are too small to keep 256 threads busy on
+    // one (measured: one is slower for (dd|dp), 258 vs 182 ms over three
+    // SCFs, and for (dd|dd), 137 vs 131; four is slower for (dd|dp), 193)
+    const int np = 2;
     const int vstride = (int)(((size_t)P->nV * rsz + 7) / 8 * 8 / rsz);  // whole doubles per region
     const int region = (int)std::max<size_t>((np * (size_t)vstride * rsz + 7) / 8, (size_t)(P->nH - P->nacc));
     const size_t lds = sizeof(double) * ((size_t)P->nacc + region + kNHCoef);
@@ -696,16 +697,8 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
                        PP, bt, D, L.N, out0, out1)
 #define MESS_COOP_M(MODE)                                                            \
     do {                                                                             \
-        if (np == 4) {                                                               \
-            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 4);              \
-            else MESS_COOP_GO(MODE, double, L.pp, 4);                                \
-        } else if (np == 2) {                                                        \
-            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 2);              \
-            else MESS_COOP_GO(MODE, double, L.pp, 2);                                \
-        } else {                                                                     \
-            if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 1);              \
-            else MESS_COOP_GO(MODE, double, L.pp, 1);                                \
-        }                                                                            \
+        if (prec == MESS_FP32) MESS_COOP_GO(MODE, float, L.ppf, 2);                  \
+        else MESS_COOP_GO(MODE, double, L.pp, 2);                                    \
     } while (0)
     switch (mode) {
         case kModeSchwarz: MESS_COOP_M(kModeSchwarz); break;
