@@ -353,15 +353,25 @@ __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo 
     const Real AC[3] = {Real(bra.Ax - ket.Ax), Real(bra.Ay - ket.Ay), Real(bra.Az - ket.Az)};
     // Lanes of a wave take consecutive quartets of one bra row: the ket's
     // primitive pairs (different for every lane) are read once each, the
-    // bra's (the same for the wave) in the inner loop.
-    for (int ik = 0; ik < ket.npp; ++ik) {
-        const PrimPairT<Real> Q = pp[ket.pp0 + ik];
-        for (int ib = 0; ib < bra.npp; ++ib) {
-            const PrimPairT<Real> P = pp[bra.pp0 + ib];
-            prim_quartet<Dm, Real>(P, Q, AC, bt, [&](auto X, Real v) {
-                constexpr int x = decltype(X)::value;
-                acc[x / Dm::NEA][x % Dm::NEA] += v;
-            });
+    // bra's (the same for the wave) in the inner loop.  When every active
+    // lane has the same bra pair (the usual case), its primitive pairs are
+    // read once for the wave through the scalar cache.
+    auto add = [&](auto X, Real v) {
+        constexpr int x = decltype(X)::value;
+        acc[x / Dm::NEA][x % Dm::NEA] += v;
+    };
+    const int pbu = __builtin_amdgcn_readfirstlane(bra.pp0);
+    if (__all(bra.pp0 == pbu)) {
+        const int nbu = __builtin_amdgcn_readfirstlane(bra.npp);
+        const PrimPairT<Real> *__restrict__ pb = pp + pbu;
+        for (int ik = 0; ik < ket.npp; ++ik) {
+            const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+            for (int ib = 0; ib < nbu; ++ib) prim_quartet<Dm, Real>(pb[ib], Q, AC, bt, add);
+        }
+    } else {
+        for (int ik = 0; ik < ket.npp; ++ik) {
+            const PrimPairT<Real> Q = pp[ket.pp0 + ik];
+            for (int ib = 0; ib < bra.npp; ++ib) prim_quartet<Dm, Real>(pp[bra.pp0 + ib], Q, AC, bt, add);
         }
     }
     // bra HRR for every ket index f
