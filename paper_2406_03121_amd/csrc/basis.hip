@@ -28,9 +28,10 @@ void set_error(const char *fmt, ...) {
 // (all terms positive), lower orders by the stable downward recurrence
 //   F_n = (2T F_{n+1} + e^{-T}) / (2n+1).
 
-static void build_boys_table(std::vector<double> &tab, std::vector<double> &etab) {
+static void build_boys_table(std::vector<double> &tab, std::vector<double> &etab, std::vector<double> &tabt) {
     tab.assign((size_t)kBoysRows * kBoysN, 0.0);
     etab.assign(kBoysRows, 0.0);
+    tabt.assign((size_t)kBoysTL * kBoysRows * 8, 0.0);
     for (int k = 0; k < kBoysRows; ++k) {
         const long double T = (long double)k / (long double)kBoysInvStep;
         const long double eT = expl(-T);
@@ -46,6 +47,13 @@ static void build_boys_table(std::vector<double> &tab, std::vector<double> &etab
         for (int m = n - 1; m >= 0; --m) F[m] = (2.0L * T * F[m + 1] + eT) / (long double)(2 * m + 1);
         for (int m = 0; m < kBoysN; ++m) tab[(size_t)k * kBoysN + m] = (double)F[m];
         etab[k] = (double)eT;
+        for (int L = 0; L < kBoysTL; ++L) {
+            long double fact = 1.0L;
+            for (int i = 0; i < 8; ++i) {
+                if (i > 0) fact *= (long double)i;
+                tabt[((size_t)L * kBoysRows + k) * 8 + i] = (double)(F[L + i] / fact);
+            }
+        }
     }
 }
 
@@ -235,6 +243,7 @@ static int make_class_launch(const mess_basis *B, ClassLaunch &L, hipStream_t s)
     L.ppf = B->d_ppf;
     L.tab = B->d_boys;
     L.etab = B->d_boys_exp;
+    L.tabt = B->d_boys_t;
     L.tabf = B->d_boys_f;
     L.etabf = B->d_boys_exp_f;
     L.N = B->nbf;
@@ -362,6 +371,7 @@ static void free_basis(mess_basis *B) {
     hipFree(B->d_Zd);
     hipFree(B->d_boys);
     hipFree(B->d_boys_exp);
+    hipFree(B->d_boys_t);
     hipFree(B->d_boys_f);
     hipFree(B->d_boys_exp_f);
     hipFree(B->d_pairs);
@@ -516,10 +526,13 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
 
     // Boys tables
     std::vector<double> tab, etab;
-    build_boys_table(tab, etab);
+    std::vector<double> tabt;
+    build_boys_table(tab, etab, tabt);
     std::vector<float> tabf(tab.begin(), tab.end()), etabf(etab.begin(), etab.end());
     MESS_HIP(hipMalloc(&B->d_boys, sizeof(double) * tab.size()));
     MESS_HIP(hipMalloc(&B->d_boys_exp, sizeof(double) * etab.size()));
+    MESS_HIP(hipMalloc(&B->d_boys_t, sizeof(double) * tabt.size()));
+    MESS_HIP(hipMemcpy(B->d_boys_t, tabt.data(), sizeof(double) * tabt.size(), hipMemcpyHostToDevice));
     MESS_HIP(hipMalloc(&B->d_boys_f, sizeof(float) * tabf.size()));
     MESS_HIP(hipMalloc(&B->d_boys_exp_f, sizeof(float) * etabf.size()));
     MESS_HIP(hipMemcpy(B->d_boys, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));

@@ -13,6 +13,7 @@ struct ClassLaunch {
     const PrimPairF *ppf;
     const double *tab, *etab;
     const float *tabf, *etabf;
+    const double *tabt;  // per-order Taylor table (F_{L+i}(T_k) / i!)
     int bra_off, ket_off, nbra, same_class;  // nbra: rows of the work list
     const int64_t *rowstart;
     const int2 *rowmap;  // per row: {bra index, first ket index}

@@ -690,7 +690,7 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
         set_error("internal: class (%d,%d) needs %zu bytes of LDS", cb, ck, lds);
         return MESS_E_UNSUPPORTED;
     }
-    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
 #define MESS_COOP_GO(MODE, R, PP, NPV)                                                                            \
     hipLaunchKernelGGL((k_coop<MODE, R, 256, NPV>), dim3((unsigned)g), dim3(256), lds, L.stream, A, region,      \
                        vstride, L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, total, \

@@ -30,7 +30,7 @@ int ClassOps<MESS_CB, MESS_CK>::schwarz(const ClassLaunch &L, int off, int n, do
         using Dm = ClassOf<MESS_CB, MESS_CK>;
         if (n <= 0) return MESS_OK;
         hipLaunchKernelGGL(k_schwarz<Dm>, dim3((n + 63) / 64), dim3(64), 0, L.stream, L.pairs, off, n,
-                           L.pp, L.tab, L.etab, Q);
+                           L.pp, BoysTabs{L.tab, L.etab, L.tabf, L.etabf, L.tabt}, Q);
         MESS_LAUNCH_CHECK();
         return MESS_OK;
     }
@@ -40,7 +40,7 @@ template <>
 int ClassOps<MESS_CB, MESS_CK>::dense(const ClassLaunch &L, double *eri, int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
-    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_eri_dense<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
                            L.pairs, L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.ppf, bt, (int64_t)L.N, eri);
@@ -56,7 +56,7 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
                                    int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
-    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_jk_direct<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
                            L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.ppf, bt, D, L.N, Gj,
@@ -73,7 +73,7 @@ template <>
 int ClassOps<MESS_CB, MESS_CK>::store(const ClassLaunch &L, void *base, int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
-    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_eri_store<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream, L.pairs,
                            L.bra_off, L.ket_off, L.nbra, L.rowstart, L.rowmap, L.ppf, bt, static_cast<float *>(base));

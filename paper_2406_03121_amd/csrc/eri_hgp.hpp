@@ -87,7 +87,53 @@ __device__ __forceinline__ void boys_f64(double T, const double *__restrict__ ta
 struct BoysTabs {
     const double *tab, *etab;
     const float *tabf, *etabf;
+    const double *tabt;  // F_{L+i}(T_k) / i! per order L (FP64 Taylor with no per-term scaling)
 };
+
+// FP64 F_0..F_L as boys_f64, the Taylor sums in Horner form on the
+// prescaled table (F_{L+i}(T_k)/i!) and the constants 1/i! for exp(-T):
+// seven FMAs each.
+template <int L>
+__device__ __forceinline__ void boys_f64t(double T, const double *__restrict__ tabt, const double *__restrict__ etab,
+                                          double (&F)[L + 1]) {
+    if (T < kBoysTmax) {
+        const int k = __double2int_rn(T * kBoysInvStep);
+        const double md = static_cast<double>(k) * (1.0 / kBoysInvStep) - T;  // -(T - T_k), exact
+        const double *row = tabt + ((size_t)L * kBoysRows + k) * 8;
+        double f = row[7];
+        f = row[6] + md * f;
+        f = row[5] + md * f;
+        f = row[4] + md * f;
+        f = row[3] + md * f;
+        f = row[2] + md * f;
+        f = row[1] + md * f;
+        f = row[0] + md * f;
+        F[L] = f;
+        if constexpr (L > 0) {
+            double e = 1.0 / 5040.0;
+            e = 1.0 / 720.0 + md * e;
+            e = 1.0 / 120.0 + md * e;
+            e = 1.0 / 24.0 + md * e;
+            e = 1.0 / 6.0 + md * e;
+            e = 0.5 + md * e;
+            e = 1.0 + md * e;
+            e = 1.0 + md * e;
+            e *= etab[k];
+            const double t2 = 2.0 * T;
+            static_for<0, L>([&](auto I) {
+                constexpr int m = L - 1 - decltype(I)::value;
+                F[m] = (t2 * F[m + 1] + e) * (1.0 / (2 * m + 1));
+            });
+        }
+    } else {
+        const double sT = rsqrt_nr(T), rT = sT * sT;
+        F[0] = 0.88622692545275801365 * sT;  // sqrt(pi) / 2
+        static_for<0, L>([&](auto I) {
+            constexpr int m = decltype(I)::value;
+            F[m + 1] = F[m] * ((2 * m + 1) * 0.5) * rT;
+        });
+    }
+}
 
 template <int L>
 __device__ __forceinline__ void boys_f32(float T, const BoysTabs &bt, float (&F)[L + 1]) {
@@ -125,7 +171,7 @@ __device__ __forceinline__ void boys_f32(float T, const BoysTabs &bt, float (&F)
 template <int L, typename Real>
 __device__ __forceinline__ void boys_eval(Real T, const BoysTabs &bt, Real (&F)[L + 1]) {
     if constexpr (sizeof(Real) == 8)
-        boys_f64<L>(T, bt.tab, bt.etab, F);
+        boys_f64t<L>(T, bt.tabt, bt.etab, F);
     else
         boys_f32<L>(T, bt, F);
 }
@@ -405,9 +451,8 @@ __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo 
 
 template <class Dm>
 __device__ __forceinline__ void eri_quartet_f64(const PairInfo &bra, const PairInfo &ket,
-                                                const PrimPair *__restrict__ pp, const double *__restrict__ tab,
-                                                const double *__restrict__ etab, double (&out)[Dm::NOUT]) {
-    const BoysTabs bt{tab, etab, nullptr, nullptr};
+                                                const PrimPair *__restrict__ pp, const BoysTabs &bt,
+                                                double (&out)[Dm::NOUT]) {
     eri_quartet<Dm, double>(bra, ket, pp, bt, out);
 }
 

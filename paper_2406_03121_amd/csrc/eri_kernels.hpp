@@ -30,15 +30,13 @@ __device__ __forceinline__ int2 quartet_pairs(const int64_t *__restrict__ rowsta
 // Q = sqrt(max_{a in sa, b in sb} |(ab|ab)|) for every pair of one class.
 template <class Dm>
 __global__ void __launch_bounds__(64) k_schwarz(const PairInfo *__restrict__ pairs, int off, int n,
-                                                const PrimPair *__restrict__ pp,
-                                                const double *__restrict__ tab,
-                                                const double *__restrict__ etab,
+                                                const PrimPair *__restrict__ pp, BoysTabs bt,
                                                 double *__restrict__ Q) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const PairInfo pr = pairs[off + i];
     double out[Dm::NOUT];
-    eri_quartet_f64<Dm>(pr, pr, pp, tab, etab, out);
+    eri_quartet_f64<Dm>(pr, pr, pp, bt, out);
     double m = 0.0;
     static_for<0, Dm::NAB>([&](auto I) {
         constexpr int ab = decltype(I)::value;

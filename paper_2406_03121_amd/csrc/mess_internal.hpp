@@ -136,6 +136,8 @@ constexpr int kBoysN = 16;
 constexpr double kBoysInvStep = 16.0;
 constexpr double kBoysTmax = 60.0;
 constexpr int kBoysRows = 961;  // kBoysTmax * kBoysInvStep + 1
+// Taylor table per order L = 0..kBoysTL-1: row k holds F_{L+i}(T_k) / i!, i < 8.
+constexpr int kBoysTL = kBoysN - 7;
 
 // Pair classes (l_a, l_b), l_a >= l_b: ss ps pp ds dp dd.
 constexpr int kNumPairClasses = 6;
@@ -218,6 +220,7 @@ struct mess_basis {
     double *d_Zd = nullptr;    // [nat] charges as double
     double *d_boys = nullptr;  // [kBoysRows * kBoysN]
     double *d_boys_exp = nullptr;  // [kBoysRows]: exp(-T_k)
+    double *d_boys_t = nullptr;    // [kBoysTL][kBoysRows][8]: F_{L+i}(T_k) / i!
     float *d_boys_f = nullptr;     // FP32 copy of the table
     float *d_boys_exp_f = nullptr;
 

@@ -133,7 +133,7 @@ void PlaneOps<MESS_PCB, MESS_PCK, MESS_PREAL>::launch(int mode, const CoopArgs &
                                                       double *out0, double *out1) {
     using Dm = ClassOf<MESS_PCB, MESS_PCK>;
     using R = MESS_PREAL;
-    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf};
+    const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
     const PrimPairT<R> *pp;
     pp = reinterpret_cast<const PrimPairT<R> *>(sizeof(R) == 8 ? (const void *)L.pp : (const void *)L.ppf);
     switch (mode) {
