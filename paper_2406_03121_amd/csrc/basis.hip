@@ -263,6 +263,9 @@ int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, C
     L.same_class = cl.cb == cl.ck;
     L.rowstart = cl.d_rowstart;
     L.rowmap = cl.d_rowmap;
+    L.segs = cl.d_segs;
+    L.nseg = cl.d_segs ? cl.nseg : 0;
+    L.nmax = B->nbf_max;
     L.total = cl.total;
     return MESS_OK;
 }
@@ -323,15 +326,33 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
             }
             cl.nrow = (int)cl.h_rowmap.size();
             cl.total = cl.h_rowstart.back();
+            std::vector<int4> segs;
+            if (cl.total < ((int64_t)1 << 31))
+                for (int r0 = 0; r0 < cl.nrow;) {
+                    int r1 = r0 + 1;
+                    while (r1 < cl.nrow && cl.h_rowmap[r1].x == cl.h_rowmap[r0].x) ++r1;
+                    int rq = r0;  // row holding quartet q
+                    for (int64_t q = cl.h_rowstart[r0]; q < cl.h_rowstart[r1]; q += kSegLen) {
+                        const int64_t e = std::min(q + kSegLen, cl.h_rowstart[r1]);
+                        while (cl.h_rowstart[rq + 1] <= q) ++rq;
+                        segs.push_back(make_int4(rq, (int)q, (int)e, r1));
+                    }
+                    r0 = r1;
+                }
+            cl.nseg = (int)segs.size();
             if (cl.nrow > 0) {
                 if (hipMalloc(&cl.d_rowstart, sizeof(int64_t) * (cl.nrow + 1)) != hipSuccess ||
                     hipMalloc(&cl.d_rowmap, sizeof(int2) * cl.nrow) != hipSuccess ||
+                    (cl.nseg > 0 && hipMalloc(&cl.d_segs, sizeof(int4) * cl.nseg) != hipSuccess) ||
+                    (cl.nseg > 0 && hipMemcpy(cl.d_segs, segs.data(), sizeof(int4) * cl.nseg,
+                                              hipMemcpyHostToDevice) != hipSuccess) ||
                     hipMemcpy(cl.d_rowstart, cl.h_rowstart.data(), sizeof(int64_t) * (cl.nrow + 1),
                               hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(cl.d_rowmap, cl.h_rowmap.data(), sizeof(int2) * cl.nrow, hipMemcpyHostToDevice) !=
                         hipSuccess) {
                     hipFree(cl.d_rowstart);
                     hipFree(cl.d_rowmap);
+                    hipFree(cl.d_segs);
                     set_error("hipMalloc(work list) failed");
                     rc = MESS_E_NOMEM;
                     break;
@@ -343,6 +364,7 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
         for (auto &cl : W->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
             if (cl.d_rowmap) hipFree(cl.d_rowmap);
+            if (cl.d_segs) hipFree(cl.d_segs);
         }
         delete W;
         return rc;
@@ -358,6 +380,7 @@ static void free_basis(mess_basis *B) {
         for (auto &cl : kv.second->classes) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
             if (cl.d_rowmap) hipFree(cl.d_rowmap);
+            if (cl.d_segs) hipFree(cl.d_segs);
         }
         delete kv.second;
     }

@@ -21,7 +21,7 @@ struct ClassLaunch {
     int N;
     hipStream_t stream;
     // stored-block digestion by bra-row segments (NULL: one lane per quartet)
-    const int4 *segs = nullptr;  // {row, first quartet, end quartet, 0}
+    const int4 *segs = nullptr;  // {first row, first quartet, end quartet, end row}
     int nseg = 0;
     int nmax = 0;                // largest molecule dimension (LDS rows)
 };

@@ -57,6 +57,26 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
+    if constexpr (MESS_CB != 2 && MESS_CK != 2 && (MESS_CB <= 3 || MESS_CK == 0)) {
+        // one 256-thread block per bra segment, K rows of the bra functions
+        // in LDS and J[a,b] in registers (one flush per segment), so only
+        // J[c,d] takes a global atomic per quartet (measured slower this way:
+        // classes with a pp pair, and dp or dd bras with a ps ket)
+        const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
+        if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
+            const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
+            if (prec == MESS_FP32)
+                hipLaunchKernelGGL((k_jk_stored_rows<Dm, float, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
+                                   L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
+                                   (const float *)nullptr, L.total, D, Gj, Gk, L.ppf, bt);
+            else
+                hipLaunchKernelGGL((k_jk_stored_rows<Dm, double, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
+                                   L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
+                                   (const double *)nullptr, L.total, D, Gj, Gk, L.pp, bt);
+            MESS_LAUNCH_CHECK();
+            return MESS_OK;
+        }
+    }
     if (prec == MESS_FP32)
         hipLaunchKernelGGL((k_jk_direct<Dm, float>), dim3(grid_for(L.total, 128)), dim3(128), 0, L.stream,
                            L.pairs, L.bra_off, L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.ppf, bt, D, L.N, Gj,

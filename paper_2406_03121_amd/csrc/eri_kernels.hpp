@@ -220,13 +220,17 @@ __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ 
 // to the half-matrices once per segment; only J[c,d] goes to global memory
 // per quartet.  This cuts the FP64 global atomics, which bound the
 // streaming digestion, by a factor of up to six for the low classes.
-template <class Dm, typename Real>
+// DIRECT: the same digestion with each quartet's block computed by the
+// recursion instead of read from the store (base unused).
+template <class Dm, typename Real, bool DIRECT = false>
 __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
                                                         int same_class, const int64_t *__restrict__ rowstart,
                                                         const int2 *__restrict__ rowmap, const int4 *__restrict__ segs,
                                                         int nseg, const Real *__restrict__ base, int64_t total,
                                                         const double *__restrict__ Dall, double *__restrict__ Gjall,
-                                                        double *__restrict__ Gkall) {
+                                                        double *__restrict__ Gkall,
+                                                        const PrimPairT<Real> *__restrict__ pp = nullptr,
+                                                        BoysTabs bt = BoysTabs{}) {
     constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND;
     extern __shared__ double lds[];
     for (int sidx = blockIdx.x; sidx < nseg; sidx += gridDim.x) {
@@ -253,7 +257,10 @@ __global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restri
             const PairInfo ket = pairs[ket_off + j];
             const int c0 = ket.bfa, d0 = ket.bfb;
             Real out[Dm::NOUT];
-            static_for<0, Dm::NOUT>([&](auto I) { out[I] = base[(int64_t)decltype(I)::value * total + q]; });
+            if constexpr (DIRECT)
+                eri_quartet<Dm, Real>(bra, ket, pp, bt, out);
+            else
+                static_for<0, Dm::NOUT>([&](auto I) { out[I] = base[(int64_t)decltype(I)::value * total + q]; });
             double fac = 1.0;
             if (bra.sa == bra.sb) fac *= 0.5;
             if (ket.sa == ket.sb) fac *= 0.5;

@@ -173,7 +173,13 @@ struct ClassList {
     int2 *d_rowmap = nullptr;         // nrow
     std::vector<int64_t> h_rowstart;  // host copies
     std::vector<int2> h_rowmap;
+    // the quartets of each bra (its consecutive rows) in pieces of at most
+    // kSegLen: {first row, first quartet, end quartet, end row}; NULL when
+    // the list has 2^31 quartets or more
+    int4 *d_segs = nullptr;
+    int nseg = 0;
 };
+constexpr int64_t kSegLen = 1024;
 
 // Index 0..20 of the class (cb >= ck).
 inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
