@@ -66,11 +66,11 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
         if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
             const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
             if (prec == MESS_FP32)
-                hipLaunchKernelGGL((k_jk_stored_rows<Dm, float, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
+                hipLaunchKernelGGL((k_jk_rows<Dm, float, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
                                    L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                    (const float *)nullptr, L.total, D, Gj, Gk, L.ppf, bt);
             else
-                hipLaunchKernelGGL((k_jk_stored_rows<Dm, double, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
+                hipLaunchKernelGGL((k_jk_rows<Dm, double, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,
                                    L.bra_off, L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                    (const double *)nullptr, L.total, D, Gj, Gk, L.pp, bt);
             MESS_LAUNCH_CHECK();
@@ -113,11 +113,11 @@ int ClassOps<MESS_CB, MESS_CK>::jk_stored(const ClassLaunch &L, const void *base
     if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
         const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
         if (prec == MESS_FP32)
-            hipLaunchKernelGGL((k_jk_stored_rows<Dm, float>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
+            hipLaunchKernelGGL((k_jk_rows<Dm, float>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
                                L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                static_cast<const float *>(base), L.total, D, Gj, Gk);
         else
-            hipLaunchKernelGGL((k_jk_stored_rows<Dm, double>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
+            hipLaunchKernelGGL((k_jk_rows<Dm, double>), dim3(g), dim3(256), lds, L.stream, L.pairs, L.bra_off,
                                L.ket_off, L.same_class, L.rowstart, L.rowmap, L.segs, L.nseg,
                                static_cast<const double *>(base), L.total, D, Gj, Gk);
         MESS_LAUNCH_CHECK();

@@ -212,18 +212,18 @@ __global__ void __launch_bounds__(128) k_jk_stored(const PairInfo *__restrict__ 
     }
 }
 
-// J/K from stored blocks, one 256-thread block per segment of one bra row
-// (at most a few thousand quartets sharing the bra pair (ab)).  Every
+// J/K by bra segments: one 256-thread block per segment of one bra's
+// quartets (at most kSegLen sharing the bra pair (ab)).  Every
 // exchange family and J[a,b] index rows of the bra pair's functions, so they
 // are accumulated in LDS (K rows of a and b, NA + NB rows of the molecule's
 // N columns) and in registers (J[a,b], reduced over the wave), and flushed
 // to the half-matrices once per segment; only J[c,d] goes to global memory
 // per quartet.  This cuts the FP64 global atomics, which bound the
-// streaming digestion, by a factor of up to six for the low classes.
-// DIRECT: the same digestion with each quartet's block computed by the
+// streaming digestion and much of the direct one for the low classes, by a
+// factor of up to six.  DIRECT: each quartet's block is computed by the
 // recursion instead of read from the store (base unused).
 template <class Dm, typename Real, bool DIRECT = false>
-__global__ void __launch_bounds__(256) k_jk_stored_rows(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+__global__ void __launch_bounds__(256) k_jk_rows(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
                                                         int same_class, const int64_t *__restrict__ rowstart,
                                                         const int2 *__restrict__ rowmap, const int4 *__restrict__ segs,
                                                         int nseg, const Real *__restrict__ base, int64_t total,
