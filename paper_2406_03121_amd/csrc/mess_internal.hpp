@@ -179,7 +179,7 @@ struct ClassList {
     int4 *d_segs = nullptr;
     int nseg = 0;
 };
-constexpr int64_t kSegLen = 1024;
+constexpr int64_t kSegLen = 512;
 
 // Index 0..20 of the class (cb >= ck).
 inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
