@@ -341,6 +341,35 @@ int mess_prof_enable(int32_t on);
 int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops, int64_t *quartets,
                    int64_t *prim_quartets);
 
+/* ---- Kernel forms and the autotuner ----
+ * Each angular class can run in several mappings onto the GPU:
+ *   MESS_FORM_LANE   one lane per shell quartet (recursion in registers);
+ *   MESS_FORM_ROWS   one block per segment of a bra's quartets, exchange rows
+ *                    of the bra functions accumulated in LDS (low classes);
+ *   MESS_FORM_PLANE  one wave per shell quartet, one lane per primitive
+ *                    quartet, intermediates summed across the wave;
+ *   MESS_FORM_COOP   one block per shell quartet, the recursion table-driven
+ *                    in LDS (high classes).
+ * The choice is process-wide and applies to every later launch (mess_eri,
+ * mess_jk, SCF and batch steps; FP64 and FP32).
+ *
+ * mess_kernel_form: set the form of class cls (index as for
+ * mess_work_stats) when form >= 0 (MESS_FORM_AUTO restores the built-in
+ * default), and return the active form in *active (may be NULL).
+ * MESS_E_UNSUPPORTED if the form is not built for the class.
+ *
+ * mess_autotune: for every class with quartets in the basis's work list at
+ * schwarz_tol, time each available form on a direct J/K pass with density D
+ * (device N x N, or packed for a batch) as the best of reps runs after one
+ * warm-up (HIP events on the stream), and keep the fastest.  forms[21]
+ * (host, may be NULL) receives the chosen forms; ms[21 * 5] (host, may be
+ * NULL) the best time of form f for class c at ms[c * 5 + f] (-1 where not
+ * run).  Synchronises the stream; uses the basis's own J/K work buffer. */
+enum { MESS_FORM_AUTO = 0, MESS_FORM_LANE = 1, MESS_FORM_ROWS = 2, MESS_FORM_PLANE = 3, MESS_FORM_COOP = 4 };
+int mess_kernel_form(int32_t cls, int32_t form, int32_t *active);
+int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, int32_t reps, int32_t *forms,
+                  double *ms, mess_stream stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *mess_last_error(void);
 

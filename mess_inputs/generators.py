@@ -302,3 +302,13 @@ def mlp_initial_params(seed: int = 0) -> np.ndarray:
 def guess_train_seeds():
     """Training, validation and test molecule seeds of the learned guess."""
     return range(100000, 110000), range(110000, 110500), range(1000, 2024)
+
+
+# ---------------------------------------------------------------- densities
+
+def symmetric_density(n: int, seed: int = 0) -> np.ndarray:
+    """A seeded symmetric N x N test density: (A + A^T)/2 with A standard
+    normal (PCG64(seed)).  Not a physical density; J/K are linear in D."""
+    rng = _rng(seed)
+    A = rng.normal(size=(n, n))
+    return (A + A.T) / 2

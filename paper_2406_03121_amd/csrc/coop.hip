@@ -459,6 +459,14 @@ bool coop_class(int cb, int ck) {
     return (cb == 5 && ck >= 2) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
 }
 
+// True when class (cb, ck) needs no cooperative step tables or they are
+// already on the device (nothing left to allocate for its launches).
+bool coop_program_cached(int cb, int ck) {
+    if (!coop_class(cb, ck)) return true;
+    std::lock_guard<std::mutex> lk(g_prog_mutex);
+    return g_programs.count(std::make_pair(cb, ck)) != 0;
+}
+
 static const CoopProgram *coop_program(int cb, int ck) {
     std::lock_guard<std::mutex> lk(g_prog_mutex);
     auto key = std::make_pair(cb, ck);
@@ -631,13 +639,9 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
     }
 }
 
-// Classes run with the primitive-lane mapping in FP64 (measured faster than
-// the table-driven kernel; for (dd|dp) and (dd|dd) the unrolled recursion
-// spills too much and the table-driven kernel wins).  In FP32 the
-// primitive-lane mapping serves every high class except (dd|dp), (dd|dd).
-static bool plane_class(int cb, int ck) {
-    return (cb == 5 && (ck == 2 || ck == 3)) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
-}
+// Classes run with the primitive-lane mapping: the form chosen for the
+// class (built-in default or autotuned; see tune.hip).
+static bool plane_class(int cb, int ck) { return plane_compiled(cb, ck) && class_form(cb, ck) == kFormPlane; }
 
 static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, const ClassLaunch &L, int64_t total,
                          unsigned g, size_t lds, const double *D, double *out0, double *out1) {
@@ -646,6 +650,8 @@ static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, 
         if (prec == MESS_FP32) PlaneOps<B, K, float>::launch(mode, A, L, total, g, lds, D, out0, out1);  \
         else PlaneOps<B, K, double>::launch(mode, A, L, total, g, lds, D, out0, out1);                   \
     }
+    MESS_PL(5, 5)
+    MESS_PL(5, 4)
     MESS_PL(5, 3)
     MESS_PL(5, 2)
     MESS_PL(4, 4)

@@ -61,9 +61,10 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
         // one 256-thread block per bra segment, K rows of the bra functions
         // in LDS and J[a,b] in registers (one flush per segment), so only
         // J[c,d] takes a global atomic per quartet (measured slower this way:
-        // classes with a pp pair, and dp or dd bras with a ps ket)
+        // classes with a pp pair, and dp or dd bras with a ps ket); the
+        // default form of these classes unless the form table says lane
         const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
-        if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
+        if (L.segs && L.nseg > 0 && lds <= 48 * 1024 && class_form(MESS_CB, MESS_CK) == kFormRows) {
             const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
             if (prec == MESS_FP32)
                 hipLaunchKernelGGL((k_jk_rows<Dm, float, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,

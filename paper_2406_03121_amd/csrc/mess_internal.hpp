@@ -189,6 +189,21 @@ inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
 // and per shell quartet (horizontal recursion + J/K digestion).
 void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk);
 
+// True when class (cb, ck) has nothing left to allocate on the device for
+// its launches (cooperative step tables built, or none needed).
+bool coop_program_cached(int cb, int ck);
+// Classes evaluated by the wave-per-quartet kernels (coop.hip, plane.hip).
+bool coop_class(int cb, int ck);
+
+// Kernel form of a class (tune.hip): the mapping of its quartets onto the
+// hardware.  Values match the MESS_FORM_* constants of the C ABI.
+enum : int { kFormAuto = 0, kFormLane = 1, kFormRows = 2, kFormPlane = 3, kFormCoop = 4, kNumForms = 5 };
+constexpr int kNumClasses = 21;
+int class_form(int cb, int ck);       // active form (built-in default unless set)
+bool form_valid(int cb, int ck, int form);
+bool plane_compiled(int cb, int ck);  // primitive-lane kernel built for the class
+bool rows_compiled(int cb, int ck);   // bra-segment kernel built for the class
+
 // Profiling of class launches (HIP events on the launch stream).
 bool prof_on();
 void prof_record(hipStream_t s, int cls, bool begin, int64_t quartets, int64_t prims, double flops);

@@ -33,27 +33,32 @@ __device__ __forceinline__ void rs_step(Real (&v)[NP], const int lane) {
 }
 
 // Position of intermediate x = (f - F0) NEA + (e - E0) in the order
-// prim_quartet hands them out, and the last such position of each block of
-// 64 (tables evaluated once per class at compile time).
+// prim_quartet hands them out, and its inverse (tables evaluated once per
+// class at compile time).  Blocks of 64 are cut in that order, so a block is
+// complete (and reduced) after 64 consecutive outputs and at most one block
+// is pending at a time.
 template <class Dm, int NACC>
 struct PlaneBlocks {
-    static constexpr int NB = (NACC + 63) / 64;
-    int pos[NB * 64];
-    int last[NB];
+    int pos[NACC];
+    int xof[NACC];
 };
 template <class Dm, int NACC>
 __host__ __device__ constexpr PlaneBlocks<Dm, NACC> make_plane_blocks() {
     PlaneBlocks<Dm, NACC> r{};
     const KetDfs<Dm::LCD> kd = make_ket_dfs<Dm::LC, Dm::LCD>();
-    for (int b = 0; b < PlaneBlocks<Dm, NACC>::NB; ++b) r.last[b] = -1;
     for (int x = 0; x < NACC; ++x) {
         r.pos[x] = kd.rank[Dm::F0 + x / Dm::NEA] * Dm::NEA + x % Dm::NEA;
-        if (r.pos[x] > r.last[x / 64]) r.last[x / 64] = r.pos[x];
+        r.xof[r.pos[x]] = x;
     }
     return r;
 }
 template <class Dm, int NACC>
 inline constexpr PlaneBlocks<Dm, NACC> kPlaneBlocks = make_plane_blocks<Dm, NACC>();
+template <class Dm, int NACC>
+__constant__ PlaneBlocks<Dm, NACC> kPlaneBlocksDev = make_plane_blocks<Dm, NACC>();
+
+template <class Dm>
+inline constexpr int kPlaneBlockSize = 32;
 
 template <class Dm, int MODE, typename Real>
 __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
@@ -63,7 +68,15 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
                                               const double *__restrict__ D, int N,
                                               double *__restrict__ out0, double *__restrict__ out1) {
     constexpr int NACC = Dm::NFA * Dm::NEA;
-    constexpr int NP = ((NACC + 63) / 64) * 64, NPER = NP / 64;
+    // reduction block: 64 outputs, or 32 where the recursion itself nearly
+    // fills the registers (at most one block of outputs is pending)
+    constexpr int BS = kPlaneBlockSize<Dm>;
+    constexpr int NP = ((NACC + BS - 1) / BS) * BS, NPER = NP / BS;
+    // the recursion may run with the ket pair on the e side (fewer live
+    // values); intermediates are then numbered in that orientation and put
+    // back in the class's own order when stored to LDS
+    constexpr bool SW = VrrOrient<Dm>::swap;
+    using Dr = std::conditional_t<SW, ClassDims<Dm::LC, Dm::LD, Dm::LA, Dm::LB>, Dm>;
     extern __shared__ double lds[];
     double *H = lds;
     double *hc = lds + A.nH;
@@ -79,7 +92,9 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
         }
         const PairInfo bra = pairs[bra_off + i];
         const PairInfo ket = pairs[(MODE == kModeSchwarz ? bra_off : ket_off) + j];
-        const Real AC[3] = {Real(bra.Ax - ket.Ax), Real(bra.Ay - ket.Ay), Real(bra.Az - ket.Az)};
+        // anchor difference of the recursion's e-side and f-side pairs
+        const Real sg = SW ? Real(-1) : Real(1);
+        const Real AC[3] = {sg * Real(bra.Ax - ket.Ax), sg * Real(bra.Ay - ket.Ay), sg * Real(bra.Az - ket.Az)};
         Real part[NPER];
         static_for<0, NPER>([&](auto I) { part[I] = Real(0); });
         const int nprim = bra.npp * ket.npp;
@@ -96,29 +111,40 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
             // over the wave (lane l keeps entry 64 b + l) as soon as its last
             // entry is final, so finished outputs do not stay live through
             // the rest of the recursion
-            Real vb[NPER][64];
+            Real vb[NPER][BS];
             static_for<NACC, NP>([&](auto X) {
                 constexpr int x = decltype(X)::value;
-                vb[x / 64][x % 64] = Real(0);
+                vb[x / BS][x % BS] = Real(0);
             });
-            prim_quartet<Dm, Real>(P, Q, AC, bt, [&](auto X, Real val) {
-                constexpr int x = decltype(X)::value;
-                constexpr int b = x / 64;
-                vb[b][x % 64] = val;
-                if constexpr (kPlaneBlocks<Dm, NACC>.last[b] == kPlaneBlocks<Dm, NACC>.pos[x]) {
-                    rs_step<64, 64, 32>(vb[b], lane);
-                    rs_step<64, 32, 16>(vb[b], lane);
-                    rs_step<64, 16, 8>(vb[b], lane);
-                    rs_step<64, 8, 4>(vb[b], lane);
-                    rs_step<64, 4, 2>(vb[b], lane);
-                    rs_step<64, 2, 1>(vb[b], lane);
+            auto emit = [&](auto X, Real val) {
+                constexpr int ps = kPlaneBlocks<Dr, NACC>.pos[decltype(X)::value];
+                constexpr int b = ps / BS;
+                vb[b][ps % BS] = val;
+                if constexpr (ps % BS == BS - 1 || ps == NACC - 1) {
+                    if constexpr (BS == 64) rs_step<64, 64, 32>(vb[b], lane);
+                    rs_step<BS, 32, 16>(vb[b], lane);
+                    rs_step<BS, 16, 8>(vb[b], lane);
+                    rs_step<BS, 8, 4>(vb[b], lane);
+                    rs_step<BS, 4, 2>(vb[b], lane);
+                    rs_step<BS, 2, 1>(vb[b], lane);
+                    // blocks of 32: lanes l and l ^ 32 hold halves of entry l % 32
+                    if constexpr (BS == 32) vb[b][0] += __shfl_xor(vb[b][0], 32, 64);
                     part[b] += vb[b][0];
                 }
-            });
+            };
+            if constexpr (SW)
+                prim_quartet<Dr, Real>(Q, P, AC, bt, emit);
+            else
+                prim_quartet<Dr, Real>(P, Q, AC, bt, emit);
         }
         static_for<0, NPER>([&](auto I) {
-            const int idx = 64 * decltype(I)::value + lane;
-            if (idx < NACC) H[idx] = (double)part[I];
+            const int ps = BS * decltype(I)::value + lane;
+            if (lane < BS && ps < NACC) {
+                const int x = kPlaneBlocksDev<Dr, NACC>.xof[ps];
+                // swapped: x = (e - E0) NFA + (f - F0) holds [e0|f0]
+                const int h = SW ? (x % Dm::NFA) * Dm::NEA + x / Dm::NFA : x;
+                H[h] = (double)part[I];
+            }
         });
         __syncthreads();
         coop_finish<MODE>(A, H, hc, lane, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);

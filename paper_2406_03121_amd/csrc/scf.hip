@@ -61,6 +61,7 @@ struct mess_scf {
     double *partial = nullptr;                           // reduction partials
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
     double *Vx = nullptr;                                // LDA exchange potential
+    int *d_hs = nullptr;                                 // DIIS history slot list, kMaxDiis
     double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
     double last_dmax = 0.0;  // max |dD| and screening threshold of the last incremental build
     double last_tau = 0.0;
@@ -485,6 +486,7 @@ static void free_scf(mess_scf *st) {
                       st->P2, st->Fh, st->Eh, st->Bm, st->partial, st->Dprev, st->dD, st->Gja, st->Gka, st->Vx})
         hipFree(p);
     hipFree(st->sc);
+    hipFree(st->d_hs);
     delete st;
 }
 
@@ -550,6 +552,7 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * nn * nd));
     MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * nn * nd));
     MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kMaxDiis * kMaxDiis));
+    MESS_HIP(hipMalloc(&st->d_hs, sizeof(int) * kMaxDiis));
     if (st->opts.prec == MESS_FP32)
         for (double **p : {&st->Dprev, &st->dD, &st->Gja, &st->Gka})
             MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
@@ -694,12 +697,9 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         st->hist.push_back(slot);
         if ((int)st->hist.size() > nd) st->hist.erase(st->hist.begin());
         st->next_slot = (slot + 1) % nd;
-        int *dslots = reinterpret_cast<int *>(st->P2);  // scratch for the slot list
-        (void)dslots;
         int hs[kMaxDiis];
         for (size_t i = 0; i < st->hist.size(); ++i) hs[i] = st->hist[i];
-        int *d_hs = nullptr;
-        MESS_HIP(hipMalloc(&d_hs, sizeof(int) * kMaxDiis));
+        int *d_hs = st->d_hs;
         int rc = MESS_OK;
         if (hipMemcpyAsync(d_hs, hs, sizeof(int) * st->hist.size(), hipMemcpyHostToDevice, s) != hipSuccess)
             rc = MESS_E_DEVICE;
@@ -714,7 +714,6 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
             }
             if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) rc = MESS_E_DEVICE;
         }
-        hipFree(d_hs);
         if (rc != MESS_OK) {
             set_error("mess_scf_step: DIIS kernels failed");
             return rc;

@@ -28,9 +28,8 @@ def zeros(*shape):
 
 
 def random_density(n, seed=0):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    A = rng.normal(size=(n, n))
-    return (A + A.T) / 2
+    from mess_inputs.generators import symmetric_density
+    return symmetric_density(n, seed)
 
 
 def announce(msg):

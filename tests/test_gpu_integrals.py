@@ -6,6 +6,7 @@ built with long double), so the bound measures the GPU's own rounding.  J/K
 are sums of up to N^2 ERIs times density elements; the bound used is
 1e-11 * max(1, |X|) for unit-scale random densities, against the FP64 oracle.
 """
+import functools
 import os
 import sys
 
@@ -27,7 +28,17 @@ CASES = {
     "mol3to20/1000-small": lambda: G.batched_molecule(1007),
     # two waters far apart: most primitive pairs between them are screened
     "water2_spd_far/3": lambda: G.water_cluster(3, n_waters=2, box=14.0),
+    # 83 functions; bras with more than 512 quartets, so the segmented
+    # J/K kernels run several segments per bra
+    "mol3to20/1001": lambda: G.batched_molecule(1001),
 }
+
+
+@functools.lru_cache(maxsize=8)
+def _oracle_jk(case, tau, seed):
+    mol = CASES[case]()
+    J, K, _ = core.jk_unique(mol, G.symmetric_density(mol.n_bf, seed), tau)
+    return J, K
 
 
 def _rel_err(a, b):
@@ -82,14 +93,13 @@ def test_jk(case, tau, mode):
     announce(f"jk {mode} {case} tau={tau} nbf={mol.n_bf}")
     B = mess.basis_from_molecule(mol)
     N = B.nbf
-    D = random_density(N, seed=11)
     J, K = zeros(N, N), zeros(N, N)
     m = mess.MESS_JK_DIRECT if mode == "direct" else mess.MESS_JK_STORED
+    if mode == "stored":  # the second call streams the cached blocks
+        mess.mess_jk(B, dev(random_density(N, seed=12)), J, K, mode=m, schwarz_tol=tau)
+    D = random_density(N, seed=11)
     mess.mess_jk(B, dev(D), J, K, mode=m, schwarz_tol=tau)
-    if mode == "stored":  # second call streams the cached blocks
-        D = random_density(N, seed=12)
-        mess.mess_jk(B, dev(D), J, K, mode=m, schwarz_tol=tau)
-    Jo, Ko, _ = core.jk_unique(mol, D, tau)
+    Jo, Ko = _oracle_jk(case, tau, 11)
     assert _rel_err(host(J), Jo) < 1e-11
     assert _rel_err(host(K), Ko) < 1e-11
     if tau == 0.0 and N <= 60:

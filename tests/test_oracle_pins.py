@@ -80,6 +80,47 @@ def test_unit_self_overlap_and_overlap_by_quadrature():
             assert abs(Q.overlap(f[i], f[i]) - 1.0) < 1e-13
 
 
+def _contracted_shells(seed=11):
+    """Shells of 3-6 primitives with raw contraction coefficients drawn as
+    the workloads draw them (exponents log-uniform in [0.05, 5000],
+    coefficients uniform in (0, 1]), one s, p and d shell per atom."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xyz = rng.uniform(0, 2.0, size=(2, 3))
+    shells = []
+    for a in range(2):
+        for l in (0, 1, 2):
+            k = int(rng.integers(3, 7))
+            shells.append((a, l, np.exp(rng.uniform(np.log(0.05), np.log(5000.0), k)),
+                           1.0 - rng.uniform(0.0, 1.0, k)))
+    return G._assemble([8, 1], xyz, shells, "contracted_spd")
+
+
+def test_contraction_weights_from_raw_coefficients():
+    """Reading of the contraction coefficients: each raw coefficient
+    multiplies a primitive normalised to unit self-overlap, and the sum is
+    renormalised.  Built here from the raw (exponent, coefficient) lists with
+    every norm taken by quadrature of the squared function, so a weighting
+    of raw primitives or a wrong primitive norm fails."""
+    mol = _contracted_shells()
+    got = core.coefficients(mol)
+    p0 = 0
+    for s in range(mol.n_shells):
+        l, k = int(mol.shell_l[s]), int(mol.shell_nprim[s])
+        ex, raw = mol.exps[p0:p0 + k], mol.coefs[p0:p0 + k]
+        for c, lmn in enumerate(Q.cart_components(l)):
+            def ov(a, b):
+                return np.prod([Q.overlap_1d(lmn[x], 0.0, a, lmn[x], 0.0, b) for x in range(3)])
+            nprim = np.array([1.0 / math.sqrt(ov(a, a)) for a in ex])
+            w = raw * nprim
+            self_ov = sum(w[i] * w[j] * ov(ex[i], ex[j]) for i in range(k) for j in range(k))
+            want = w / math.sqrt(self_ov)
+            assert np.max(np.abs(got[p0:p0 + k, c] - want) / np.abs(want)) < 1e-13, (s, c)
+            # the raw-primitive weighting differs from the reading by far more
+            wraw = raw / math.sqrt(sum(raw[i] * raw[j] * ov(ex[i], ex[j]) for i in range(k) for j in range(k)))
+            assert np.max(np.abs(wraw - want) / np.abs(want)) > 1e-3
+        p0 += k
+
+
 def test_kinetic_and_nuclear_by_quadrature():
     mol = _tiny_spd()
     S, T, V = core.one_electron(mol)
