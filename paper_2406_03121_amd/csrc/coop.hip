@@ -650,7 +650,6 @@ static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, 
         if (prec == MESS_FP32) PlaneOps<B, K, float>::launch(mode, A, L, total, g, lds, D, out0, out1);  \
         else PlaneOps<B, K, double>::launch(mode, A, L, total, g, lds, D, out0, out1);                   \
     }
-    MESS_PL(5, 5)
     MESS_PL(5, 4)
     MESS_PL(5, 3)
     MESS_PL(5, 2)

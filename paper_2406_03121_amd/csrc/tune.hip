@@ -30,7 +30,7 @@ int g_form[kNumClasses] = {};  // kFormAuto: built-in default
 }  // namespace
 
 bool plane_compiled(int cb, int ck) {
-    return (cb == 5 && ck >= 2) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
+    return (cb == 5 && ck >= 2 && ck <= 4) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
 }
 
 bool rows_compiled(int cb, int ck) {
