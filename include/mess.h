@@ -163,6 +163,24 @@ int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwa
 int mess_jk(const mess_basis *basis, const double *D, double *J, double *K,
             int32_t mode, int32_t prec, double schwarz_tol, mess_stream stream);
 
+/* mess_jk in MESS_JK_DIRECT mode for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results as mess_jk, but the J/K
+ * half matrices live in a fixed device array of the library (2 x 2^19
+ * doubles, 8 MB per device, held until the process ends) instead of the
+ * basis handle's buffer, and the call allocates and frees nothing.
+ *   D, J, K as for mess_jk (J or K may be NULL); prec MESS_FP64 or
+ *   MESS_FP32; schwarz_tol as for mess_jk.
+ * The work lists for (basis, schwarz_tol) must already exist: call mess_jk
+ * once with the same basis and tolerance first (MESS_E_ARG otherwise).
+ * MESS_E_SIZE if the basis has more than 2^19 matrix elements (N > 724,
+ * or a batch whose packed matrices exceed that).  MESS_E_ARG while class
+ * profiling is on.  All calls on one device share the array: calls that
+ * overlap in time on one device (two streams, two threads) race; calls
+ * ordered on one stream do not. */
+int mess_jk_noalloc(const mess_basis *basis, const double *D, double *J, double *K, int32_t prec,
+                    double schwarz_tol, mess_stream stream);
+
 /* LDA exchange (the local density approximation the paper names for its
  * batched DFT example, section 5), as Dirac-Slater exchange on an
  * atom-centred grid:

@@ -5,6 +5,7 @@
 #include "mess_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace mess {
 
@@ -88,6 +89,40 @@ int jk_full(mess_basis *B, const double *D, double *J, double *K, int mode, int 
     return MESS_OK;
 }
 
+// Fixed device workspace of the allocation-free J/K entry point: the two
+// half matrices Gj, Gk of at most kNoAllocMaxPacked doubles each (8 MB in
+// all per device, held until the process ends).  Host code never passes the
+// array's name to a kernel: it uses the per-device address below.
+constexpr int64_t kNoAllocMaxPacked = int64_t(1) << 19;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxPacked];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+static int scratch_address(double **out) {
+    int dev = 0;
+    MESS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("mess_jk_noalloc: device index %d beyond %d", dev, kMaxDevices);
+        return MESS_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("mess_jk_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return MESS_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MESS_OK;
+}
+
 }  // namespace mess
 
 using namespace mess;
@@ -151,6 +186,49 @@ int mess_jk(const mess_basis *basis, const double *D, double *J, double *K, int3
     if (!J && !K) return MESS_OK;
     return jk_full(const_cast<mess_basis *>(basis), D, J, K, mode, prec, schwarz_tol,
                    static_cast<hipStream_t>(stream));
+}
+
+int mess_jk_noalloc(const mess_basis *basis, const double *D, double *J, double *K, int32_t prec,
+                    double schwarz_tol, mess_stream stream) {
+    if (!basis || !D) {
+        set_error("mess_jk_noalloc: NULL basis or density");
+        return MESS_E_ARG;
+    }
+    if (prec != MESS_FP64 && prec != MESS_FP32) {
+        set_error("mess_jk_noalloc: unknown precision %d", prec);
+        return MESS_E_UNSUPPORTED;
+    }
+    auto *B = const_cast<mess_basis *>(basis);
+    if (B->packed > kNoAllocMaxPacked) {
+        set_error("mess_jk_noalloc: %lld matrix elements exceed the fixed workspace of %lld per matrix",
+                  (long long)B->packed, (long long)kNoAllocMaxPacked);
+        return MESS_E_SIZE;
+    }
+    if (prof_on()) {
+        set_error("mess_jk_noalloc: class profiling is on (it records events); turn it off first");
+        return MESS_E_ARG;
+    }
+    const double tau = schwarz_tol > 0.0 ? schwarz_tol : 0.0;
+    auto it = B->lists.find(tau);
+    bool ready = it != B->lists.end();
+    if (ready)
+        for (const ClassList &cl : it->second->classes)
+            if (cl.total > 0 && !coop_program_cached(cl.cb, cl.ck)) ready = false;
+    if (!ready) {
+        set_error("mess_jk_noalloc: the work lists for schwarz_tol %g are not built yet; call mess_jk once "
+                  "with this basis, precision and tolerance first", schwarz_tol);
+        return MESS_E_ARG;
+    }
+    if (!J && !K) return MESS_OK;
+    double *ws = nullptr;
+    MESS_TRY(scratch_address(&ws));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *Gj = J ? ws : nullptr;
+    double *Gk = K ? ws + kNoAllocMaxPacked : nullptr;
+    MESS_TRY(jk_direct_half(B, D, Gj, Gk, prec, tau, s));
+    if (J) MESS_TRY(symmetrise_async(B, Gj, J, s));
+    if (K) MESS_TRY(symmetrise_async(B, Gk, K, s));
+    return MESS_OK;
 }
 
 }  // extern "C"

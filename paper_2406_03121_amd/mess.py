@@ -33,7 +33,7 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune",
+    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc",
 ]
 MESS_MLP_NPARAM = 115328
 
@@ -69,6 +69,7 @@ def lib():
         L.mess_one_electron.argtypes = [vp, vp, vp, vp, vp]
         L.mess_eri.argtypes = [vp, i32, i32, f64, vp, sz, vp]
         L.mess_jk.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp]
+        L.mess_jk_noalloc.argtypes = [vp, vp, vp, vp, i32, f64, vp]
         if hasattr(L, "mess_scf_create"):
             L.mess_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, ctypes.POINTER(vp)]
             L.mess_scf_step.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), ctypes.POINTER(f64),
@@ -237,6 +238,13 @@ def mess_jk(basis: Basis, D, J=None, K=None, mode=MESS_JK_DIRECT, prec=MESS_FP64
             stream=None):
     _check(lib().mess_jk(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(mode), int(prec), float(schwarz_tol),
                          _stream(stream)), "mess_jk")
+
+
+def mess_jk_noalloc(basis: Basis, D, J=None, K=None, prec=MESS_FP64, schwarz_tol=0.0, stream=None):
+    """Direct J/K with no device allocation (fixed library workspace); the
+    work lists must exist (an earlier mess_jk on this basis and tolerance)."""
+    _check(lib().mess_jk_noalloc(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(prec), float(schwarz_tol),
+                                 _stream(stream)), "mess_jk_noalloc")
 
 
 def mess_lda_x(basis: Basis, D, Vx=None, rho=None, stream=None):
