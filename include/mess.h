@@ -59,7 +59,8 @@ enum {
 
 enum { MESS_FP64 = 0, MESS_FP32 = 1 };                       /* arithmetic of the ERI path */
 enum { MESS_ERI_DENSE = 0, MESS_ERI_BLOCKS = 1 };            /* mess_eri output layout */
-enum { MESS_JK_DIRECT = 0, MESS_JK_STORED = 1 };             /* mess_jk source of integrals */
+enum { MESS_JK_DIRECT = 0, MESS_JK_STORED = 1,               /* mess_jk source of integrals */
+       MESS_JK_DETERMINISTIC = 2 };                          /* stored blocks, exact accumulation */
 enum { MESS_XC_HF = 0, MESS_XC_LDA_X = 1 };                  /* exchange in the Fock matrix */
 
 typedef struct mess_scf_opts {
@@ -77,7 +78,9 @@ typedef struct mess_scf_opts {
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
     int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X (F = H + J + V_x,
                             E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; FP64 only; see mess_lda_x) */
-    int32_t reserved;
+    int32_t deterministic; /* nonzero: every Fock build runs as mess_jk(MESS_JK_DETERMINISTIC)
+                              (overrides jk_mode), so a rerun reproduces every energy and
+                              density bit for bit */
 } mess_scf_opts;
 
 /* Build a basis on a molecule (section 3, eq. 1: each atomic orbital sits
@@ -141,25 +144,48 @@ int mess_basis_info(const mess_basis *basis, int32_t *nbf, int32_t *n_occ, doubl
  * device N x N buffer or NULL to skip. */
 int mess_one_electron(const mess_basis *basis, double *S, double *T, double *V, mess_stream stream);
 
-/* Electron-repulsion integrals (mu nu|lambda sigma) over the basis.
+/* Electron-repulsion integrals (mu nu|lambda sigma) over the basis: the
+ * four-centre Coulomb integrals of pairs of basis functions (section 3,
+ * eq. 1 basis functions; the closed-form Gaussian integrals the section
+ * lists with the overlap of eq. 3).
  *   layout MESS_ERI_DENSE: out is a device N^4 FP64 tensor (i slowest);
  *     every element is written (screened quartets are zero).
- *     out_bytes must be >= 8 N^4.
- *   prec: MESS_FP64 (FP32 accepted: integrals computed in FP32, stored
- *     widened to FP64).
+ *     out_bytes must be >= 8 N^4.  Single molecules only.  prec MESS_FP32
+ *     computes in FP32 and stores widened to FP64.
+ *   layout MESS_ERI_BLOCKS: the unique shell quartets (ab|cd), pair (ab)
+ *     >= pair (cd), that pass the Schwarz test, class by class in the order
+ *     cls = cb (cb + 1) / 2 + ck (pair classes ss ps pp ds dp dd = 0..5);
+ *     within class cls, element k = ((a NB + b) NC + c) ND + d of its
+ *     quartet t (a, b, c, d Cartesian components of the four shells, NA..ND
+ *     their counts) at out[off_cls + k nq_cls + t], off_cls the sum of
+ *     NA NB NC ND nq over the earlier classes.  Elements are FP64, or FP32
+ *     with prec MESS_FP32.  mess_eri_quartets gives nq_cls and the shells
+ *     of every quartet.  Works for batches too (quartets of one molecule).
  *   schwarz_tol: skip quartet iff Q_ab Q_cd < tol (<= 0 keeps all).
  * Errors: MESS_E_SIZE, MESS_E_UNSUPPORTED (layout), MESS_E_ARG. */
 int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwarz_tol,
              void *out, size_t out_bytes, mess_stream stream);
 
+/* Unique shell quartets of the MESS_ERI_BLOCKS layout (host outputs, either
+ * may be NULL): counts[21] quartets per class; shells[sum counts][4] the
+ * shell indices (a, b, c, d) of every quartet in output order (shells
+ * numbered as given at create, across a batch). */
+int mess_eri_quartets(const mess_basis *basis, double schwarz_tol, int64_t *counts, int32_t *shells);
+
 /* Coulomb and exchange matrices from a symmetric density D (device N x N):
- *   J_ij = sum_kl (ij|kl) D_kl,  K_ij = sum_kl (ik|jl) D_kl.
+ *   J_ij = sum_kl (ij|kl) D_kl,  K_ij = sum_kl (ik|jl) D_kl,
+ * the two-electron parts of the Fock operator of the Roothaan equation
+ * (section 3, eq. 2; K is the exact (Hartree-Fock) exchange the paper's
+ * examples select as the exchange functional, section 5.1).
  * J or K may be NULL to skip.  mode MESS_JK_DIRECT recomputes integrals
  * over unique shell quartets (8-fold permutational symmetry) with Schwarz
  * screening and digests them in registers; MESS_JK_STORED computes the
  * unique blocks once per (basis, prec, tol) and streams them from device
- * memory on later calls.  prec selects FP64 or FP32 integral arithmetic
- * (J, K are always returned in FP64). */
+ * memory on later calls; MESS_JK_DETERMINISTIC digests the same stored
+ * blocks with exact 128-bit fixed-point accumulation (resolution 2^-80),
+ * so repeated calls return bitwise equal J and K (synchronous;
+ * MESS_E_NUMERIC if a contribution exceeds 2^46).  prec selects FP64 or
+ * FP32 integral arithmetic (J, K are always returned in FP64). */
 int mess_jk(const mess_basis *basis, const double *D, double *J, double *K,
             int32_t mode, int32_t prec, double schwarz_tol, mess_stream stream);
 

@@ -402,6 +402,7 @@ static void free_basis(mess_basis *B) {
     hipFree(B->d_pp);
     hipFree(B->d_ppf);
     hipFree(B->scratch_jk);
+    hipFree(B->det_acc);
     hipFree(B->d_mol_moff);
     hipFree(B->d_mol_nbf);
     delete B;

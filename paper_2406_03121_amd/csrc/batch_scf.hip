@@ -779,6 +779,11 @@ int mess_batch_scf_create(const mess_basis *basis, const mess_scf_opts *opts, co
                       m, basis->mol_nelec[m]);
             return MESS_E_UNSUPPORTED;
         }
+    if (opts->deterministic) {
+        set_error("mess_batch_scf_create: the deterministic mode reads a host flag after every build; "
+                  "run batches of it through mess_jk(MESS_JK_DETERMINISTIC) or single-molecule SCFs");
+        return MESS_E_UNSUPPORTED;
+    }
     if (opts->jk_mode != MESS_JK_DIRECT && opts->jk_mode != MESS_JK_STORED) {
         set_error("mess_batch_scf_create: unknown J/K mode %d", opts->jk_mode);
         return MESS_E_UNSUPPORTED;

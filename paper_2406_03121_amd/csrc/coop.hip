@@ -424,29 +424,36 @@ std::map<std::pair<int, int>, std::unique_ptr<CoopProgram>> g_programs;
 // the e_j/2(p+q) term) and one add per contracted intermediate; per shell
 // quartet each horizontal step (2) and the J/K digestion (six families of
 // one FMA per integral: 12 per integral).
-void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk) {
-    std::lock_guard<std::mutex> lk(g_flop_mutex);
-    auto key = std::make_pair(cb, ck);
-    auto it = g_flops.find(key);
-    if (it == g_flops.end()) {
-        CoopTables T;
-        double fp = 0.0, fq = 0.0;
-        std::unique_ptr<CoopProgram> P;
-        try {
-            P = build_tables(cb, ck, T);
-        } catch (...) {
-            P.reset();
-        }
-        if (P) {
-            fp = 80.0 + 4.0 * P->L + P->nacc;
-            for (const int4 &op : T.vops) {
-                const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
-                fp += 3.0 + (k3 ? 4.0 : 0.0) + (k5 ? 2.0 : 0.0);
-            }
-            fq = 2.0 * (double)T.hops.size() + 12.0 * P->nout;
-        }
-        it = g_flops.emplace(key, std::make_pair(fp, fq)).first;
+// The vertical steps are counted in the orientation the class's kernel
+// runs: the primitive-lane kernels may put the ket pair on the e side
+// (swap_vrr), every other form keeps the bra there.
+static std::pair<double, double> count_flops(int cb, int ck, bool swapped) {
+    CoopTables T, Tv;
+    std::unique_ptr<CoopProgram> P, Pv;
+    try {
+        P = build_tables(cb, ck, T);
+        if (swapped) Pv = build_tables(ck, cb, Tv);
+    } catch (...) {
+        P.reset();
     }
+    if (!P || (swapped && !Pv)) return {0.0, 0.0};
+    const std::vector<int4> &vops = swapped ? Tv.vops : T.vops;
+    double fp = 80.0 + 4.0 * P->L + P->nacc;
+    for (const int4 &op : vops) {
+        const int k3 = (op.w >> 25) & 7, k5 = (op.w >> 28) & 7;
+        fp += 3.0 + (k3 ? 4.0 : 0.0) + (k5 ? 2.0 : 0.0);
+    }
+    const double fq = 2.0 * (double)T.hops.size() + 12.0 * P->nout;
+    return {fp, fq};
+}
+
+void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk) {
+    const int la = pair_class_la(cb), lb = pair_class_lb(cb), lc = pair_class_la(ck), ld = pair_class_lb(ck);
+    const bool swapped = coop_class(cb, ck) && class_form(cb, ck) == kFormPlane && swap_vrr(la, lb, lc, ld);
+    std::lock_guard<std::mutex> lk(g_flop_mutex);
+    auto key = std::make_pair(cb * 8 + (swapped ? 1 : 0), ck);
+    auto it = g_flops.find(key);
+    if (it == g_flops.end()) it = g_flops.emplace(key, count_flops(cb, ck, swapped)).first;
     *per_prim = it->second.first;
     *per_quartet_jk = it->second.second;
 }

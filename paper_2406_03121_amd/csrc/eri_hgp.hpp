@@ -204,7 +204,9 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // the live set of one primitive quartet (e.g. (dd|ds): 262 -> 154 values,
 // (dd|dp): 437 -> 343) with about the same number of steps.  Chosen per
 // class from a count of live values and steps of both orders; classes with
-// a ds bra on an s or p ket, and the small ones, keep the bra side.
+// a ds bra on an s or p ket, and the small ones, keep the bra side.  Used by
+// the primitive-lane kernels, whose registers hold one primitive quartet's
+// recursion.
 __host__ __device__ constexpr bool swap_vrr(int LA, int LB, int LC, int LD) {
     return (LA + LB) > (LC + LD) && (LA + LB + LC + LD) >= 3 && !(LA == 2 && LB == 0);
 }
@@ -409,15 +411,16 @@ template <class Dm, typename Real>
 __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo &ket,
                                             const PrimPairT<Real> *__restrict__ pp, const BoysTabs &bt,
                                             Real (&out)[Dm::NOUT]) {
-    // acc[f - F0][e - E0] = contracted [e0|f0], e on the bra side
+    // acc[f - F0][e - E0] = contracted [e0|f0], e on the bra side.  The
+    // per-lane kernels keep the bra on the e side in every class: their
+    // registers go mostly to the contracted intermediates, and the swapped
+    // order has more steps where it has fewer live values (measured slower
+    // for (dd|ps), (dp|ps)).
     Real acc[Dm::NFA][Dm::NEA];
     static_for<0, Dm::NFA>([&](auto F) {
         static_for<0, Dm::NEA>([&](auto E) { acc[decltype(F)::value][decltype(E)::value] = Real(0); });
     });
-    constexpr bool SW = VrrOrient<Dm>::swap;
-    using Dv = ClassDims<Dm::LC, Dm::LD, Dm::LA, Dm::LB>;  // swapped orientation
     const Real AC[3] = {Real(bra.Ax - ket.Ax), Real(bra.Ay - ket.Ay), Real(bra.Az - ket.Az)};
-    const Real CA[3] = {-AC[0], -AC[1], -AC[2]};
     // Lanes of a wave take consecutive quartets of one bra row: the ket's
     // primitive pairs (different for every lane) are read once each, the
     // bra's (the same for the wave) in the inner loop.  When every active
@@ -427,30 +430,18 @@ __device__ __forceinline__ void eri_quartet(const PairInfo &bra, const PairInfo 
         constexpr int x = decltype(X)::value;
         acc[x / Dm::NEA][x % Dm::NEA] += v;
     };
-    // swapped recursion: x indexes (f' - F0') NEA' + (e' - E0') with e' on the
-    // ket side, i.e. [f'0|e'0] = [e0|f0] for e = f', f = e'
-    auto addT = [&](auto X, Real v) {
-        constexpr int x = decltype(X)::value;
-        acc[x % Dv::NEA][x / Dv::NEA] += v;
-    };
-    auto one = [&](const PrimPairT<Real> &Pb, const PrimPairT<Real> &Qk) {
-        if constexpr (SW)
-            prim_quartet<Dv, Real>(Qk, Pb, CA, bt, addT);
-        else
-            prim_quartet<Dm, Real>(Pb, Qk, AC, bt, add);
-    };
     const int pbu = __builtin_amdgcn_readfirstlane(bra.pp0);
     if (__all(bra.pp0 == pbu)) {
         const int nbu = __builtin_amdgcn_readfirstlane(bra.npp);
         const PrimPairT<Real> *__restrict__ pb = pp + pbu;
         for (int ik = 0; ik < ket.npp; ++ik) {
             const PrimPairT<Real> Q = pp[ket.pp0 + ik];
-            for (int ib = 0; ib < nbu; ++ib) one(pb[ib], Q);
+            for (int ib = 0; ib < nbu; ++ib) prim_quartet<Dm, Real>(pb[ib], Q, AC, bt, add);
         }
     } else {
         for (int ik = 0; ik < ket.npp; ++ik) {
             const PrimPairT<Real> Q = pp[ket.pp0 + ik];
-            for (int ib = 0; ib < bra.npp; ++ib) one(pp[bra.pp0 + ib], Q);
+            for (int ib = 0; ib < bra.npp; ++ib) prim_quartet<Dm, Real>(pp[bra.pp0 + ib], Q, AC, bt, add);
         }
     }
     // bra HRR for every ket index f

@@ -12,6 +12,8 @@ namespace mess {
 int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out);
 int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, ClassLaunch &L);
 int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+int jk_det(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+int eri_blocks(mess_basis *B, int prec, double tau, void *out, size_t out_bytes, hipStream_t s);
 
 __global__ void k_fill_zero(double *__restrict__ p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -82,6 +84,8 @@ int jk_full(mess_basis *B, const double *D, double *J, double *K, int mode, int 
     double *Gk = K ? static_cast<double *>(B->scratch_jk) + B->packed : nullptr;
     if (mode == MESS_JK_DIRECT)
         MESS_TRY(jk_direct_half(B, D, Gj, Gk, prec, tau, s));
+    else if (mode == MESS_JK_DETERMINISTIC)
+        MESS_TRY(jk_det(B, D, Gj, Gk, prec, tau, s));
     else
         MESS_TRY(jk_stored(B, D, Gj, Gk, prec, tau, s));
     if (J) MESS_TRY(symmetrise_async(B, Gj, J, s));
@@ -139,11 +143,13 @@ int mess_eri(const mess_basis *basis, int32_t layout, int32_t prec, double schwa
         set_error("mess_eri: unknown precision %d", prec);
         return MESS_E_UNSUPPORTED;
     }
-    if (layout != MESS_ERI_DENSE) {
-        set_error("mess_eri: layout %d is not supported by this entry point", layout);
+    if (layout != MESS_ERI_DENSE && layout != MESS_ERI_BLOCKS) {
+        set_error("mess_eri: unknown layout %d", layout);
         return MESS_E_UNSUPPORTED;
     }
     auto *B = const_cast<mess_basis *>(basis);
+    if (layout == MESS_ERI_BLOCKS)
+        return eri_blocks(B, prec, schwarz_tol, out, out_bytes, static_cast<hipStream_t>(stream));
     if (B->n_mol != 1) {
         set_error("mess_eri: the dense tensor is built for a single molecule, not a batch of %d", B->n_mol);
         return MESS_E_UNSUPPORTED;
@@ -175,7 +181,7 @@ int mess_jk(const mess_basis *basis, const double *D, double *J, double *K, int3
         set_error("mess_jk: NULL basis or density");
         return MESS_E_ARG;
     }
-    if (mode != MESS_JK_DIRECT && mode != MESS_JK_STORED) {
+    if (mode != MESS_JK_DIRECT && mode != MESS_JK_STORED && mode != MESS_JK_DETERMINISTIC) {
         set_error("mess_jk: unknown mode %d", mode);
         return MESS_E_UNSUPPORTED;
     }

@@ -259,6 +259,7 @@ struct mess_basis {
     std::map<double, mess::WorkLists *> lists;  // keyed by tau
     std::map<std::pair<int, double>, mess::StoredEri *> stored;  // (prec, tau)
     void *scratch_jk = nullptr;   // [2 * packed] doubles: Gj, Gk
+    void *det_acc = nullptr;      // deterministic J/K: 128-bit accumulators (built on first use)
     void *xc = nullptr;           // LDA grid and basis values (built on first use)
     void *guess = nullptr;        // learned-guess pair tables (built on first use)
 };

@@ -24,6 +24,7 @@ namespace mess {
 
 int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
 int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
+int jk_det(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
 int zero_async(double *p, int64_t n, hipStream_t s);
 int lda_x_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev);
 
@@ -591,6 +592,20 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     return MESS_OK;
 }
 
+static bool scf_deterministic(const mess_scf *st) {
+    return st->opts.deterministic != 0 || st->opts.jk_mode == MESS_JK_DETERMINISTIC;
+}
+
+// J/K half matrices of one Fock build in the state's mode: deterministic
+// (stored blocks, exact accumulation, always at the options' threshold),
+// direct or stored.
+static int scf_jk(mess_scf *st, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s) {
+    mess_basis *B = st->basis;
+    if (scf_deterministic(st)) return jk_det(B, D, Gj, Gk, prec, st->opts.schwarz_tol, s);
+    if (st->opts.jk_mode == MESS_JK_DIRECT) return jk_direct_half(B, D, Gj, Gk, prec, tau, s);
+    return jk_stored(B, D, Gj, Gk, prec, tau, s);
+}
+
 static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *resid, int32_t *converged,
                          hipStream_t s) {
     mess_basis *B = st->basis;
@@ -608,10 +623,7 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         const bool full = (st->iter % 8) == 0;
         const int dprec = st->last_de < 1e-3 ? MESS_FP32 : MESS_FP64;
         if (full) {
-            if (st->opts.jk_mode == MESS_JK_DIRECT)
-                MESS_TRY(jk_direct_half(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
-            else
-                MESS_TRY(jk_stored(B, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
+            MESS_TRY(scf_jk(st, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
         } else {
             MESS_TRY(axpby(s, nn, 1.0, st->D, -1.0, st->Dprev, st->dD));
             // Direct builds screen the change by its size as well: a quartet
@@ -621,7 +633,7 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
             // such quartets.  Stored blocks keep the list they were built for.
             double tau = st->opts.schwarz_tol;
             bool none = false;
-            if (st->opts.jk_mode == MESS_JK_DIRECT && tau > 0.0) {
+            if (st->opts.jk_mode == MESS_JK_DIRECT && !scf_deterministic(st) && tau > 0.0) {
                 hipLaunchKernelGGL(k_maxabs_to, dim3(1), dim3(1024), 0, s, nn, st->dD, &st->sc->dmax);
                 MESS_LAUNCH_CHECK();
                 double dmax = 0.0;
@@ -637,10 +649,7 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
                 st->last_tau = none ? 0.0 : tau;
             }
             if (!none) {
-                if (st->opts.jk_mode == MESS_JK_DIRECT)
-                    MESS_TRY(jk_direct_half(B, st->dD, st->Gj, st->Gk, dprec, tau, s));
-                else
-                    MESS_TRY(jk_stored(B, st->dD, st->Gj, st->Gk, dprec, tau, s));
+                MESS_TRY(scf_jk(st, st->dD, st->Gj, st->Gk, dprec, tau, s));
                 MESS_TRY(axpby(s, nn, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
                 MESS_TRY(axpby(s, nn, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
             }
@@ -651,10 +660,7 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     } else {
         // LDA exchange needs no K
         double *Gk = st->Vx ? nullptr : st->Gk;
-        if (st->opts.jk_mode == MESS_JK_DIRECT)
-            MESS_TRY(jk_direct_half(B, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
-        else
-            MESS_TRY(jk_stored(B, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
+        MESS_TRY(scf_jk(st, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
     }
     const double *ex = nullptr;
     if (st->Vx) MESS_TRY(lda_x_async(B, st->D, st->Vx, s, &ex));
@@ -749,7 +755,8 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
         set_error("mess_scf_create: %d electrons; only closed-shell (even) systems are supported", basis->nelec);
         return MESS_E_UNSUPPORTED;
     }
-    if (opts->jk_mode != MESS_JK_DIRECT && opts->jk_mode != MESS_JK_STORED) {
+    if (opts->jk_mode != MESS_JK_DIRECT && opts->jk_mode != MESS_JK_STORED &&
+        opts->jk_mode != MESS_JK_DETERMINISTIC) {
         set_error("mess_scf_create: unknown J/K mode %d", opts->jk_mode);
         return MESS_E_UNSUPPORTED;
     }

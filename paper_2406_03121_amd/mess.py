@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmess_hip.so")
 MESS_OK, MESS_E_ARG, MESS_E_UNSUPPORTED, MESS_E_NOMEM, MESS_E_DEVICE, MESS_E_NUMERIC, MESS_E_SIZE = range(7)
 MESS_FP64, MESS_FP32 = 0, 1
 MESS_ERI_DENSE, MESS_ERI_BLOCKS = 0, 1
-MESS_JK_DIRECT, MESS_JK_STORED = 0, 1
+MESS_JK_DIRECT, MESS_JK_STORED, MESS_JK_DETERMINISTIC = 0, 1, 2
 MESS_XC_HF, MESS_XC_LDA_X = 0, 1
 MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP = range(5)
 
@@ -33,7 +33,7 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc",
+    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc", "mess_eri_quartets",
 ]
 MESS_MLP_NPARAM = 115328
 
@@ -48,7 +48,7 @@ class ScfOpts(ctypes.Structure):
     _fields_ = [("schwarz_tol", ctypes.c_double), ("conv_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("jk_mode", ctypes.c_int32),
-                ("xc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("xc", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,6 +70,7 @@ def lib():
         L.mess_eri.argtypes = [vp, i32, i32, f64, vp, sz, vp]
         L.mess_jk.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp]
         L.mess_jk_noalloc.argtypes = [vp, vp, vp, vp, i32, f64, vp]
+        L.mess_eri_quartets.argtypes = [vp, f64, vp, vp]
         if hasattr(L, "mess_scf_create"):
             L.mess_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, ctypes.POINTER(vp)]
             L.mess_scf_step.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), ctypes.POINTER(f64),
@@ -234,6 +235,17 @@ def mess_eri(basis: Basis, out, layout=MESS_ERI_DENSE, prec=MESS_FP64, schwarz_t
                           _stream(stream)), "mess_eri")
 
 
+def mess_eri_quartets(basis: Basis, schwarz_tol=0.0):
+    """(counts[21], shells[sum counts, 4]) of the MESS_ERI_BLOCKS layout."""
+    counts = np.zeros(21, np.int64)
+    _check(lib().mess_eri_quartets(basis.handle, float(schwarz_tol), counts.ctypes.data_as(ctypes.c_void_p), None),
+           "mess_eri_quartets")
+    shells = np.zeros((max(1, int(counts.sum())), 4), np.int32)
+    _check(lib().mess_eri_quartets(basis.handle, float(schwarz_tol), None, shells.ctypes.data_as(ctypes.c_void_p)),
+           "mess_eri_quartets")
+    return counts, shells[:int(counts.sum())]
+
+
 def mess_jk(basis: Basis, D, J=None, K=None, mode=MESS_JK_DIRECT, prec=MESS_FP64, schwarz_tol=0.0,
             stream=None):
     _check(lib().mess_jk(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(mode), int(prec), float(schwarz_tol),
@@ -281,9 +293,9 @@ class Scf:
 
 
 def mess_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
-                    prec=MESS_FP64, jk_mode=MESS_JK_DIRECT, xc=MESS_XC_HF, D0=None) -> Scf:
+                    prec=MESS_FP64, jk_mode=MESS_JK_DIRECT, xc=MESS_XC_HF, D0=None, deterministic=False) -> Scf:
     opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), int(prec),
-                   int(jk_mode), int(xc), 0)
+                   int(jk_mode), int(xc), 1 if deterministic else 0)
     h = ctypes.c_void_p()
     _check(lib().mess_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), ctypes.byref(h)), "mess_scf_create")
     return Scf(h, basis)
