@@ -393,7 +393,11 @@ int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops
  *   MESS_FORM_PLANE  one wave per shell quartet, one lane per primitive
  *                    quartet, intermediates summed across the wave;
  *   MESS_FORM_COOP   one block per shell quartet, the recursion table-driven
- *                    in LDS (high classes).
+ *                    in LDS (high classes);
+ *   MESS_FORM_WAVE   one block per shell quartet, one wave per primitive
+ *                    quartet, lanes over the recursion's intermediates, the
+ *                    contracted outputs kept in registers ((dd|ds), (dd|dp),
+ *                    (dd|dd)).
  * The choice is process-wide and applies to every later launch (mess_eri,
  * mess_jk, SCF and batch steps; FP64 and FP32).
  *
@@ -406,10 +410,11 @@ int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops
  * schwarz_tol, time each available form on a direct J/K pass with density D
  * (device N x N, or packed for a batch) as the best of reps runs after one
  * warm-up (HIP events on the stream), and keep the fastest.  forms[21]
- * (host, may be NULL) receives the chosen forms; ms[21 * 5] (host, may be
- * NULL) the best time of form f for class c at ms[c * 5 + f] (-1 where not
+ * (host, may be NULL) receives the chosen forms; ms[21 * 6] (host, may be
+ * NULL) the best time of form f for class c at ms[c * 6 + f] (-1 where not
  * run).  Synchronises the stream; uses the basis's own J/K work buffer. */
-enum { MESS_FORM_AUTO = 0, MESS_FORM_LANE = 1, MESS_FORM_ROWS = 2, MESS_FORM_PLANE = 3, MESS_FORM_COOP = 4 };
+enum { MESS_FORM_AUTO = 0, MESS_FORM_LANE = 1, MESS_FORM_ROWS = 2, MESS_FORM_PLANE = 3, MESS_FORM_COOP = 4,
+       MESS_FORM_WAVE = 5 };
 int mess_kernel_form(int32_t cls, int32_t form, int32_t *active);
 int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, int32_t reps, int32_t *forms,
                   double *ms, mess_stream stream);

@@ -33,6 +33,8 @@ COOP_CLASSES = {(2, 2), (4, 2), (4, 4), (5, 2), (5, 3), (5, 4), (5, 5)}
 UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
 # primitive-lane kernels (plane.hip), one object per class and precision
 PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (4, 4), (4, 2), (2, 2)]
+# wave-per-primitive-quartet kernels (wave.hip)
+WAVE_CLASSES = [(5, 5), (5, 4), (5, 3)]
 
 
 def _units():
@@ -43,6 +45,11 @@ def _units():
             for cb, ck in UNROLLED_CLASSES:
                 units.append((src, os.path.join(OBJ, f"eri_class_{cb}{ck}.o"),
                               [f"-DMESS_CB={cb}", f"-DMESS_CK={ck}"]))
+        elif name == "wave":
+            for cb, ck in WAVE_CLASSES:
+                for real in ("double", "float"):
+                    units.append((src, os.path.join(OBJ, f"wave_{cb}{ck}_{real}.o"),
+                                  [f"-DMESS_WCB={cb}", f"-DMESS_WCK={ck}", f"-DMESS_WREAL={real}"]))
         elif name == "plane":
             for cb, ck in PLANE_CLASSES:
                 for real in ("double", "float"):
@@ -54,7 +61,8 @@ def _units():
     def weight(u):
         w = 0
         for d in u[2]:
-            if d.startswith("-DMESS_CB=") or d.startswith("-DMESS_CK=") or d.startswith("-DMESS_PC"):
+            if d.startswith("-DMESS_CB=") or d.startswith("-DMESS_CK=") or d.startswith("-DMESS_PC") \
+                    or d.startswith("-DMESS_WC"):
                 w += int(d.split("=")[1])
         return -w - (10 if "plane" in u[1] else 0)
     units.sort(key=weight)

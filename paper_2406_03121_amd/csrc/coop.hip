@@ -542,26 +542,6 @@ __device__ __forceinline__ void run_level(const CoopArgs &A, int lv, int gl, Rea
     }
 }
 
-// F_m(T) in the kernel's arithmetic: FP64 form above, or FP32 Taylor for
-// 1e-3 <= T <= 30 with the FP64 form rounded to FP32 outside.
-template <typename Real>
-__device__ __forceinline__ Real coop_boys_r(int m, Real T, const BoysTabs &bt) {
-    if constexpr (sizeof(Real) == 8) {
-        return coop_boys(m, T, bt.tab);
-    } else {
-        if (T < 1e-3f || T > 30.0f) return (float)coop_boys(m, (double)T, bt.tab);
-        const int k = __float2int_rn(T * (float)kBoysInvStep);
-        const float md = (float)k * (float)(1.0 / kBoysInvStep) - T;
-        const float *row = bt.tabf + k * kBoysN + m;
-        float f = row[5];
-        f = row[4] + md * (1.0f / 5.0f) * f;
-        f = row[3] + md * (1.0f / 4.0f) * f;
-        f = row[2] + md * (1.0f / 3.0f) * f;
-        f = row[1] + md * (1.0f / 2.0f) * f;
-        return row[0] + md * f;
-    }
-}
-
 // NT threads (one to four waves) share each shell quartet.
 // NT threads share each shell quartet; they form NP groups of NT/NP threads,
 // each group running the vertical recursion of its own primitive quartet
@@ -666,6 +646,19 @@ static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, 
 #undef MESS_PL
 }
 
+static void launch_wave(int mode, int cb, int ck, int prec, const CoopArgs &A, const ClassLaunch &L, int64_t total,
+                        unsigned g, const double *D, double *out0, double *out1, size_t *lds) {
+#define MESS_WV(B, K)                                                                                        \
+    if (cb == B && ck == K) {                                                                                \
+        if (prec == MESS_FP32) WaveOps<B, K, float>::launch(mode, A, L, total, g, D, out0, out1, lds);        \
+        else WaveOps<B, K, double>::launch(mode, A, L, total, g, D, out0, out1, lds);                         \
+    }
+    MESS_WV(5, 5)
+    MESS_WV(5, 4)
+    MESS_WV(5, 3)
+#undef MESS_WV
+}
+
 static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t total, double *out0, double *out1,
                        const double *D, int prec = MESS_FP64) {
     const CoopProgram *P = coop_program(cb, ck);
@@ -683,6 +676,17 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     A.NA = ncart(P->LA); A.NB = ncart(P->LB); A.NC = ncart(P->LC); A.ND = ncart(P->LD);
     int64_t g = total;
     if (g > (1 << 20)) g = 1 << 20;
+    if (wave_compiled(cb, ck) && class_form(cb, ck) == kFormWave) {
+        size_t lds = 0;
+        launch_wave(mode, cb, ck, prec, A, L, total, (unsigned)g, D, out0, out1, &lds);
+        if (lds > 64 * 1024) {
+            set_error("internal: class (%d,%d) needs %zu bytes of LDS in the wave form", cb, ck, lds);
+            return MESS_E_UNSUPPORTED;
+        }
+        launch_wave(mode, cb, ck, prec, A, L, total, (unsigned)g, D, out0, out1, nullptr);
+        MESS_LAUNCH_CHECK();
+        return MESS_OK;
+    }
     if (plane_class(cb, ck)) {
         const size_t lds = sizeof(double) * (size_t)(P->nH + kNHCoef);
         launch_plane(mode, cb, ck, prec, A, L, total, (unsigned)g, lds, D, out0, out1);

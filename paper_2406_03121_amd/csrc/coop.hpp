@@ -4,6 +4,8 @@
 // Schwarz factor or J/K digestion) of one quartet.
 #pragma once
 
+#include <algorithm>
+
 #include "class_ops.hpp"
 #include "eri_kernels.hpp"
 #include "mess_internal.hpp"
@@ -58,6 +60,26 @@ __device__ __forceinline__ double coop_boys(int m, double T, const double *__res
     double f = 0.5 * sqrt(M_PI * rT);
     for (int n = 0; n < m; ++n) f *= (2 * n + 1) * 0.5 * rT;
     return f;
+}
+
+// F_m(T) in the kernel's arithmetic: FP64 form of coop_boys, or FP32 Taylor for
+// 1e-3 <= T <= 30 with the FP64 form rounded to FP32 outside.
+template <typename Real>
+__device__ __forceinline__ Real coop_boys_r(int m, Real T, const BoysTabs &bt) {
+    if constexpr (sizeof(Real) == 8) {
+        return coop_boys(m, T, bt.tab);
+    } else {
+        if (T < 1e-3f || T > 30.0f) return (float)coop_boys(m, (double)T, bt.tab);
+        const int k = __float2int_rn(T * (float)kBoysInvStep);
+        const float md = (float)k * (float)(1.0 / kBoysInvStep) - T;
+        const float *row = bt.tabf + k * kBoysN + m;
+        float f = row[5];
+        f = row[4] + md * (1.0f / 5.0f) * f;
+        f = row[3] + md * (1.0f / 4.0f) * f;
+        f = row[2] + md * (1.0f / 3.0f) * f;
+        f = row[1] + md * (1.0f / 2.0f) * f;
+        return row[0] + md * f;
+    }
 }
 
 __device__ __forceinline__ double run_op(const int4 op, const double *__restrict__ V, const double *__restrict__ c) {
@@ -203,6 +225,15 @@ __device__ __forceinline__ void coop_finish(const CoopArgs &A, double *__restric
         }
 }
 
+
+// Wave-per-primitive-quartet launch of one class in one precision
+// (wave.hip, compiled once per class and precision).  With lds_out != NULL
+// only reports the dynamic LDS bytes the launch needs.
+template <int CB, int CK, typename Real>
+struct WaveOps {
+    static void launch(int mode, const CoopArgs &A, const ClassLaunch &L, int64_t total, unsigned g,
+                       const double *D, double *out0, double *out1, size_t *lds_out);
+};
 
 // Primitive-lane launch of one class in one precision (plane.hip, compiled
 // once per class and precision).

@@ -197,11 +197,13 @@ bool coop_class(int cb, int ck);
 
 // Kernel form of a class (tune.hip): the mapping of its quartets onto the
 // hardware.  Values match the MESS_FORM_* constants of the C ABI.
-enum : int { kFormAuto = 0, kFormLane = 1, kFormRows = 2, kFormPlane = 3, kFormCoop = 4, kNumForms = 5 };
+enum : int { kFormAuto = 0, kFormLane = 1, kFormRows = 2, kFormPlane = 3, kFormCoop = 4, kFormWave = 5,
+             kNumForms = 6 };
 constexpr int kNumClasses = 21;
 int class_form(int cb, int ck);       // active form (built-in default unless set)
 bool form_valid(int cb, int ck, int form);
 bool plane_compiled(int cb, int ck);  // primitive-lane kernel built for the class
+bool wave_compiled(int cb, int ck);   // wave-per-primitive-quartet kernel built for the class
 bool rows_compiled(int cb, int ck);   // bra-segment kernel built for the class
 
 // Profiling of class launches (HIP events on the launch stream).

@@ -5,7 +5,9 @@
 //  - rows:  one 256-thread block per segment of a bra's quartets, exchange
 //           rows of the bra functions in LDS (low classes);
 //  - plane: one wave per shell quartet, one lane per primitive quartet;
-//  - coop:  one block per shell quartet, the recursion table-driven in LDS.
+//  - coop:  one block per shell quartet, the recursion table-driven in LDS;
+//  - wave:  one block per shell quartet, one wave per primitive quartet,
+//           lanes over the recursion's intermediates (wave.hip).
 // Which is fastest depends on the class (registers, primitive counts) and
 // on the workload, so the choice is a run-time table.  The built-in
 // defaults come from measurements on MI355X; mess_autotune times every
@@ -33,6 +35,8 @@ bool plane_compiled(int cb, int ck) {
     return (cb == 5 && ck >= 2 && ck <= 4) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
 }
 
+bool wave_compiled(int cb, int ck) { return cb == 5 && ck >= 3; }
+
 bool rows_compiled(int cb, int ck) {
     // classes whose unrolled kernels include the bra-segment form
     return cb != 2 && ck != 2 && (cb <= 3 || ck == 0);
@@ -40,14 +44,16 @@ bool rows_compiled(int cb, int ck) {
 
 bool form_valid(int cb, int ck, int form) {
     if (form == kFormAuto) return true;
-    if (coop_class(cb, ck)) return form == kFormCoop || (form == kFormPlane && plane_compiled(cb, ck));
+    if (coop_class(cb, ck))
+        return form == kFormCoop || (form == kFormPlane && plane_compiled(cb, ck)) ||
+               (form == kFormWave && wave_compiled(cb, ck));
     if (form == kFormLane) return true;
     if (form == kFormRows) return rows_compiled(cb, ck);
     return false;
 }
 
 static int default_form(int cb, int ck) {
-    if (coop_class(cb, ck)) return (cb == 5 && ck == 5) ? kFormCoop : kFormPlane;
+    if (coop_class(cb, ck)) return (cb == 5 && ck == 5) ? kFormWave : kFormPlane;
     return rows_compiled(cb, ck) ? kFormRows : kFormLane;
 }
 

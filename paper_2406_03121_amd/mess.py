@@ -20,7 +20,7 @@ MESS_FP64, MESS_FP32 = 0, 1
 MESS_ERI_DENSE, MESS_ERI_BLOCKS = 0, 1
 MESS_JK_DIRECT, MESS_JK_STORED, MESS_JK_DETERMINISTIC = 0, 1, 2
 MESS_XC_HF, MESS_XC_LDA_X = 0, 1
-MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP = range(5)
+MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP, MESS_FORM_WAVE = range(6)
 
 EXPORTED = [
     "mess_basis_create", "mess_basis_destroy", "mess_basis_info", "mess_one_electron",
@@ -485,10 +485,10 @@ def mess_kernel_form(cls, form=-1):
 
 def mess_autotune(basis: Basis, D, schwarz_tol=0.0, reps=3, stream=None):
     """Time every form of every class on the basis and keep the fastest.
-    Returns (forms[21], ms[21, 5]) as numpy arrays."""
+    Returns (forms[21], ms[21, 6]) as numpy arrays."""
     forms = np.zeros(21, np.int32)
-    ms = np.zeros(21 * 5, np.float64)
+    ms = np.zeros(21 * 6, np.float64)
     _check(lib().mess_autotune(basis.handle, float(schwarz_tol), _ptr(D), int(reps),
                                forms.ctypes.data_as(ctypes.c_void_p), ms.ctypes.data_as(ctypes.c_void_p),
                                _stream(stream)), "mess_autotune")
-    return forms, ms.reshape(21, 5)
+    return forms, ms.reshape(21, 6)

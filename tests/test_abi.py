@@ -106,7 +106,7 @@ def test_kernel_form_table(mess):
     assert mess.mess_kernel_form(0, mess.MESS_FORM_LANE) == mess.MESS_FORM_LANE
     assert mess.mess_kernel_form(0, mess.MESS_FORM_AUTO) == mess.MESS_FORM_ROWS
     dd_dd = mess.class_index(5, 5)
-    assert mess.mess_kernel_form(dd_dd) == mess.MESS_FORM_COOP
+    assert mess.mess_kernel_form(dd_dd) == mess.MESS_FORM_WAVE
     assert L.mess_kernel_form(dd_dd, mess.MESS_FORM_LANE, None) == mess.MESS_E_UNSUPPORTED
     dd_dp = mess.class_index(5, 4)
     assert mess.mess_kernel_form(dd_dp) == mess.MESS_FORM_PLANE

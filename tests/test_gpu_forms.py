@@ -1,0 +1,72 @@
+"""Every kernel form of every class (the choices the autotuner makes) meets
+the same parity bar: with the form of one class forced, dense ERIs within
+1e-12 * max(1, |x|) of the extended-precision oracle and direct J/K within
+1e-11 * max(1, |x|) of the oracle's defining sums, for a molecule holding
+every angular class."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import announce, dev, host, need_gpu, random_density, zeros  # noqa: E402
+
+from mess_inputs import generators as G  # noqa: E402
+from oracle import core  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PC = ["ss", "ps", "pp", "ds", "dp", "dd"]
+FORMS = {1: "lane", 2: "rows", 3: "plane", 4: "coop", 5: "wave"}
+
+
+def _cases():
+    out = []
+    for cb in range(6):
+        for ck in range(cb + 1):
+            for f in FORMS:
+                out.append((cb, ck, f))
+    return out
+
+
+@pytest.fixture(scope="module")
+def ref():
+    mol = G.water_cluster(0, n_waters=2, box=7.0)
+    with core.extended_precision():
+        eri = core.eri_dense(mol)
+    D = random_density(mol.n_bf, seed=51)
+    J, K = core.jk_from_dense(core.eri_dense(mol), D)
+    return mol, eri, D, J, K
+
+
+@pytest.mark.parametrize("cb,ck,form", _cases())
+def test_form_parity(ref, cb, ck, form):
+    mess = need_gpu()
+    cls = mess.class_index(cb, ck)
+    import ctypes
+    if mess.lib().mess_kernel_form(cls, form, None) != mess.MESS_OK:
+        pytest.skip(f"form {FORMS[form]} not built for ({PC[cb]}|{PC[ck]})")
+    try:
+        mol, eri, D, Jo, Ko = ref
+        announce(f"form {FORMS[form]} for ({PC[cb]}|{PC[ck]})")
+        B = mess.basis_from_molecule(mol)
+        N = B.nbf
+        out = zeros(N, N, N, N)
+        mess.mess_eri(B, out, schwarz_tol=0.0)
+        got = host(out)
+        err = np.abs(got - eri) / np.maximum(1.0, np.abs(eri))
+        assert err.max() < 1e-12, err.max()
+        for tau in (0.0, 1e-10):
+            J, K = zeros(N, N), zeros(N, N)
+            mess.mess_jk(B, dev(D), J, K, schwarz_tol=tau)
+            if tau == 0.0:
+                rel = lambda a, b: np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))  # noqa: E731
+                assert rel(host(J), Jo) < 1e-11 and rel(host(K), Ko) < 1e-11
+            else:
+                Jt, Kt, _ = core.jk_unique(mol, D, tau)
+                rel = lambda a, b: np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b)))  # noqa: E731
+                assert rel(host(J), Jt) < 1e-11 and rel(host(K), Kt) < 1e-11
+        B.close()
+    finally:
+        mess.mess_kernel_form(cls, mess.MESS_FORM_AUTO)
