@@ -94,6 +94,34 @@ def cpu_baseline(mol, target_seconds):
                       f"FP64 McMurchie-Davidson oracle, {dt:.1f} s"}
 
 
+def fp32_jk_error(mess, mol, a, torch):
+    """max |dJ|, max |dK| of one FP32 build at the oracle's converged density
+    D* against the oracle's J(D*), K(D*) (stored golden of this workload)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{mol.name.replace('/', '_')}_jk.npz")
+    if not os.path.exists(path):
+        return {}
+    g = np.load(path)
+    N = mol.n_bf
+    iu = np.triu_indices(N)
+
+    def full(v):
+        M = np.zeros((N, N))
+        M[iu] = v
+        return M + np.triu(M, 1).T
+    Dst, Jo, Ko = full(g["dstar_D"]), full(g["dstar_J"]), full(g["dstar_K"])
+    B = mess.basis_from_molecule(mol)
+    D = torch.tensor(Dst, dtype=torch.float64, device="cuda")
+    J = torch.zeros(N, N, dtype=torch.float64, device="cuda")
+    K = torch.zeros_like(J)
+    mess.mess_jk(B, D, J, K, prec=mess.MESS_FP32, schwarz_tol=a.tau)
+    torch.cuda.synchronize()
+    dJ = float(np.max(np.abs(J.cpu().numpy() - Jo)))
+    dK = float(np.max(np.abs(K.cpu().numpy() - Ko)))
+    B.close()
+    return {"max_abs_dJ_at_converged_density": dJ, "max_abs_dK_at_converged_density": dK,
+            "max_abs_J": float(np.max(np.abs(Jo))), "max_abs_K": float(np.max(np.abs(Ko)))}
+
+
 def recorded_traffic(class_name):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-scaled), or None when it
@@ -110,6 +138,27 @@ def recorded_traffic(class_name):
     for src in d["sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
     return d["hbm_bytes_per_launch"] if h.hexdigest() == d["sources_sha256"] else None
+
+
+FORM_NAMES = {1: "lane", 2: "rows", 3: "plane", 4: "coop", 5: "wave", 6: "fp64"}
+
+
+def autotune_block(mess, mol, a, torch):
+    """Kernel form per class chosen by the library's autotuner on this
+    molecule (FP64 and FP32 arithmetic), before any timed work."""
+    from mess_inputs import generators as G
+    B = mess.basis_from_molecule(mol)
+    D = torch.tensor(G.symmetric_density(mol.n_bf, 3), dtype=torch.float64, device="cuda")
+    out = {}
+    for prec, name in ((mess.MESS_FP64, "fp64"), (mess.MESS_FP32, "fp32")):
+        forms, ms = mess.mess_autotune(B, D, schwarz_tol=a.tau, reps=2, prec=prec)
+        out[name] = {CLASS_NAMES[c]: {"form": FORM_NAMES.get(int(forms[c]), str(int(forms[c]))),
+                                      "ms": {FORM_NAMES[f]: round(float(ms[c, f]), 3)
+                                             for f in FORM_NAMES if ms[c, f] >= 0}}
+                     for c in range(21)}
+    B.close()
+    log("autotuned forms (fp64): " + ", ".join(f"{k} {v['form']}" for k, v in out["fp64"].items()))
+    return out
 
 
 def lda_block(mess, mol, a, torch):
@@ -196,6 +245,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 1024-molecule batched SCF")
     ap.add_argument("--batch-molecules", type=int, default=1024)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel forms")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -207,6 +257,7 @@ def main():
     torch.cuda.init()
     mol = make_workload(a.workload, a.seed)
     log(f"workload {mol.name}: {mol.n_atoms} atoms, {mol.n_shells} shells, {mol.n_bf} functions")
+    tune = None if a.no_tune else autotune_block(mess, mol, a, torch)
     for w in range(a.warmup):
         e, it, conv = scf_once(mess, mol, a.tau, a.conv)
         log(f"warmup {w}: E={e:.10f} iterations={it} converged={conv}")
@@ -268,26 +319,39 @@ def main():
                      "traffic": recorded_traffic(CLASS_NAMES[dom])},
         "cpu_baseline": None,
     }
+    if tune is not None:
+        line["autotune"] = tune
     golden = os.path.join(ROOT, "tests", "golden", f"{mol.name.replace('/', '_')}_rhf.json")
     if os.path.exists(golden):
         ref = json.load(open(golden))["energy"]
         line["delta_e_vs_oracle_hartree"] = energies[-1] - ref
     if not a.no_fp32:
-        # same molecule, mixed precision (FP32 dD builds), timed separately
+        # same molecule, mixed precision, timed like the FP64 run (class
+        # events on), per-class kernel times in both arithmetics
         scf_once(mess, mol, a.tau, a.conv, verbose=False, prec=mess.MESS_FP32)
         torch.cuda.synchronize()
+        mess.mess_prof_enable(True)
         t2 = time.perf_counter()
         r32 = [scf_once(mess, mol, a.tau, a.conv, verbose=False, prec=mess.MESS_FP32) for _ in range(a.steps)]
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        pc32 = {}
+        for c in range(21):
+            r64, r32c = mess.mess_prof_read(c), mess.mess_prof_read(64 + c)
+            pc32[CLASS_NAMES[c]] = {
+                "fp32_ms_per_launch": round(r32c["ms"] / r32c["launches"], 4) if r32c["launches"] else None,
+                "fp64_ms_per_launch": round(per[c]["ms"] / per[c]["launches"], 4) if c in per else None,
+                "fp32_launches": r32c["launches"], "fp64_launches": r64["launches"]}
+        mess.mess_prof_enable(False)
         fp32 = {"ms_per_step": (t3 - t2) / a.steps * 1e3, "molecules_per_s": a.steps / (t3 - t2),
                 "scf_iterations": r32[-1][1], "energy_hartree": r32[-1][0],
-                "delta_e_vs_fp64_hartree": r32[-1][0] - energies[-1]}
+                "delta_e_vs_fp64_hartree": r32[-1][0] - energies[-1], "per_class": pc32}
         fp32["speedup_vs_fp64"] = fp32["molecules_per_s"] / line["molecules_per_s"]
         if "delta_e_vs_oracle_hartree" in line:
             fp32["delta_e_vs_oracle_hartree"] = r32[-1][0] - ref
+        fp32.update(fp32_jk_error(mess, mol, a, torch))
         line["fp32_mixed"] = fp32
-        log(f"fp32: {fp32}")
+        log(f"fp32: {dict((k, v) for k, v in fp32.items() if k != 'per_class')}")
     if not a.no_stored:
         # same molecule, stored J/K: blocks computed once per SCF (first
         # Fock build), streamed from HBM by the later builds

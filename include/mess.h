@@ -68,13 +68,17 @@ typedef struct mess_scf_opts {
     double conv_tol;     /* converged when |E_k - E_{k-1}| < conv_tol */
     int32_t max_iter;    /* informational for callers driving mess_scf_step */
     int32_t diis_size;   /* Pulay DIIS history length; 0 = plain Roothaan iteration */
-    int32_t prec;        /* MESS_FP64, or MESS_FP32: Fock builds of the density change
-                            dD = D_k - D_{k-1} added to FP64 J/K, in FP32 arithmetic once the
-                            previous |dE| < 1e-3 Ha (FP64 before); full FP64 build at the
-                            first iteration and every 8th.  With MESS_JK_DIRECT and
-                            schwarz_tol > 0 the dD builds also skip quartets with
-                            Q_ab Q_cd max|dD| < schwarz_tol (threshold rounded down to a
-                            power of ten) */
+    int32_t prec;        /* MESS_FP64, or MESS_FP32 (mixed precision): until |dE| first
+                            drops below 0.1 Ha every Fock build is a complete FP32 build;
+                            the first build after that is a complete FP64 build, the next ones
+                            build dD = D_k - D_{k-1} in FP32 and add it to the FP64 J/K,
+                            with a complete FP64 rebuild after every 8 of them.  With
+                            MESS_JK_DIRECT and schwarz_tol > 0 the dD builds also skip
+                            quartets with Q_ab Q_cd max|dD| < schwarz_tol (threshold
+                            rounded down to a power of ten).  Convergence is declared only
+                            on two successive FP64-anchored energies.  Energies,
+                            eigen-problem and density in FP64; classes whose FP64 kernel is
+                            faster run in FP64 (MESS_FORM_FP64) */
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
     int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X (F = H + J + V_x,
                             E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; FP64 only; see mess_lda_x) */
@@ -372,7 +376,8 @@ int mess_guess_judge(const mess_basis *basis, const mess_scf_opts *opts, double 
  *
  * mess_prof_enable(1) starts recording a pair of HIP events on the launch
  * stream around every class launch of mess_jk / mess_scf_step (0 stops;
- * both discard earlier records).  mess_prof_read sums, for one class (or
+ * both discard earlier records).  Direct launches in FP32 arithmetic are
+ * recorded under cls + 64, stored-block streams under cls + 32.  mess_prof_read sums, for one class (or
  * all with cls = -1), launches, elapsed milliseconds between the events,
  * algorithmic operations, shell and primitive quartets.  Synchronises on
  * the recorded events. */
@@ -397,27 +402,33 @@ int mess_prof_read(int32_t cls, int64_t *launches, double *ms, double *alg_flops
  *   MESS_FORM_WAVE   one block per shell quartet, one wave per primitive
  *                    quartet, lanes over the recursion's intermediates, the
  *                    contracted outputs kept in registers ((dd|ds), (dd|dp),
- *                    (dd|dd)).
- * The choice is process-wide and applies to every later launch (mess_eri,
- * mess_jk, SCF and batch steps; FP64 and FP32).
+ *                    (dd|dd));
+ *   MESS_FORM_FP64   FP32 table only: direct J/K builds asked for in FP32
+ *                    evaluate the class with its FP64 kernel (more accurate,
+ *                    and faster for the low classes on this hardware).
+ * The choice is process-wide, kept per precision of the integral arithmetic
+ * (MESS_FP64, MESS_FP32), and applies to every later launch in that
+ * precision (mess_eri, mess_jk, SCF and batch steps).
  *
  * mess_kernel_form: set the form of class cls (index as for
- * mess_work_stats) when form >= 0 (MESS_FORM_AUTO restores the built-in
- * default), and return the active form in *active (may be NULL).
- * MESS_E_UNSUPPORTED if the form is not built for the class.
+ * mess_work_stats) in precision prec when form >= 0 (MESS_FORM_AUTO
+ * restores the built-in default), and return the active form in *active
+ * (may be NULL).  MESS_E_UNSUPPORTED if the form is not built for the
+ * class, MESS_E_ARG for an unknown precision or class.
  *
  * mess_autotune: for every class with quartets in the basis's work list at
- * schwarz_tol, time each available form on a direct J/K pass with density D
+ * schwarz_tol, time each available form in precision prec on a direct J/K
+ * pass with density D
  * (device N x N, or packed for a batch) as the best of reps runs after one
  * warm-up (HIP events on the stream), and keep the fastest.  forms[21]
- * (host, may be NULL) receives the chosen forms; ms[21 * 6] (host, may be
- * NULL) the best time of form f for class c at ms[c * 6 + f] (-1 where not
+ * (host, may be NULL) receives the chosen forms; ms[21 * 7] (host, may be
+ * NULL) the best time of form f for class c at ms[c * 7 + f] (-1 where not
  * run).  Synchronises the stream; uses the basis's own J/K work buffer. */
 enum { MESS_FORM_AUTO = 0, MESS_FORM_LANE = 1, MESS_FORM_ROWS = 2, MESS_FORM_PLANE = 3, MESS_FORM_COOP = 4,
-       MESS_FORM_WAVE = 5 };
-int mess_kernel_form(int32_t cls, int32_t form, int32_t *active);
-int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, int32_t reps, int32_t *forms,
-                  double *ms, mess_stream stream);
+       MESS_FORM_WAVE = 5, MESS_FORM_FP64 = 6 };
+int mess_kernel_form(int32_t prec, int32_t cls, int32_t form, int32_t *active);
+int mess_autotune(const mess_basis *basis, int32_t prec, double schwarz_tol, const double *D, int32_t reps,
+                  int32_t *forms, double *ms, mess_stream stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *mess_last_error(void);

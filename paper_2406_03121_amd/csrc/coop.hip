@@ -447,9 +447,9 @@ static std::pair<double, double> count_flops(int cb, int ck, bool swapped) {
     return {fp, fq};
 }
 
-void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk) {
+void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk, int prec) {
     const int la = pair_class_la(cb), lb = pair_class_lb(cb), lc = pair_class_la(ck), ld = pair_class_lb(ck);
-    const bool swapped = coop_class(cb, ck) && class_form(cb, ck) == kFormPlane && swap_vrr(la, lb, lc, ld);
+    const bool swapped = coop_class(cb, ck) && class_form(cb, ck, prec) == kFormPlane && swap_vrr(la, lb, lc, ld);
     std::lock_guard<std::mutex> lk(g_flop_mutex);
     auto key = std::make_pair(cb * 8 + (swapped ? 1 : 0), ck);
     auto it = g_flops.find(key);
@@ -628,7 +628,9 @@ __global__ void __launch_bounds__(NT) k_coop(CoopArgs A, int region, int vstride
 
 // Classes run with the primitive-lane mapping: the form chosen for the
 // class (built-in default or autotuned; see tune.hip).
-static bool plane_class(int cb, int ck) { return plane_compiled(cb, ck) && class_form(cb, ck) == kFormPlane; }
+static bool plane_class(int cb, int ck, int prec) {
+    return plane_compiled(cb, ck) && class_form(cb, ck, prec) == kFormPlane;
+}
 
 static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, const ClassLaunch &L, int64_t total,
                          unsigned g, size_t lds, const double *D, double *out0, double *out1) {
@@ -676,7 +678,7 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
     A.NA = ncart(P->LA); A.NB = ncart(P->LB); A.NC = ncart(P->LC); A.ND = ncart(P->LD);
     int64_t g = total;
     if (g > (1 << 20)) g = 1 << 20;
-    if (wave_compiled(cb, ck) && class_form(cb, ck) == kFormWave) {
+    if (wave_compiled(cb, ck) && class_form(cb, ck, prec) == kFormWave) {
         size_t lds = 0;
         launch_wave(mode, cb, ck, prec, A, L, total, (unsigned)g, D, out0, out1, &lds);
         if (lds > 64 * 1024) {
@@ -687,7 +689,7 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
         MESS_LAUNCH_CHECK();
         return MESS_OK;
     }
-    if (plane_class(cb, ck)) {
+    if (plane_class(cb, ck, prec)) {
         const size_t lds = sizeof(double) * (size_t)(P->nH + kNHCoef);
         launch_plane(mode, cb, ck, prec, A, L, total, (unsigned)g, lds, D, out0, out1);
         MESS_LAUNCH_CHECK();

@@ -64,7 +64,7 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
         // classes with a pp pair, and dp or dd bras with a ps ket); the
         // default form of these classes unless the form table says lane
         const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
-        if (L.segs && L.nseg > 0 && lds <= 48 * 1024 && class_form(MESS_CB, MESS_CK) == kFormRows) {
+        if (L.segs && L.nseg > 0 && lds <= 48 * 1024 && class_form(MESS_CB, MESS_CK, prec) == kFormRows) {
             const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
             if (prec == MESS_FP32)
                 hipLaunchKernelGGL((k_jk_rows<Dm, float, true>), dim3(g), dim3(256), lds, L.stream, L.pairs,

@@ -64,14 +64,19 @@ int jk_direct_half(mess_basis *B, const double *D, double *Gj, double *Gk, int p
         if (cl.total == 0) continue;
         ClassLaunch L;
         fill_class_launch(B, cl, s, L);
+        // arithmetic of this class: a build asked for in FP32 runs a class in
+        // FP64 where the FP32 form table says its FP64 kernel is faster
+        const int cp = (prec == MESS_FP32 && class_form(cl.cb, cl.ck, MESS_FP32) == kFormFp64) ? MESS_FP64 : prec;
         if (prof) {
             double fp = 0.0, fq = 0.0;
-            class_flops(cl.cb, cl.ck, &fp, &fq);
-            prof_record(s, class_index(cl.cb, cl.ck), true, cl.total, cl.prim_quartets,
+            class_flops(cl.cb, cl.ck, &fp, &fq, cp);
+            // FP32 launches are recorded under class index + 64
+            prof_record(s, class_index(cl.cb, cl.ck) + (cp == MESS_FP32 ? 64 : 0), true, cl.total,
+                        cl.prim_quartets,
                         fp * (double)cl.prim_quartets + fq * (double)cl.total);
         }
         MESS_TRY(dispatch_class(cl.cb, cl.ck, [&](auto CB, auto CK) {
-            return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(L, D, Gj, Gk, prec);
+            return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(L, D, Gj, Gk, cp);
         }));
         if (prof) prof_record(s, 0, false, 0, 0, 0.0);
     }

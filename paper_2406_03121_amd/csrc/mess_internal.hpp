@@ -187,7 +187,7 @@ inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
 // Algorithmic FP64 operation counts of the recursion for one class (an FMA
 // counts 2): per primitive quartet (Boys, vertical recursion, contraction)
 // and per shell quartet (horizontal recursion + J/K digestion).
-void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk);
+void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk, int prec = MESS_FP64);
 
 // True when class (cb, ck) has nothing left to allocate on the device for
 // its launches (cooperative step tables built, or none needed).
@@ -198,10 +198,12 @@ bool coop_class(int cb, int ck);
 // Kernel form of a class (tune.hip): the mapping of its quartets onto the
 // hardware.  Values match the MESS_FORM_* constants of the C ABI.
 enum : int { kFormAuto = 0, kFormLane = 1, kFormRows = 2, kFormPlane = 3, kFormCoop = 4, kFormWave = 5,
-             kNumForms = 6 };
+             kFormFp64 = 6, kNumForms = 7 };
+// kFormFp64 (FP32 table only): builds asked for in FP32 evaluate the class in
+// FP64 arithmetic, with its FP64 form (where that kernel is the faster one).
 constexpr int kNumClasses = 21;
-int class_form(int cb, int ck);       // active form (built-in default unless set)
-bool form_valid(int cb, int ck, int form);
+int class_form(int cb, int ck, int prec = MESS_FP64);  // active form (built-in default unless set)
+bool form_valid(int cb, int ck, int form, int prec = MESS_FP64);
 bool plane_compiled(int cb, int ck);  // primitive-lane kernel built for the class
 bool wave_compiled(int cb, int ck);   // wave-per-primitive-quartet kernel built for the class
 bool rows_compiled(int cb, int ck);   // bra-segment kernel built for the class

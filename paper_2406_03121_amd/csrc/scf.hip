@@ -66,6 +66,11 @@ struct mess_scf {
     double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
     double last_dmax = 0.0;  // max |dD| and screening threshold of the last incremental build
     double last_tau = 0.0;
+    bool acc_valid = false;   // FP32 mode: Gja/Gka hold an FP64 build plus dD builds
+    bool near = false;        // FP32 mode: the energy change has been below kNearDe
+    bool prev_anchored = false;  // FP32 mode: the previous energy came from anchored J/K
+    int since_full = 0;       // dD builds since the last complete build
+    int last_build_prec = 0;  // last Fock build: MESS_FP64/MESS_FP32 complete, -prec-1 for a dD build
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
     int sp2_iters_last = 0;
@@ -74,6 +79,10 @@ struct mess_scf {
 namespace mess {
 
 constexpr int kRedBlocks = 256;
+// Mixed precision: energy change below which the Fock builds switch from
+// complete FP32 builds to an FP64 build plus FP32 builds of the density
+// change (Hartree).
+constexpr double kNearDe = 1e-1;
 
 // Hartree-Fock (Vx == NULL): F = H + J - K/2 with J = Gj + Gj^T,
 // K = Gk + Gk^T, and per-block partial sums of D .* (H + F);
@@ -613,18 +622,26 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     const int64_t nn = (int64_t)N * N, mm = (int64_t)M * M;
     // J, K half matrices
     if (st->opts.prec == MESS_FP32) {
-        // Incremental builds: a full FP64 build at the first iteration and
-        // every 8th, otherwise the build of dD = D_k - D_{k-1} added to the
-        // FP64 running half-matrices.  The dD build runs in FP32 once the
-        // previous energy change is below 1e-3 Ha (its FP32 rounding then
-        // scales with a small change and stays far below 1e-6 Ha in E);
-        // earlier, larger changes are built in FP64, since an FP32 error in
-        // them would persist in the running Fock matrix.
-        const bool full = (st->iter % 8) == 0;
-        const int dprec = st->last_de < 1e-3 ? MESS_FP32 : MESS_FP64;
-        if (full) {
-            MESS_TRY(scf_jk(st, st->D, st->Gja, st->Gka, MESS_FP64, st->opts.schwarz_tol, s));
+        // Mixed precision.  Until the energy change first drops below
+        // kNearDe, every Fock build is a complete FP32 build (its rounding is
+        // far below the change of the density, and nothing of it is kept).
+        // From then on (for good) the first build is a complete FP64 build;
+        // after it, builds of dD = D_k - D_{k-1} in FP32 are added to the
+        // FP64 running half-matrices (their rounding scales with the small
+        // change), with a complete FP64 rebuild after every 8 of them.
+        // Convergence is only declared on FP64-anchored builds.
+        if (st->last_de < kNearDe) st->near = true;
+        const bool near = st->near;
+        if (!near || !st->acc_valid || st->since_full >= 8) {
+            const int fprec = near ? MESS_FP64 : MESS_FP32;
+            MESS_TRY(scf_jk(st, st->D, st->Gja, st->Gka, fprec, st->opts.schwarz_tol, s));
+            st->acc_valid = near;
+            st->since_full = 0;
+            st->last_build_prec = fprec;
         } else {
+            const int dprec = MESS_FP32;
+            st->last_build_prec = -dprec - 1;
+            ++st->since_full;
             MESS_TRY(axpby(s, nn, 1.0, st->D, -1.0, st->Dprev, st->dD));
             // Direct builds screen the change by its size as well: a quartet
             // with Q_ab Q_cd max|dD| < tol moves no element of J or K by more
@@ -687,7 +704,11 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         return MESS_E_NUMERIC;
     }
     const double de = st->iter > 0 ? h.energy - st->e_prev : 0.0;
-    const bool conv = st->iter > 0 && std::fabs(de) < st->opts.conv_tol;
+    // mixed precision: only an energy on FP64-anchored J/K, following
+    // another such energy, may end the iteration
+    const bool anchored = st->opts.prec != MESS_FP32 || (st->acc_valid && st->prev_anchored);
+    const bool conv = st->iter > 0 && std::fabs(de) < st->opts.conv_tol && anchored;
+    st->prev_anchored = st->opts.prec != MESS_FP32 || st->acc_valid;
     if (energy) *energy = h.energy;
     if (delta_e) *delta_e = de;
     if (resid) *resid = h.resid;

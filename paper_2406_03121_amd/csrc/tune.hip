@@ -7,7 +7,9 @@
 //  - plane: one wave per shell quartet, one lane per primitive quartet;
 //  - coop:  one block per shell quartet, the recursion table-driven in LDS;
 //  - wave:  one block per shell quartet, one wave per primitive quartet,
-//           lanes over the recursion's intermediates (wave.hip).
+//           lanes over the recursion's intermediates (wave.hip);
+//  - fp64:  (mixed precision only) the class's FP64 kernel serves builds
+//           asked for in FP32, where it is the faster one.
 // Which is fastest depends on the class (registers, primitive counts) and
 // on the workload, so the choice is a run-time table.  The built-in
 // defaults come from measurements on MI355X; mess_autotune times every
@@ -28,7 +30,7 @@ int zero_async(double *p, int64_t n, hipStream_t s);
 
 namespace {
 std::mutex g_form_mutex;
-int g_form[kNumClasses] = {};  // kFormAuto: built-in default
+int g_form[2][kNumClasses] = {};  // [precision][class]; kFormAuto: built-in default
 }  // namespace
 
 bool plane_compiled(int cb, int ck) {
@@ -42,8 +44,9 @@ bool rows_compiled(int cb, int ck) {
     return cb != 2 && ck != 2 && (cb <= 3 || ck == 0);
 }
 
-bool form_valid(int cb, int ck, int form) {
+bool form_valid(int cb, int ck, int form, int prec) {
     if (form == kFormAuto) return true;
+    if (form == kFormFp64) return prec == MESS_FP32;
     if (coop_class(cb, ck))
         return form == kFormCoop || (form == kFormPlane && plane_compiled(cb, ck)) ||
                (form == kFormWave && wave_compiled(cb, ck));
@@ -52,20 +55,28 @@ bool form_valid(int cb, int ck, int form) {
     return false;
 }
 
-static int default_form(int cb, int ck) {
+static int default_form(int cb, int ck, int prec) {
+    // FP32 builds: the classes with an s pair or a ps/pp pair against a lower
+    // one run as fast or faster in FP64 (measured on MI355X; the FP32 Boys
+    // function falls back to FP64 outside 1e-3 <= T <= 30, and FP32 and FP64
+    // FMAs issue at the same rate without packed math)
+    if (prec == MESS_FP32) {
+        const int c = class_index(cb, ck);
+        if (c == 0 || c == 1 || c == 3 || c == 4 || c == 8 || c == 10 || c == 11 || c == 15) return kFormFp64;
+    }
     if (coop_class(cb, ck)) return (cb == 5 && ck == 5) ? kFormWave : kFormPlane;
     return rows_compiled(cb, ck) ? kFormRows : kFormLane;
 }
 
-int class_form(int cb, int ck) {
+int class_form(int cb, int ck, int prec) {
     std::lock_guard<std::mutex> lk(g_form_mutex);
-    const int f = g_form[class_index(cb, ck)];
-    return f == kFormAuto ? default_form(cb, ck) : f;
+    const int f = g_form[prec == MESS_FP32 ? 1 : 0][class_index(cb, ck)];
+    return f == kFormAuto ? default_form(cb, ck, prec) : f;
 }
 
-static void set_form(int cls, int form) {
+static void set_form(int prec, int cls, int form) {
     std::lock_guard<std::mutex> lk(g_form_mutex);
-    g_form[cls] = form;
+    g_form[prec == MESS_FP32 ? 1 : 0][cls] = form;
 }
 
 }  // namespace mess
@@ -74,7 +85,11 @@ using namespace mess;
 
 extern "C" {
 
-int mess_kernel_form(int32_t cls, int32_t form, int32_t *active) {
+int mess_kernel_form(int32_t prec, int32_t cls, int32_t form, int32_t *active) {
+    if (prec != MESS_FP64 && prec != MESS_FP32) {
+        set_error("mess_kernel_form: unknown precision %d", prec);
+        return MESS_E_ARG;
+    }
     if (cls < 0 || cls >= kNumClasses) {
         set_error("mess_kernel_form: class index %d outside 0..%d", cls, kNumClasses - 1);
         return MESS_E_ARG;
@@ -83,20 +98,24 @@ int mess_kernel_form(int32_t cls, int32_t form, int32_t *active) {
     while ((cb + 1) * (cb + 2) / 2 <= cls) ++cb;
     const int ck = cls - cb * (cb + 1) / 2;
     if (form >= 0) {
-        if (!form_valid(cb, ck, form)) {
+        if (!form_valid(cb, ck, form, prec)) {
             set_error("mess_kernel_form: form %d is not available for class %d", form, cls);
             return MESS_E_UNSUPPORTED;
         }
-        set_form(cls, form);
+        set_form(prec, cls, form);
     }
-    if (active) *active = class_form(cb, ck);
+    if (active) *active = class_form(cb, ck, prec);
     return MESS_OK;
 }
 
-int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, int32_t reps, int32_t *forms,
-                  double *ms, mess_stream stream) {
+int mess_autotune(const mess_basis *basis, int32_t prec, double schwarz_tol, const double *D, int32_t reps,
+                  int32_t *forms, double *ms, mess_stream stream) {
     if (!basis || !D) {
         set_error("mess_autotune: NULL basis or density");
+        return MESS_E_ARG;
+    }
+    if (prec != MESS_FP64 && prec != MESS_FP32) {
+        set_error("mess_autotune: unknown precision %d", prec);
         return MESS_E_ARG;
     }
     if (reps < 1 || reps > 100) {
@@ -125,8 +144,8 @@ int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, 
         double best_ms = 0.0;
         if (cl.total > 0) {
             for (int form = 1; form < kNumForms && rc == MESS_OK; ++form) {
-                if (!form_valid(cl.cb, cl.ck, form)) continue;
-                set_form(cls, form);
+                if (!form_valid(cl.cb, cl.ck, form, prec)) continue;
+                set_form(prec, cls, form);
                 ClassLaunch L;
                 fill_class_launch(B, cl, s, L);
                 double tmin = 1e300;
@@ -136,7 +155,8 @@ int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, 
                     if (hipEventRecord(e0, s) != hipSuccess) rc = MESS_E_DEVICE;
                     if (rc == MESS_OK)
                         rc = dispatch_class(cl.cb, cl.ck, [&](auto CB, auto CK) {
-                            return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(L, D, Gj, Gk, MESS_FP64);
+                            return ClassOps<decltype(CB)::value, decltype(CK)::value>::jk(
+                                L, D, Gj, Gk, form == kFormFp64 ? MESS_FP64 : prec);
                         });
                     if (rc == MESS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                         rc = MESS_E_DEVICE;
@@ -153,11 +173,11 @@ int mess_autotune(const mess_basis *basis, double schwarz_tol, const double *D, 
             }
         }
         if (rc != MESS_OK) {
-            set_form(cls, kFormAuto);
+            set_form(prec, cls, kFormAuto);
             break;
         }
-        set_form(cls, best);
-        if (forms) forms[cls] = best == kFormAuto ? class_form(cl.cb, cl.ck) : best;
+        set_form(prec, cls, best);
+        if (forms) forms[cls] = best == kFormAuto ? class_form(cl.cb, cl.ck, prec) : best;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

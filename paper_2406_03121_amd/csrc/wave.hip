@@ -305,18 +305,22 @@ __global__ void __launch_bounds__(256) k_wave(CoopArgs A, int region, const Pair
             });
         }
         // the four waves' sums into H[(f - F0) NEA + (e - E0)] in the class's
-        // own orientation
+        // own orientation: each wave writes its own copy (after H), then the
+        // copies are added in wave order, so the result does not depend on
+        // timing (the deterministic J/K mode relies on reproducible blocks)
         __syncthreads();
-        for (int s = tid; s < A.nacc; s += 256) H[s] = 0.0;
-        __syncthreads();
+        double *Hw = H + A.nacc;
         if (out_lane) {
             const int e = kWaveMapDev<Dr>.pe[lane];
             static_for<0, NFO>([&](auto F) {
                 constexpr int fo = decltype(F)::value;
                 const int x = SW ? (e - Dr::E0) * Dm::NEA + fo : fo * Dm::NEA + (e - Dr::E0);
-                atomicAdd(&H[x], (double)acc[fo]);
+                Hw[wave * A.nacc + x] = (double)acc[fo];
             });
         }
+        __syncthreads();
+        for (int s = tid; s < A.nacc; s += 256)
+            H[s] = ((Hw[s] + Hw[A.nacc + s]) + Hw[2 * A.nacc + s]) + Hw[3 * A.nacc + s];
         __syncthreads();
         coop_finish<MODE, 256>(A, H, hc, tid, bra, ket, i, j, bra_off, same_class, D, N, out0, out1, q, total);
         __syncthreads();
@@ -330,7 +334,9 @@ void WaveOps<MESS_WCB, MESS_WCK, MESS_WREAL>::launch(int mode, const CoopArgs &A
     using Dm = ClassOf<MESS_WCB, MESS_WCK>;
     using R = MESS_WREAL;
     using Lds = WaveLds<Dm, R>;
-    const int region = std::max(Lds::VRR_DOUBLES, A.nH);
+    // VRR blocks during the primitive loop; then the accumulators, the four
+    // waves' copies of them, and the HRR slots
+    const int region = std::max(std::max(Lds::VRR_DOUBLES, A.nH), 5 * A.nacc);
     const size_t lds = sizeof(double) * ((size_t)region + kNHCoef);
     if (lds_out) {
         *lds_out = lds;

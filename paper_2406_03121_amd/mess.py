@@ -20,7 +20,7 @@ MESS_FP64, MESS_FP32 = 0, 1
 MESS_ERI_DENSE, MESS_ERI_BLOCKS = 0, 1
 MESS_JK_DIRECT, MESS_JK_STORED, MESS_JK_DETERMINISTIC = 0, 1, 2
 MESS_XC_HF, MESS_XC_LDA_X = 0, 1
-MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP, MESS_FORM_WAVE = range(6)
+MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP, MESS_FORM_WAVE, MESS_FORM_FP64 = range(7)
 
 EXPORTED = [
     "mess_basis_create", "mess_basis_destroy", "mess_basis_info", "mess_one_electron",
@@ -109,8 +109,8 @@ def lib():
         L.mess_prof_enable.argtypes = [i32]
         L.mess_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(f64),
                                      ctypes.POINTER(i64), ctypes.POINTER(i64)]
-        L.mess_kernel_form.argtypes = [i32, i32, ctypes.POINTER(i32)]
-        L.mess_autotune.argtypes = [vp, f64, vp, i32, vp, vp, vp]
+        L.mess_kernel_form.argtypes = [i32, i32, i32, ctypes.POINTER(i32)]
+        L.mess_autotune.argtypes = [vp, i32, f64, vp, i32, vp, vp, vp]
         L.mess_last_error.argtypes = []
         L.mess_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -476,19 +476,20 @@ def mess_prof_read(cls=-1):
             "prim_quartets": p.value}
 
 
-def mess_kernel_form(cls, form=-1):
-    """Set the kernel form of class cls (form >= 0); returns the active form."""
+def mess_kernel_form(cls, form=-1, prec=MESS_FP64):
+    """Set the kernel form of class cls in precision prec (form >= 0);
+    returns the active form."""
     act = ctypes.c_int32()
-    _check(lib().mess_kernel_form(int(cls), int(form), ctypes.byref(act)), "mess_kernel_form")
+    _check(lib().mess_kernel_form(int(prec), int(cls), int(form), ctypes.byref(act)), "mess_kernel_form")
     return act.value
 
 
-def mess_autotune(basis: Basis, D, schwarz_tol=0.0, reps=3, stream=None):
+def mess_autotune(basis: Basis, D, schwarz_tol=0.0, reps=3, prec=MESS_FP64, stream=None):
     """Time every form of every class on the basis and keep the fastest.
-    Returns (forms[21], ms[21, 6]) as numpy arrays."""
+    Returns (forms[21], ms[21, 7]) as numpy arrays."""
     forms = np.zeros(21, np.int32)
-    ms = np.zeros(21 * 6, np.float64)
-    _check(lib().mess_autotune(basis.handle, float(schwarz_tol), _ptr(D), int(reps),
+    ms = np.zeros(21 * 7, np.float64)
+    _check(lib().mess_autotune(basis.handle, int(prec), float(schwarz_tol), _ptr(D), int(reps),
                                forms.ctypes.data_as(ctypes.c_void_p), ms.ctypes.data_as(ctypes.c_void_p),
                                _stream(stream)), "mess_autotune")
-    return forms, ms.reshape(21, 6)
+    return forms, ms.reshape(21, 7)

@@ -98,23 +98,31 @@ def test_kernel_form_table(mess):
     """The form table is host state: validation needs no device."""
     L = mess.lib()
     act = ctypes.c_int32()
-    assert L.mess_kernel_form(21, -1, ctypes.byref(act)) == mess.MESS_E_ARG
-    assert L.mess_kernel_form(-1, -1, None) == mess.MESS_E_ARG
+    assert L.mess_kernel_form(0, 21, -1, ctypes.byref(act)) == mess.MESS_E_ARG
+    assert L.mess_kernel_form(0, -1, -1, None) == mess.MESS_E_ARG
+    assert L.mess_kernel_form(9, 0, -1, None) == mess.MESS_E_ARG
     # (ss|ss) has no primitive-lane or table-driven form
-    assert L.mess_kernel_form(0, mess.MESS_FORM_PLANE, None) == mess.MESS_E_UNSUPPORTED
+    assert L.mess_kernel_form(0, 0, mess.MESS_FORM_PLANE, None) == mess.MESS_E_UNSUPPORTED
+    # forms are kept per precision
+    assert mess.mess_kernel_form(0, mess.MESS_FORM_LANE, prec=mess.MESS_FP32) == mess.MESS_FORM_LANE
+    assert mess.mess_kernel_form(0) == mess.MESS_FORM_ROWS
+    # FP32 builds run (ss|ss) with its FP64 kernel by default
+    assert mess.mess_kernel_form(0, mess.MESS_FORM_AUTO, prec=mess.MESS_FP32) == mess.MESS_FORM_FP64
+    assert L.mess_kernel_form(0, 0, mess.MESS_FORM_FP64, None) == mess.MESS_E_UNSUPPORTED
+    assert mess.mess_kernel_form(mess.class_index(5, 5), prec=mess.MESS_FP32) == mess.MESS_FORM_WAVE
     assert mess.mess_kernel_form(0) == mess.MESS_FORM_ROWS          # built-in default
     assert mess.mess_kernel_form(0, mess.MESS_FORM_LANE) == mess.MESS_FORM_LANE
     assert mess.mess_kernel_form(0, mess.MESS_FORM_AUTO) == mess.MESS_FORM_ROWS
     dd_dd = mess.class_index(5, 5)
     assert mess.mess_kernel_form(dd_dd) == mess.MESS_FORM_WAVE
-    assert L.mess_kernel_form(dd_dd, mess.MESS_FORM_LANE, None) == mess.MESS_E_UNSUPPORTED
+    assert L.mess_kernel_form(0, dd_dd, mess.MESS_FORM_LANE, None) == mess.MESS_E_UNSUPPORTED
     dd_dp = mess.class_index(5, 4)
     assert mess.mess_kernel_form(dd_dp) == mess.MESS_FORM_PLANE
 
 
 def test_new_entry_points_reject_null(mess):
     L = mess.lib()
-    assert L.mess_autotune(None, 0.0, None, 1, None, None, None) == mess.MESS_E_ARG
+    assert L.mess_autotune(None, 0, 0.0, None, 1, None, None, None) == mess.MESS_E_ARG
     assert L.mess_eri_quartets(None, 0.0, None, None) == mess.MESS_E_ARG
     assert L.mess_jk_noalloc(None, None, None, None, 0, 0.0, None) == mess.MESS_E_ARG
     assert L.mess_jk(None, None, None, None, mess.MESS_JK_DETERMINISTIC, 0, 0.0, None) == mess.MESS_E_ARG
