@@ -269,8 +269,13 @@ void mess_scf_destroy(mess_scf *scf);
 
 /* Batched SCF over every molecule of a batch handle: the step of
  * mess_scf_step applied to each molecule, with all molecules' ERI classes,
- * Fock builds, DIIS and density purifications sharing launches.  FP64
- * only (opts->prec must be MESS_FP64); X is the Loewdin S^{-1/2} of each
+ * Fock builds, DIIS and density purifications sharing launches.
+ * opts->prec MESS_FP64, or MESS_FP32 (mixed precision decided by the step
+ * count alone, so steps stay free of host decisions): the first 2 Fock
+ * builds are complete FP32 builds, the third a complete FP64 build, later
+ * ones FP32 builds of the density change added to it with a complete FP64
+ * rebuild after every 8; a molecule freezes only on two successive
+ * FP64-anchored energies.  X is the Loewdin S^{-1/2} of each
  * molecule (MESS_E_NUMERIC if an overlap block may be near-singular).
  * D0: device packed initial density, or NULL for the core-Hamiltonian
  * guess.  use_graph != 0 captures the first step into a HIP graph and

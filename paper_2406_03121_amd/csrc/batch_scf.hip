@@ -31,6 +31,13 @@ int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, 
 
 constexpr int kBMaxDiis = 16;
 constexpr int kSp2Rounds = 100;  // purification rounds per step (finished molecules idle)
+// Mixed-precision batches: the first kFarSteps Fock builds are complete FP32
+// builds; then a complete FP64 build, FP32 builds of the density change added
+// to it, and a complete FP64 rebuild after every kDeltaRun of those.
+constexpr int kFarSteps = 2;
+constexpr int kDeltaRun = 8;
+// Kinds of step (one captured graph each).
+enum { kStepFull64 = 0, kStepFull64Open = 1, kStepFull32 = 2, kStepDelta32 = 3, kNumStepKinds = 4 };
 
 struct MolScalars {
     double energy, e_new, de, resid;
@@ -55,8 +62,10 @@ struct mess_batch_scf {
     int64_t packed = 0;
     bool use_graph = false;
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[mess::kNumStepKinds] = {};
+    hipGraphExec_t exec[mess::kNumStepKinds] = {};
+    int host_iter = 0, since_full = 0;  // mixed precision: steps so far, dD builds since a complete FP64 build
+    double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // mixed precision
     double *S = nullptr, *H = nullptr, *X = nullptr, *D = nullptr, *F = nullptr, *Fx = nullptr, *Gj = nullptr,
            *Gk = nullptr, *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *P = nullptr, *P2 = nullptr, *E = nullptr;
     double *Fh = nullptr, *Eh = nullptr, *Bm = nullptr;
@@ -494,14 +503,35 @@ static int purify_density(mess_batch_scf *st, const double *Fp, double *Dn, hipS
     return MESS_OK;
 }
 
-static int enqueue_step(mess_batch_scf *st, hipStream_t s) {
-    mess_basis *B = st->basis;
-    const BLaunch L = blaunch(st);
+static int batch_jk(mess_batch_scf *st, const double *D, double *Gj, double *Gk, int prec, hipStream_t s) {
     if (st->opts.jk_mode == MESS_JK_DIRECT)
-        MESS_TRY(jk_direct_half(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
-    else
-        MESS_TRY(jk_stored(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
-    hipLaunchKernelGGL(k_bfock, L.per_mol, dim3(256), 0, s, L.nmol, L.moff, L.nb, st->H, st->Gj, st->Gk, st->D,
+        return jk_direct_half(st->basis, D, Gj, Gk, prec, st->opts.schwarz_tol, s);
+    return jk_stored(st->basis, D, Gj, Gk, prec, st->opts.schwarz_tol, s);
+}
+
+static int enqueue_step(mess_batch_scf *st, hipStream_t s, int kind) {
+    const BLaunch L = blaunch(st);
+    const double *Gjf = st->Gj, *Gkf = st->Gk;
+    bool may_converge = kind == kStepFull64 || kind == kStepDelta32;
+    if (st->opts.prec != MESS_FP32) {
+        MESS_TRY(batch_jk(st, st->D, st->Gj, st->Gk, MESS_FP64, s));
+        may_converge = true;
+    } else {
+        // mixed precision: the running half-matrices Gja/Gka
+        if (kind == kStepDelta32) {
+            MESS_TRY(axpby(s, st->packed, 1.0, st->D, -1.0, st->Dprev, st->dD));
+            MESS_TRY(batch_jk(st, st->dD, st->Gj, st->Gk, MESS_FP32, s));
+            MESS_TRY(axpby(s, st->packed, 1.0, st->Gja, 1.0, st->Gj, st->Gja));
+            MESS_TRY(axpby(s, st->packed, 1.0, st->Gka, 1.0, st->Gk, st->Gka));
+        } else {
+            MESS_TRY(batch_jk(st, st->D, st->Gja, st->Gka, kind == kStepFull32 ? MESS_FP32 : MESS_FP64, s));
+        }
+        hipLaunchKernelGGL(k_bcopy, dim3((unsigned)std::min<int64_t>((st->packed + 255) / 256, 65536)), dim3(256), 0,
+                           s, st->packed, st->D, st->Dprev);
+        Gjf = st->Gja;
+        Gkf = st->Gka;
+    }
+    hipLaunchKernelGGL(k_bfock, L.per_mol, dim3(256), 0, s, L.nmol, L.moff, L.nb, st->H, Gjf, Gkf, st->D,
                        st->enuc, st->F, st->ms);
     MESS_LAUNCH_CHECK();
     // e = X^T (F D S - S D F) X
@@ -512,7 +542,10 @@ static int enqueue_step(mess_batch_scf *st, hipStream_t s) {
     MESS_TRY(bgemm(st, s, true, false, 1.0, st->X, st->W1, 0.0, st->W3));
     MESS_TRY(bgemm(st, s, false, false, 1.0, st->W3, st->X, 0.0, st->E));
     hipLaunchKernelGGL(k_bmaxabs, L.per_mol, dim3(256), 0, s, L.nmol, L.moff, L.nb, st->E, st->ms);
-    hipLaunchKernelGGL(k_bconv, L.per_thread, dim3(64), 0, s, L.nmol, st->opts.conv_tol, st->bs, st->ms);
+    // only energies on FP64-anchored J/K following another such energy may
+    // freeze a molecule (a negative tolerance freezes none)
+    hipLaunchKernelGGL(k_bconv, L.per_thread, dim3(64), 0, s, L.nmol, may_converge ? st->opts.conv_tol : -1.0,
+                       st->bs, st->ms);
     MESS_LAUNCH_CHECK();
     const double *Fuse = st->F;
     if (st->nd > 0) {
@@ -537,11 +570,13 @@ static int enqueue_step(mess_batch_scf *st, hipStream_t s) {
 
 static void free_batch(mess_batch_scf *st) {
     if (!st) return;
-    if (st->exec) hipGraphExecDestroy(st->exec);
-    if (st->graph) hipGraphDestroy(st->graph);
+    for (int k = 0; k < kNumStepKinds; ++k) {
+        if (st->exec[k]) hipGraphExecDestroy(st->exec[k]);
+        if (st->graph[k]) hipGraphDestroy(st->graph[k]);
+    }
     if (st->cap) hipStreamDestroy(st->cap);
     for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
-                      st->P2, st->E, st->Fh, st->Eh, st->Bm, st->enuc, st->nocc})
+                      st->P2, st->E, st->Fh, st->Eh, st->Bm, st->enuc, st->nocc, st->Dprev, st->dD, st->Gja, st->Gka})
         hipFree(p);
     hipFree(st->ms);
     hipFree(st->bs);
@@ -628,6 +663,8 @@ static int batch_create_impl(mess_batch_scf *st, const double *D0, bool ortho_on
     MESS_HIP(hipMalloc(&st->Fh, sizeof(double) * pk * nd1));
     MESS_HIP(hipMalloc(&st->Eh, sizeof(double) * pk * nd1));
     MESS_HIP(hipMalloc(&st->Bm, sizeof(double) * kBMaxDiis * kBMaxDiis * st->nmol));
+    if (st->opts.prec == MESS_FP32)
+        for (double **p : {&st->Dprev, &st->dD, &st->Gja, &st->Gka}) MESS_HIP(hipMalloc(p, sizeof(double) * pk));
     MESS_HIP(hipMalloc(&st->enuc, sizeof(double) * st->nmol));
     MESS_HIP(hipMalloc(&st->nocc, sizeof(double) * st->nmol));
     MESS_HIP(hipMalloc(&st->ms, sizeof(MolScalars) * st->nmol));
@@ -657,12 +694,10 @@ static int batch_create_impl(mess_batch_scf *st, const double *D0, bool ortho_on
     }
     // the purification state of the guess is not a step's: reset it
     MESS_HIP(hipMemsetAsync(st->ms, 0, sizeof(MolScalars) * st->nmol, s));
-    // work lists (and the stored integrals) are built here, so that a step
-    // allocates nothing and can be captured
-    if (st->opts.jk_mode == MESS_JK_DIRECT)
-        MESS_TRY(jk_direct_half(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
-    else
-        MESS_TRY(jk_stored(B, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+    // work lists (and the stored integrals, in every precision a step uses)
+    // are built here, so that a step allocates nothing and can be captured
+    MESS_TRY(batch_jk(st, st->D, st->Gj, st->Gk, MESS_FP64, s));
+    if (st->opts.prec == MESS_FP32) MESS_TRY(batch_jk(st, st->D, st->Gj, st->Gk, MESS_FP32, s));
     MESS_HIP(hipStreamSynchronize(s));
     if (st->use_graph) MESS_HIP(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
     return MESS_OK;
@@ -788,9 +823,8 @@ int mess_batch_scf_create(const mess_basis *basis, const mess_scf_opts *opts, co
         set_error("mess_batch_scf_create: unknown J/K mode %d", opts->jk_mode);
         return MESS_E_UNSUPPORTED;
     }
-    if (opts->prec != MESS_FP64) {
-        set_error("mess_batch_scf_create: precision %d; batches run in FP64 (mess_jk takes FP32 for a batch)",
-                  opts->prec);
+    if (opts->prec != MESS_FP64 && opts->prec != MESS_FP32) {
+        set_error("mess_batch_scf_create: unknown precision %d", opts->prec);
         return MESS_E_UNSUPPORTED;
     }
     if (opts->xc != MESS_XC_HF) {
@@ -820,14 +854,31 @@ int mess_batch_scf_step(mess_batch_scf *st, mess_stream stream) {
         return MESS_E_ARG;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!st->use_graph) return enqueue_step(st, s);
-    if (!st->exec) {
+    // kind of this step, decided on the host from the step count alone
+    int kind = kStepFull64;
+    if (st->opts.prec == MESS_FP32) {
+        if (st->host_iter < kFarSteps) {
+            kind = kStepFull32;
+        } else if (st->host_iter == kFarSteps) {
+            kind = kStepFull64Open;  // the previous energy was not anchored
+            st->since_full = 0;
+        } else if (st->since_full >= kDeltaRun) {
+            kind = kStepFull64;
+            st->since_full = 0;
+        } else {
+            kind = kStepDelta32;
+            ++st->since_full;
+        }
+    }
+    st->host_iter += 1;
+    if (!st->use_graph) return enqueue_step(st, s, kind);
+    if (!st->exec[kind]) {
         if (prof_on()) {
             set_error("mess_batch_scf_step: class profiling cannot be recorded inside a graph");
             return MESS_E_ARG;
         }
         MESS_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(st, st->cap);
+        int rc = enqueue_step(st, st->cap, kind);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(st->cap, &g);
         if (rc != MESS_OK) {
@@ -835,10 +886,10 @@ int mess_batch_scf_step(mess_batch_scf *st, mess_stream stream) {
             return rc;
         }
         MESS_HIP(e);
-        st->graph = g;
-        MESS_HIP(hipGraphInstantiate(&st->exec, st->graph, nullptr, nullptr, 0));
+        st->graph[kind] = g;
+        MESS_HIP(hipGraphInstantiate(&st->exec[kind], st->graph[kind], nullptr, nullptr, 0));
     }
-    MESS_HIP(hipGraphLaunch(st->exec, s));
+    MESS_HIP(hipGraphLaunch(st->exec[kind], s));
     return MESS_OK;
 }
 

@@ -336,8 +336,8 @@ class BatchScf:
 
 
 def mess_batch_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
-                          jk_mode=MESS_JK_DIRECT, D0=None, use_graph=False) -> BatchScf:
-    opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), MESS_FP64,
+                          jk_mode=MESS_JK_DIRECT, D0=None, use_graph=False, prec=MESS_FP64) -> BatchScf:
+    opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), int(prec),
                    int(jk_mode), MESS_XC_HF, 0)
     h = ctypes.c_void_p()
     _check(lib().mess_batch_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), 1 if use_graph else 0,

@@ -159,6 +159,36 @@ def test_batched_scf_converged_energy_vs_oracle(batch):
     bs.close()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_scf_mixed_precision(batch, use_graph):
+    """Mixed-precision batch (FP32 builds, FP64 anchors): every molecule
+    converges to its FP64 batch energy within 1e-6 Ha, and the smallest ones
+    to the oracle's within 1e-6 Ha."""
+    mess, mols, B, singles = batch
+    from oracle import scf as oscf
+    tau = 1e-10
+    out = {}
+    for prec in (mess.MESS_FP64, mess.MESS_FP32):
+        bs = mess.mess_batch_scf_create(B, schwarz_tol=tau, conv_tol=1e-9, diis_size=8, use_graph=use_graph,
+                                        prec=prec)
+        for k in range(80):
+            mess.mess_batch_scf_step(bs)
+            st = mess.mess_batch_scf_status(bs)
+            if st["n_converged"] == B.n_mol:
+                break
+        assert st["n_converged"] == B.n_mol, prec
+        out[prec] = (st["energy"].copy(), k + 1)
+        bs.close()
+    e64, n64 = out[mess.MESS_FP64]
+    e32, n32 = out[mess.MESS_FP32]
+    announce(f"mixed batch: steps {n32} (FP64 {n64}), max |dE| {np.max(np.abs(e32 - e64)):.2e}")
+    assert np.max(np.abs(e32 - e64)) < 1e-6
+    small = sorted(range(len(mols)), key=lambda m: mols[m].n_bf)[:2]
+    for m in small:
+        ref = oscf.RHF(mols[m], jk="dense", conv_tol=1e-10, max_iter=200).run()
+        assert abs(e32[m] - ref["energy"]) < 1e-6, m
+
+
 def test_batch_rejections(batch):
     mess, mols, B, singles = batch
     out = zeros(8)
