@@ -258,6 +258,30 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
 int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid,
                   int32_t *converged, mess_stream stream);
 
+/* Direct minimisation of the energy (section 3: minimise E(C) subject to
+ * the orthonormality constraint C^T S C = 1 of eq. 5, the constraint built
+ * in by QR orthonormalisation of an unconstrained trial matrix; section 5.1:
+ * first-order optimisation with Adam from Z = 1).  One step on an SCF
+ * handle: Z = Q R, C = X Q with X = S^{-1/2}, D = 2 C_occ C_occ^T (C_occ the
+ * first n_occ columns), E = 1/2 Tr[D (H + F)] + E_nuc with F from a Fock
+ * build in the handle's J/K mode and precision; the gradient
+ * dE/dZ = Q tril(B^T - B, -1) R^{-T}, B = (X^T 4 F C_occ)^T Q (zero beyond
+ * column n_occ); then one Adam update of Z (lr, beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected).  The first call starts from Z = 1.  Outputs
+ * (host, may be NULL): E of the Z before the update, max |dE/dZ|.  The
+ * handle's density and Fock matrix become those of that Z.  Synchronous.
+ * Errors: MESS_E_ARG (lr not positive), MESS_E_UNSUPPORTED (LDA exchange,
+ * or an overlap that needed the canonical orthogonaliser), MESS_E_NUMERIC
+ * (Z became singular, or a non-finite result). */
+int mess_dmin_step(mess_scf *scf, double lr, double *energy, double *grad_max, mess_stream stream);
+/* The energy E(Z) (host, may be NULL) and its gradient dE/dZ (device N x N,
+ * may be NULL) of mess_dmin_step for a given trial matrix Z (device N x N),
+ * with no optimiser update.  Synchronous.  Errors as mess_dmin_step. */
+int mess_dmin_eval(mess_scf *scf, const double *Z, double *energy, double *G, mess_stream stream);
+/* Copy the current trial matrix Z (device N x N) of a handle that has taken
+ * direct-minimisation steps. */
+int mess_dmin_trial(const mess_scf *scf, double *Z, mess_stream stream);
+
 /* Copy the current density (device N x N) into D. */
 int mess_scf_density(const mess_scf *scf, double *D, mess_stream stream);
 

@@ -38,7 +38,7 @@ struct ScfScalars {
     double idem;          // tr(X) - tr(X^2) of the last purification step
     double dmax;          // max |dD| of the last incremental build
     int sp2_iter, sp2_done, sp2_post;
-    int pad;
+    int flag;             // direct minimisation: Cholesky pivot not positive
     double diis_c[kMaxDiis + 1];
 };
 
@@ -63,6 +63,10 @@ struct mess_scf {
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
     double *Vx = nullptr;                                // LDA exchange potential
     int *d_hs = nullptr;                                 // DIIS history slot list, kMaxDiis
+    // direct minimisation (mess_dmin_step): trial matrix, QR factors, Adam
+    // moments, gradient work (N x N each, built on the first call)
+    double *Zt = nullptr, *Qf = nullptr, *Rf = nullptr, *Am = nullptr, *Av = nullptr, *Gz = nullptr;
+    int dmin_t = 0;
     double last_de = 1e300;  // |E_k - E_{k-1}| of the previous step
     double last_dmax = 0.0;  // max |dD| and screening threshold of the last incremental build
     double last_tau = 0.0;
@@ -497,6 +501,7 @@ static void free_scf(mess_scf *st) {
         hipFree(p);
     hipFree(st->sc);
     hipFree(st->d_hs);
+    for (double *p : {st->Zt, st->Qf, st->Rf, st->Am, st->Av, st->Gz}) hipFree(p);
     delete st;
 }
 
@@ -755,6 +760,176 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     return MESS_OK;
 }
 
+// ------------------------------------------------ direct minimisation
+//
+// E(Z) over an unconstrained square trial matrix Z: Z = Q R (QR
+// decomposition), C = X Q with the Loewdin X = S^{-1/2} (so C^T S C = 1,
+// the orthonormality constraint), D = 2 C_occ C_occ^T, E as in the SCF step.
+// Gradient: dE/dC_occ = 4 F C_occ; Qbar = X^T Cbar; with B = Qbar^T Q,
+// dE/dZ = Q tril(B^T - B, -1) R^{-T}.  Q and R come from the Cholesky
+// factor of Z^T Z (R upper with positive diagonal, Q = Z R^{-1}); E and its
+// gradient do not depend on the sign convention of the QR factors.
+
+__global__ void k_fill_int(int *__restrict__ p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// In place: A (n x n, symmetric positive definite) -> upper Cholesky factor
+// R with A = R^T R (the strict lower triangle set to zero); flag = 1 if a
+// pivot is not positive.  One workgroup.
+__global__ void __launch_bounds__(1024) k_chol_upper(int n, double *__restrict__ A, int *__restrict__ flag) {
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        const double akk = A[(int64_t)k * n + k];
+        if (!(akk > 0.0)) {
+            if (threadIdx.x == 0) *flag = 1;
+            return;
+        }
+        const double r = sqrt(akk), ir = 1.0 / r;
+        __syncthreads();
+        for (int j = k + threadIdx.x; j < n; j += blockDim.x) A[(int64_t)k * n + j] = j == k ? r : A[(int64_t)k * n + j] * ir;
+        __syncthreads();
+        // trailing update of the upper triangle: A[i][j] -= R[k][i] R[k][j], k < i <= j
+        const int m = n - k - 1;
+        for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+            const int i = k + 1 + (int)(t / m), j = k + 1 + (int)(t % m);
+            if (j >= i) A[(int64_t)i * n + j] -= A[(int64_t)k * n + i] * A[(int64_t)k * n + j];
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x)
+        if (t / n > t % n) A[t] = 0.0;
+}
+
+// Row-wise triangular solves with the upper factor R (n x n), one thread per
+// row: trans = 0: X R = B (X = B R^{-1}); trans = 1: X R^T = B.
+__global__ void k_trsm_rows(int n, const double *__restrict__ R, const double *__restrict__ Bm, double *__restrict__ X,
+                            int trans) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *b = Bm + (int64_t)i * n;
+    double *x = X + (int64_t)i * n;
+    if (!trans) {
+        for (int j = 0; j < n; ++j) {
+            double s = b[j];
+            for (int k = 0; k < j; ++k) s -= x[k] * R[(int64_t)k * n + j];
+            x[j] = s / R[(int64_t)j * n + j];
+        }
+    } else {
+        for (int j = n - 1; j >= 0; --j) {
+            double s = b[j];
+            for (int k = j + 1; k < n; ++k) s -= R[(int64_t)j * n + k] * x[k];
+            x[j] = s / R[(int64_t)j * n + j];
+        }
+    }
+}
+
+// W = tril(B^T - B, -1) for B with rows >= nb zero (B stored nb x n).
+__global__ void k_tril_skew(int n, int nb, const double *__restrict__ Bm, double *__restrict__ W) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t % n);
+        double v = 0.0;
+        if (i > j) v = (j < nb ? Bm[(int64_t)j * n + i] : 0.0) - (i < nb ? Bm[(int64_t)i * n + j] : 0.0);
+        W[t] = v;
+    }
+}
+
+// Adam step on Z with gradient g (bias-corrected; b1 = 0.9, b2 = 0.999, eps = 1e-8).
+__global__ void k_adam(int64_t n, double lr, double c1, double c2, const double *__restrict__ g, double *__restrict__ m,
+                       double *__restrict__ v, double *__restrict__ Z) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double gt = g[t];
+        const double mt = 0.9 * m[t] + 0.1 * gt;
+        const double vt = 0.999 * v[t] + 0.001 * gt * gt;
+        m[t] = mt;
+        v[t] = vt;
+        Z[t] -= lr * (mt / c1) / (sqrt(vt / c2) + 1e-8);
+    }
+}
+
+__global__ void k_set_identity(int n, double *__restrict__ A) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        A[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+static int dmin_buffers(mess_scf *st, hipStream_t s) {
+    const int N = st->N;
+    const int64_t nn = (int64_t)N * N;
+    if (!st->Zt) {
+        for (double **p : {&st->Zt, &st->Qf, &st->Rf, &st->Am, &st->Av, &st->Gz})
+            MESS_HIP(hipMalloc(p, sizeof(double) * std::max<int64_t>(nn, 16)));
+        hipLaunchKernelGGL(k_set_identity, dim3(grid1(nn)), dim3(256), 0, s, N, st->Zt);
+        MESS_TRY(zero_async(st->Am, nn, s));
+        MESS_TRY(zero_async(st->Av, nn, s));
+        st->dmin_t = 0;
+    }
+    return MESS_OK;
+}
+
+// E(Z) and dE/dZ (into Gz) for the trial matrix Zin (device N x N).
+static int dmin_eval(mess_scf *st, const double *Zin, double *energy, double *gmax, hipStream_t s) {
+    mess_basis *B = st->basis;
+    const int N = st->N, n = B->nocc;
+    const int64_t nn = (int64_t)N * N;
+    const unsigned gew = (unsigned)grid1(nn);
+    MESS_TRY(dmin_buffers(st, s));
+    // QR of Z through the Cholesky factor of Z^T Z
+    MESS_TRY(gemm(s, true, false, N, N, N, 1.0, Zin, N, Zin, N, 0.0, st->Rf, N));
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, &st->sc->flag, 0);
+    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, s, N, st->Rf, &st->sc->flag);
+    hipLaunchKernelGGL(k_trsm_rows, dim3((N + 63) / 64), dim3(64), 0, s, N, st->Rf, Zin, st->Qf, 0);
+    MESS_LAUNCH_CHECK();
+    // C = X Q (in W1), D = 2 C_occ C_occ^T
+    MESS_TRY(gemm(s, false, false, N, N, N, 1.0, st->X, N, st->Qf, N, 0.0, st->W1, N));
+    MESS_TRY(gemm(s, false, true, N, N, n, 2.0, st->W1, N, st->W1, N, 0.0, st->D, N));
+    // F and E
+    MESS_TRY(scf_jk(st, st->D, st->Gj, st->Gk, st->opts.prec, st->opts.schwarz_tol, s));
+    hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, (const double *)nullptr,
+                       st->D, st->F, st->partial);
+    hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc,
+                       (const double *)nullptr, st->sc);
+    MESS_LAUNCH_CHECK();
+    // Cbar = 4 F C_occ (N x n, in W2, leading dimension N); Qbar = X^T Cbar (W3)
+    MESS_TRY(gemm(s, false, false, N, n, N, 4.0, st->F, N, st->W1, N, 0.0, st->W2, N));
+    MESS_TRY(gemm(s, true, false, N, n, N, 1.0, st->X, N, st->W2, N, 0.0, st->W3, N));
+    // B = Qbar^T Q (n x N, in P); W = tril(B^T - B, -1) (P2); Gz = (Q W) R^{-T}
+    MESS_TRY(gemm(s, true, false, n, N, N, 1.0, st->W3, N, st->Qf, N, 0.0, st->P, N));
+    hipLaunchKernelGGL(k_tril_skew, dim3(gew), dim3(256), 0, s, N, n, st->P, st->P2);
+    MESS_TRY(gemm(s, false, false, N, N, N, 1.0, st->Qf, N, st->P2, N, 0.0, st->W1, N));
+    hipLaunchKernelGGL(k_trsm_rows, dim3((N + 63) / 64), dim3(64), 0, s, N, st->Rf, st->W1, st->Gz, 1);
+    hipLaunchKernelGGL(k_maxabs_to, dim3(1), dim3(1024), 0, s, nn, st->Gz, &st->sc->dmax);
+    MESS_LAUNCH_CHECK();
+    ScfScalars h;
+    MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    if (h.flag) {
+        set_error("mess_dmin_step: the trial matrix became singular (Z^T Z not positive definite)");
+        return MESS_E_NUMERIC;
+    }
+    if (!std::isfinite(h.energy) || !std::isfinite(h.dmax)) {
+        set_error("mess_dmin_step: non-finite energy or gradient");
+        return MESS_E_NUMERIC;
+    }
+    if (energy) *energy = h.energy;
+    if (gmax) *gmax = h.dmax;
+    return MESS_OK;
+}
+
+static int dmin_step_impl(mess_scf *st, double lr, double *energy, double *gmax, hipStream_t s) {
+    const int64_t nn = (int64_t)st->N * st->N;
+    const unsigned gew = (unsigned)grid1(nn);
+    MESS_TRY(dmin_buffers(st, s));
+    MESS_TRY(dmin_eval(st, st->Zt, energy, gmax, s));
+    // Adam update of Z
+    st->dmin_t += 1;
+    const double c1 = 1.0 - std::pow(0.9, st->dmin_t), c2 = 1.0 - std::pow(0.999, st->dmin_t);
+    hipLaunchKernelGGL(k_adam, dim3(gew), dim3(256), 0, s, nn, lr, c1, c2, st->Gz, st->Am, st->Av, st->Zt);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
 }  // namespace mess
 
 using namespace mess;
@@ -839,5 +1014,57 @@ int mess_scf_fock(const mess_scf *scf, double *F, mess_stream stream) {
 }
 
 void mess_scf_destroy(mess_scf *scf) { free_scf(scf); }
+
+int mess_dmin_step(mess_scf *scf, double lr, double *energy, double *grad_max, mess_stream stream) {
+    if (!scf) {
+        set_error("mess_dmin_step: NULL handle");
+        return MESS_E_ARG;
+    }
+    if (!(lr > 0.0) || !std::isfinite(lr)) {
+        set_error("mess_dmin_step: learning rate must be positive and finite");
+        return MESS_E_ARG;
+    }
+    if (scf->M != scf->N) {
+        set_error("mess_dmin_step: the overlap needed the canonical orthogonaliser (%d of %d functions kept); "
+                  "direct minimisation needs the Loewdin S^-1/2", scf->M, scf->N);
+        return MESS_E_UNSUPPORTED;
+    }
+    if (scf->opts.xc != MESS_XC_HF) {
+        set_error("mess_dmin_step: only the Hartree-Fock energy is minimised directly");
+        return MESS_E_UNSUPPORTED;
+    }
+    return dmin_step_impl(scf, lr, energy, grad_max, static_cast<hipStream_t>(stream));
+}
+
+int mess_dmin_eval(mess_scf *scf, const double *Z, double *energy, double *G, mess_stream stream) {
+    if (!scf || !Z) {
+        set_error("mess_dmin_eval: NULL handle or trial matrix");
+        return MESS_E_ARG;
+    }
+    if (scf->M != scf->N || scf->opts.xc != MESS_XC_HF) {
+        set_error("mess_dmin_eval: needs the Loewdin S^-1/2 and the Hartree-Fock energy");
+        return MESS_E_UNSUPPORTED;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MESS_TRY(dmin_eval(scf, Z, energy, nullptr, s));
+    if (G)
+        MESS_HIP(hipMemcpyAsync(G, scf->Gz, sizeof(double) * scf->N * scf->N, hipMemcpyDeviceToDevice, s));
+    MESS_HIP(hipStreamSynchronize(s));
+    return MESS_OK;
+}
+
+int mess_dmin_trial(const mess_scf *scf, double *Z, mess_stream stream) {
+    if (!scf || !Z) {
+        set_error("mess_dmin_trial: NULL argument");
+        return MESS_E_ARG;
+    }
+    if (!scf->Zt) {
+        set_error("mess_dmin_trial: no direct-minimisation step has run on this handle");
+        return MESS_E_ARG;
+    }
+    MESS_HIP(hipMemcpyAsync(Z, scf->Zt, sizeof(double) * scf->N * scf->N, hipMemcpyDeviceToDevice,
+                            static_cast<hipStream_t>(stream)));
+    return MESS_OK;
+}
 
 }  // extern "C"

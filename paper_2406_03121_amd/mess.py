@@ -33,7 +33,8 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc", "mess_eri_quartets",
+    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc", "mess_eri_quartets", "mess_dmin_step",
+    "mess_dmin_trial", "mess_dmin_eval",
 ]
 MESS_MLP_NPARAM = 115328
 
@@ -71,6 +72,9 @@ def lib():
         L.mess_jk.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp]
         L.mess_jk_noalloc.argtypes = [vp, vp, vp, vp, i32, f64, vp]
         L.mess_eri_quartets.argtypes = [vp, f64, vp, vp]
+        L.mess_dmin_step.argtypes = [vp, f64, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
+        L.mess_dmin_trial.argtypes = [vp, vp, vp]
+        L.mess_dmin_eval.argtypes = [vp, vp, ctypes.POINTER(f64), vp, vp]
         if hasattr(L, "mess_scf_create"):
             L.mess_scf_create.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, ctypes.POINTER(vp)]
             L.mess_scf_step.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), ctypes.POINTER(f64),
@@ -299,6 +303,25 @@ def mess_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, 
     h = ctypes.c_void_p()
     _check(lib().mess_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), ctypes.byref(h)), "mess_scf_create")
     return Scf(h, basis)
+
+
+def mess_dmin_step(scf: Scf, lr=0.1, stream=None):
+    """One direct-minimisation (Adam) step; returns (energy, max |dE/dZ|)."""
+    e, g = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mess_dmin_step(scf.handle, float(lr), ctypes.byref(e), ctypes.byref(g), _stream(stream)),
+           "mess_dmin_step")
+    return e.value, g.value
+
+
+def mess_dmin_eval(scf: Scf, Z, G=None, stream=None):
+    """E(Z) (returned) and dE/dZ into G (device N x N, optional)."""
+    e = ctypes.c_double()
+    _check(lib().mess_dmin_eval(scf.handle, _ptr(Z), ctypes.byref(e), _ptr(G), _stream(stream)), "mess_dmin_eval")
+    return e.value
+
+
+def mess_dmin_trial(scf: Scf, Z, stream=None):
+    _check(lib().mess_dmin_trial(scf.handle, _ptr(Z), _stream(stream)), "mess_dmin_trial")
 
 
 def mess_scf_step(scf: Scf, stream=None):
