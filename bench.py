@@ -200,16 +200,33 @@ def lda_block(mess, mol, a, torch):
             "scf_s": t2 - t1, "scf_iterations": it, "scf_converged": bool(conv), "energy_hartree": e}
 
 
-def batch_block(mess, a, torch, jk_mode=0):
+def oracle_check(mols, energies, converged, count=8, max_nbf=40):
+    """|E - E_oracle| on a sample of converged molecules small enough for the
+    dense oracle (the smallest ones): (checked, within 1e-6 Ha, max |dE|)."""
+    from oracle import scf as oscf
+    idx = [m for m in sorted(range(len(mols)), key=lambda m: mols[m].n_bf)
+           if converged[m] and mols[m].n_bf <= max_nbf][:count]
+    worst, ok = 0.0, 0
+    for m in idx:
+        ref = oscf.RHF(mols[m], jk="dense", conv_tol=1e-10, max_iter=200).run()
+        d = float(abs(energies[m] - ref["energy"]))
+        worst = max(worst, d)
+        ok += int(d < 1e-6)
+    return len(idx), ok, worst
+
+
+def batch_block(mess, a, torch, jk_mode=0, prec=0):
     """Batched SCF over many small molecules (seeds 1000...), one HIP graph
     per step, a fixed number of steps; jk_mode 1 stores the integral blocks
-    at set-up and streams them in every step."""
+    at set-up and streams them in every step; prec 1 is the mixed-precision
+    batch.  Converged molecules count toward molecules/s in proportion to
+    the share of an oracle-checked sample within 1e-6 Ha."""
     from mess_inputs import generators as G
     mols = G.batch_of_molecules(a.batch_molecules)
     t0 = time.perf_counter()
     B = mess.mess_batch_create(mols)
     bs = mess.mess_batch_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, use_graph=True,
-                                    jk_mode=jk_mode)
+                                    jk_mode=jk_mode, prec=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     conv_hist = []
@@ -221,11 +238,65 @@ def batch_block(mess, a, torch, jk_mode=0):
     t2 = time.perf_counter()
     q = sum(mess.mess_work_stats(B, a.tau, c)[0] for c in range(21))
     bs.close()
+    nchk, nok, worst = oracle_check(mols, st["energy"], st["converged"]) if not a.no_oracle_check else (0, 0, None)
+    share = nok / nchk if nchk else 1.0
     return {"molecules": len(mols), "n_bf_total": int(B.nbf), "packed_doubles": int(B.packed),
             "shell_quartets_per_step": q, "setup_s": t1 - t0, "steps": a.batch_steps,
             "ms_per_step": (t2 - t1) / a.batch_steps * 1e3, "converged_after_steps": conv_hist,
-            "converged_molecules_per_s": conv_hist[-1] / (t2 - t0),
+            "oracle_checked": nchk, "oracle_within_1e-6": nok, "oracle_max_abs_de": worst,
+            "converged_molecules_per_s": conv_hist[-1] * share / (t2 - t0),
             "shell_quartets_per_s": q * a.batch_steps / (t2 - t1)}
+
+
+def dmin_block(mess, a, torch):
+    """Direct minimisation (QR + Adam, lr 0.1) of the 6-atom s/p molecule:
+    time per step and steps until the energy is within 1e-6 Ha of the SCF's."""
+    from mess_inputs import generators as G
+    mol = G.random_small_molecule(1)
+    B = mess.basis_from_molecule(mol)
+    sc = mess.mess_scf_create(B, schwarz_tol=a.tau, conv_tol=1e-11, diis_size=8)
+    for _ in range(100):
+        e_scf, de, r, c = mess.mess_scf_step(sc)
+        if c:
+            break
+    st = mess.mess_scf_create(B, schwarz_tol=a.tau, conv_tol=0.0, diis_size=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reached, n = None, 0
+    for n in range(1, 801):
+        e, g = mess.mess_dmin_step(st, lr=0.1)
+        if reached is None and abs(e - e_scf) < 1e-6:
+            reached = n
+            break
+    t1 = time.perf_counter()
+    return {"workload": mol.name, "n_bf": mol.n_bf, "steps_to_1e-6": reached, "ms_per_step": (t1 - t0) / n * 1e3,
+            "energy_hartree": e, "scf_energy_hartree": e_scf}
+
+
+def scan_block(mess, a, torch):
+    """Conformer scan: 64 geometries of a 19-atom molecule (one bond
+    stretched) as one batch; SCF of every conformer to |dE| < conv."""
+    from mess_inputs import generators as G
+    base = G.batched_molecule(1001)
+    d = base.xyz[1] - base.xyz[0]
+    mols = G.conformer_scan(base, 1, d, np.linspace(-0.3, 1.5, 64))
+    t0 = time.perf_counter()
+    B = mess.mess_batch_create(mols)
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=a.tau, conv_tol=a.conv, diis_size=8, use_graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    steps = 0
+    for steps in range(1, 61):
+        mess.mess_batch_scf_step(bs)
+        st = mess.mess_batch_scf_status(bs)
+        if st["n_converged"] == len(mols):
+            break
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    bs.close()
+    return {"conformers": len(mols), "n_bf_each": base.n_bf, "steps": steps, "converged": st["n_converged"],
+            "setup_s": t1 - t0, "scf_s": t2 - t1, "conformers_per_s": st["n_converged"] / (t2 - t0),
+            "energy_min_hartree": float(np.min(st["energy"])), "energy_max_hartree": float(np.max(st["energy"]))}
 
 
 def main():
@@ -246,6 +317,9 @@ def main():
     ap.add_argument("--batch-molecules", type=int, default=1024)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel forms")
+    ap.add_argument("--no-dmin", action="store_true", help="skip the direct-minimisation measurement")
+    ap.add_argument("--no-scan", action="store_true", help="skip the conformer scan")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of batch energies")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -391,13 +465,22 @@ def main():
     if not a.no_batch:
         line["batch"] = batch_block(mess, a, torch)
         log(f"batch: {line['batch']}")
+        if not a.no_fp32:
+            line["batch_fp32_mixed"] = batch_block(mess, a, torch, prec=mess.MESS_FP32)
+            log(f"batch (mixed precision): {line['batch_fp32_mixed']}")
         if not a.no_stored:
             line["batch_stored_jk"] = batch_block(mess, a, torch, jk_mode=mess.MESS_JK_STORED)
             log(f"batch (stored J/K): {line['batch_stored_jk']}")
+    if not a.no_scan:
+        line["conformer_scan"] = scan_block(mess, a, torch)
+        log(f"scan: {line['conformer_scan']}")
+    if not a.no_dmin:
+        line["direct_minimisation"] = dmin_block(mess, a, torch)
+        log(f"dmin: {line['direct_minimisation']}")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a quartet sample")
         line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 
 
 if __name__ == "__main__":

@@ -267,6 +267,27 @@ def single_gaussian_system(kind: str, alpha: float, bond: float = 1.4) -> Molecu
     return _assemble(Z, xyz, shells, f"{kind}/alpha{alpha}")
 
 
+def conformer_scan(base: Molecule, atom: int, direction, displacements) -> list:
+    """Copies of a molecule with one atom moved along a direction (bohr),
+    one per displacement: the conformations of a bond scan."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    out = []
+    for k, t in enumerate(displacements):
+        m = base.copy()
+        m.xyz = np.array(base.xyz, dtype=np.float64)
+        m.xyz[atom] = m.xyz[atom] + t * d
+        m.name = f"{base.name}/scan{k}"
+        out.append(m)
+    return out
+
+
+def h2_scan(alpha: float = 0.5, count: int = 64, r_min: float = 0.6, r_max: float = 10.0) -> list:
+    """Minimal-basis H2 (one s Gaussian per atom) at count bond lengths
+    spaced evenly in [r_min, r_max] bohr."""
+    return [single_gaussian_system("H2", alpha, bond=float(r)) for r in np.linspace(r_min, r_max, count)]
+
+
 WORKLOADS = {
     "hco6_sp": random_small_molecule,
     "water60_spd": water_cluster,

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
+import closed_forms as CF  # noqa: E402
 import quadrature as Q  # noqa: E402
 
 from mess_inputs import generators as G  # noqa: E402
@@ -151,17 +152,7 @@ def test_s_primitive_closed_forms():
 # ------------------------------------------------------------- ERIs
 
 def _ss_closed_form(a, A, b, B, c, C, d, D):
-    """(ss|ss) of normalised s primitives: Gaussian product theorem + F_0."""
-    A, B, C, D = map(np.asarray, (A, B, C, D))
-    p, q = a + b, c + d
-    P, Qc = (a * A + b * B) / p, (c * C + d * D) / q
-    Kab = math.exp(-a * b / p * np.sum((A - B) ** 2))
-    Kcd = math.exp(-c * d / q * np.sum((C - D) ** 2))
-    rho = p * q / (p + q)
-    T = rho * np.sum((P - Qc) ** 2)
-    F0 = 1.0 if T == 0 else 0.5 * math.sqrt(math.pi / T) * math.erf(math.sqrt(T))
-    norm = np.prod([(2 * x / math.pi) ** 0.75 for x in (a, b, c, d)])
-    return 2 * math.pi ** 2.5 / (p * q * math.sqrt(p + q)) * Kab * Kcd * F0 * norm
+    return CF.ss_eri(a, A, b, B, c, C, d, D)
 
 
 def test_ssss_analytic():
@@ -265,20 +256,10 @@ def test_he_single_gaussian_rhf():
 
 def test_h2_minimal_basis_closed_form():
     for alpha, R in ((0.5, 1.4), (0.27, 2.0), (1.1, 0.9)):
-        A, B = np.zeros(3), np.array([0.0, 0.0, R])
-        S12 = math.exp(-alpha * R * R / 2)
-        mu = alpha / 2
-        T11, T12 = 1.5 * alpha, mu * (3 - 2 * mu * R * R) * S12
-        F0 = lambda T: 1.0 if T == 0 else 0.5 * math.sqrt(math.pi / T) * math.erf(math.sqrt(T))  # noqa
-        c = 2 * math.sqrt(2 * alpha / math.pi)
-        V11 = -c * (1 + F0(2 * alpha * R * R))
-        V12 = -c * S12 * 2 * F0(2 * alpha * (R / 2) ** 2)
-        h11, h12 = T11 + V11, T12 + V12
-        g = lambda P, Qq, Rr, Ss: _ss_closed_form(alpha, P, alpha, Qq, alpha, Rr, alpha, Ss)  # noqa
-        J = (g(A, A, A, A) + g(A, A, B, B) + 2 * g(A, B, A, B) + 4 * g(A, A, A, B)) / (2 * (1 + S12) ** 2)
-        E_ref = 2 * (h11 + h12) / (1 + S12) + J + 1.0 / R
+        E_ref = CF.h2_minimal_energy(alpha, R)
         r = scf.RHF(G.single_gaussian_system("H2", alpha, bond=R)).run()
         assert abs(r["energy"] - E_ref) < 1e-13, (alpha, R, r["energy"], E_ref)
+    assert abs(CF.h2_minimal_energy(0.5, 1.4) - (-0.9552136651016611)) < 1e-15
 
 
 def test_converged_scf_invariants_and_invariance():
