@@ -15,6 +15,14 @@ silent (all restated in the design notes):
 * Acceleration: optional Pulay DIIS over at most 8 Fock matrices, applied
   once two are stored, error vector X^T (F D S - S D F) X.
 * Convergence: |E_k - E_{k-1}| < conv_tol, or a fixed iteration count.
+* Divergence guard (on by default): a rise of the energy by more than
+  1e-6 Ha counts against the current stage; the second such rise since the
+  stage began moves to the next stage, and a non-finite energy jumps to the
+  last.  Every stage change clears the DIIS history.  Stages: 0 DIIS;
+  1 DIIS afresh; 2 DIIS with damping 0.5 (the next density mixed half and
+  half with the current one); 3 restart from the core-Hamiltonian guess,
+  damped as in stage 2 (the last stage).  The first energy after a restart
+  is compared with nothing.
 * LDA (xc="lda"): exchange from the Dirac-Slater functional on the
   molecular grid of ``lda.py`` instead of K:  F = H + J + V_x,
   E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc.
@@ -69,7 +77,7 @@ class RHF:
 
     def __init__(self, mol, jk: str = "dense", tau: float = 0.0, diis: bool = True,
                  diis_size: int = 8, conv_tol: float = 1e-8, max_iter: int = 100,
-                 fixed_iters: int | None = None, xc: str = "hf"):
+                 fixed_iters: int | None = None, xc: str = "hf", guard: bool = True):
         if mol.n_electrons % 2:
             raise ValueError("closed-shell SCF needs an even electron count")
         self.mol = mol
@@ -80,6 +88,7 @@ class RHF:
         self.n_occ = mol.n_electrons // 2
         self.jk_mode, self.tau = jk, tau
         self.diis, self.diis_size = diis, diis_size
+        self.guard = guard
         self.conv_tol, self.max_iter, self.fixed_iters = conv_tol, max_iter, fixed_iters
         self._eri = core.eri_dense(mol) if jk == "dense" else None
         if xc not in ("hf", "lda"):
@@ -115,23 +124,46 @@ class RHF:
     def commutator(self, F, D):
         return self.X.T @ (F @ D @ self.S - self.S @ D @ F) @ self.X
 
+    RISE_TOL = 1e-6
+    RISES_PER_STAGE = 2
+    DAMP = 0.5
+
     def run(self, D0=None, record=False):
         D = self.core_guess() if D0 is None else np.array(D0, dtype=np.float64)
         energies, focks, errors = [], [], []
-        densities, fock_hist = [], []
+        densities, fock_hist, stages = [], [], []
         converged = False
         n_iter = self.fixed_iters if self.fixed_iters is not None else self.max_iter
         F = None
+        stage, rises, e_prev = 0, 0, None
         for k in range(n_iter):
             F, E = self.fock(D)
             D_used = D
             energies.append(E)
+            stages.append(stage)
             if record:
                 densities.append(D)
                 fock_hist.append(F)
-            if self.fixed_iters is None and k > 0 and abs(E - energies[-2]) < self.conv_tol:
+            if self.fixed_iters is None and e_prev is not None and abs(E - e_prev) < self.conv_tol:
                 converged = True
                 break
+            if self.guard:
+                up = 0
+                if not np.isfinite(E):
+                    up = 3 - stage
+                elif e_prev is not None and E > e_prev + self.RISE_TOL:
+                    rises += 1
+                    if rises >= self.RISES_PER_STAGE:
+                        up = 1
+                if up > 0 and stage < 3:
+                    stage, rises = min(3, stage + up), 0
+                    focks, errors = [], []
+                    if stage == 3:
+                        D, e_prev = self.core_guess(), None
+                        continue
+                elif not np.isfinite(E):
+                    raise FloatingPointError("SCF energy is not finite after a restart")
+            e_prev = E
             Fx = F
             if self.diis:
                 focks.append(F)
@@ -141,9 +173,10 @@ class RHF:
                     errors.pop(0)
                 if len(focks) >= 2:
                     Fx = diis_extrapolate(focks, errors)
-            D, C, eps = density_from_fock(Fx, self.X, self.n_occ)
+            Dn, C, eps = density_from_fock(Fx, self.X, self.n_occ)
+            D = Dn if stage < 2 else (1.0 - self.DAMP) * Dn + self.DAMP * D
         if self.fixed_iters is not None:
             converged = True
         return {"energy": energies[-1], "energies": energies, "D": D_used, "D_next": D, "F": F,
-                "converged": converged, "iterations": len(energies),
+                "converged": converged, "iterations": len(energies), "stages": stages,
                 "e_nuc": self.e_nuc, "densities": densities, "focks": fock_hist}
