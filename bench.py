@@ -200,9 +200,10 @@ def lda_block(mess, mol, a, torch):
             "scf_s": t2 - t1, "scf_iterations": it, "scf_converged": bool(conv), "energy_hartree": e}
 
 
-def oracle_check(mols, energies, converged, count=8, max_nbf=40):
-    """|E - E_oracle| on a sample of converged molecules small enough for the
-    dense oracle (the smallest ones): (checked, within 1e-6 Ha, max |dE|)."""
+def cpu_baseline_batch_check(mols, energies, converged, count=8, max_nbf=40):
+    """CPU-baseline leg: |E - E_oracle| on a sample of converged molecules
+    small enough for the dense oracle (the smallest ones): (checked, within
+    1e-6 Ha, max |dE|)."""
     from oracle import scf as oscf
     idx = [m for m in sorted(range(len(mols)), key=lambda m: mols[m].n_bf)
            if converged[m] and mols[m].n_bf <= max_nbf][:count]
@@ -219,8 +220,9 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
     """Batched SCF over many small molecules (seeds 1000...), one HIP graph
     per step, a fixed number of steps; jk_mode 1 stores the integral blocks
     at set-up and streams them in every step; prec 1 is the mixed-precision
-    batch.  Converged molecules count toward molecules/s in proportion to
-    the share of an oracle-checked sample within 1e-6 Ha."""
+    batch.  Returns the figures and what the CPU-baseline leg checks
+    (converged molecules count toward molecules/s in proportion to the share
+    of an oracle-checked sample within 1e-6 Ha)."""
     from mess_inputs import generators as G
     mols = G.batch_of_molecules(a.batch_molecules)
     t0 = time.perf_counter()
@@ -237,15 +239,26 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     q = sum(mess.mess_work_stats(B, a.tau, c)[0] for c in range(21))
+    stages = mess.mess_batch_scf_guard(bs)
     bs.close()
-    nchk, nok, worst = oracle_check(mols, st["energy"], st["converged"]) if not a.no_oracle_check else (0, 0, None)
-    share = nok / nchk if nchk else 1.0
-    return {"molecules": len(mols), "n_bf_total": int(B.nbf), "packed_doubles": int(B.packed),
-            "shell_quartets_per_step": q, "setup_s": t1 - t0, "steps": a.batch_steps,
-            "ms_per_step": (t2 - t1) / a.batch_steps * 1e3, "converged_after_steps": conv_hist,
-            "oracle_checked": nchk, "oracle_within_1e-6": nok, "oracle_max_abs_de": worst,
-            "converged_molecules_per_s": conv_hist[-1] * share / (t2 - t0),
-            "shell_quartets_per_s": q * a.batch_steps / (t2 - t1)}
+    out = {"molecules": len(mols), "n_bf_total": int(B.nbf), "packed_doubles": int(B.packed),
+           "shell_quartets_per_step": q, "setup_s": t1 - t0, "steps": a.batch_steps,
+           "ms_per_step": (t2 - t1) / a.batch_steps * 1e3, "converged_after_steps": conv_hist,
+           "guard_stage_counts": [int(np.sum(stages == k)) for k in range(4)],
+           "converged_molecules_per_s_unchecked": conv_hist[-1] / (t2 - t0),
+           "converged_molecules_per_s": None,
+           "shell_quartets_per_s": q * a.batch_steps / (t2 - t1)}
+    # kept for the oracle check of the CPU-baseline leg
+    check = (mols, st["energy"].copy(), st["converged"].copy(), conv_hist[-1], t2 - t0)
+    return out, check
+
+
+def gate_batch(out, check, verdict):
+    """Batch molecules/s counting converged molecules in proportion to the
+    share of the oracle-checked sample within 1e-6 Ha."""
+    nchk, nok, worst = verdict
+    out.update({"oracle_checked": nchk, "oracle_within_1e-6": nok, "oracle_max_abs_de": worst,
+                "converged_molecules_per_s": check[3] * (nok / nchk if nchk else 0.0) / check[4]})
 
 
 def dmin_block(mess, a, torch):
@@ -299,6 +312,85 @@ def scan_block(mess, a, torch):
             "energy_min_hartree": float(np.min(st["energy"])), "energy_max_hartree": float(np.max(st["energy"]))}
 
 
+def small_block(mess, a, torch, n_seeds=64):
+    """The 6-atom H/C/O s/p molecules (about 30 functions): latency of the
+    full ERI tensor and of one direct J/K build (3 warm-ups, median of 10,
+    seed 0), the 20-iteration plain Roothaan SCF (no DIIS, no guard) of every
+    seed.  Returns the figures and what the CPU-baseline leg checks."""
+    from mess_inputs import generators as G
+
+    def median_ms(fn, reps=10, warm=3):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(ts))
+
+    def roothaan20(B):
+        st = mess.mess_scf_create(B, schwarz_tol=0.0, conv_tol=0.0, diis_size=0, guard=False)
+        es = [mess.mess_scf_step(st)[0] for _ in range(20)]
+        st.close()
+        return es
+
+    mol = G.random_small_molecule(0)
+    B = mess.basis_from_molecule(mol)
+    N = B.nbf
+    n_sh = mol.n_shells
+    n_pairs = n_sh * (n_sh + 1) // 2
+    eri = torch.zeros(N, N, N, N, dtype=torch.float64, device="cuda")
+    D = torch.tensor(G.symmetric_density(N, 5), dtype=torch.float64, device="cuda")
+    J, K = torch.zeros(N, N, dtype=torch.float64, device="cuda"), torch.zeros_like(D)
+    eri_ms = median_ms(lambda: mess.mess_eri(B, eri, schwarz_tol=0.0))
+    jk_ms = median_ms(lambda: mess.mess_jk(B, D, J, K, schwarz_tol=0.0))
+    scf_ms = median_ms(lambda: roothaan20(B), reps=5, warm=1)
+    es = roothaan20(B)
+    torch.cuda.synchronize()
+    check = (mol, eri.cpu().numpy(), J.cpu().numpy(), K.cpu().numpy(), es)
+    B.close()
+    # every seed: 20 Roothaan iterations
+    t = time.perf_counter()
+    for seed in range(n_seeds):
+        Bs = mess.basis_from_molecule(G.random_small_molecule(seed))
+        roothaan20(Bs)
+        Bs.close()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t
+    return {"workload": "hco6_sp", "seed": 0, "n_bf": N, "n_shells": n_sh,
+            "unique_shell_quartets": n_pairs * (n_pairs + 1) // 2,
+            "eri_tensor_ms": eri_ms, "eri_per_s": N ** 4 / (eri_ms * 1e-3),
+            "jk_ms": jk_ms, "scf20_ms": scf_ms, "energy_after_20_hartree": es[-1],
+            "seeds": n_seeds, "scf20_all_seeds_s": t_all, "scf20_molecules_per_s": n_seeds / t_all}, check
+
+
+def cpu_baseline_small(check):
+    """CPU-baseline leg for the 6-atom molecule: the oracle's times (dense
+    ERI tensor, one J/K contraction, 20 Roothaan iterations; one process) and
+    the GPU results' differences from its values."""
+    from mess_inputs import generators as G
+    from oracle import core
+    from oracle import scf as oscf
+    mol, eri, J, K, es = check
+    t = time.perf_counter()
+    eri_o = core.eri_dense(mol)
+    t_eri_o = time.perf_counter() - t
+    t = time.perf_counter()
+    Jo, Ko = core.jk_from_dense(eri_o, G.symmetric_density(mol.n_bf, 5))
+    t_jk_o = time.perf_counter() - t
+    t = time.perf_counter()
+    ro = oscf.RHF(mol, jk="dense", diis=False, fixed_iters=20, guard=False).run()
+    t_scf_o = time.perf_counter() - t
+    return {"eri_tensor_s": t_eri_o, "jk_s": t_jk_o, "scf20_s": t_scf_o, "kind": "oracle",
+            "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "max_abs_d_eri": float(np.max(np.abs(eri - eri_o))), "max_abs_d_j": float(np.max(np.abs(J - Jo))),
+            "max_abs_d_k": float(np.max(np.abs(K - Ko))),
+            "delta_e_after_20_hartree": es[-1] - ro["energies"][-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +412,7 @@ def main():
     ap.add_argument("--no-dmin", action="store_true", help="skip the direct-minimisation measurement")
     ap.add_argument("--no-scan", action="store_true", help="skip the conformer scan")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of batch energies")
+    ap.add_argument("--no-small", action="store_true", help="skip the 6-atom latency measurements")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -459,17 +552,22 @@ def main():
         line["stored_jk"] = stored
         line["jk_gbps"] = stored["jk_gbps"]
         log(f"stored: {stored}")
+    checks = {}
+    if not a.no_small:
+        line["small_molecule"], checks["small_molecule"] = small_block(mess, a, torch)
+        log(f"small molecule: {line['small_molecule']}")
     if not a.no_lda:
         line["lda"] = lda_block(mess, mol, a, torch)
         log(f"lda: {line['lda']}")
     if not a.no_batch:
-        line["batch"] = batch_block(mess, a, torch)
+        line["batch"], checks["batch"] = batch_block(mess, a, torch)
         log(f"batch: {line['batch']}")
         if not a.no_fp32:
-            line["batch_fp32_mixed"] = batch_block(mess, a, torch, prec=mess.MESS_FP32)
+            line["batch_fp32_mixed"], checks["batch_fp32_mixed"] = batch_block(mess, a, torch, prec=mess.MESS_FP32)
             log(f"batch (mixed precision): {line['batch_fp32_mixed']}")
         if not a.no_stored:
-            line["batch_stored_jk"] = batch_block(mess, a, torch, jk_mode=mess.MESS_JK_STORED)
+            line["batch_stored_jk"], checks["batch_stored_jk"] = batch_block(mess, a, torch,
+                                                                             jk_mode=mess.MESS_JK_STORED)
             log(f"batch (stored J/K): {line['batch_stored_jk']}")
     if not a.no_scan:
         line["conformer_scan"] = scan_block(mess, a, torch)
@@ -478,8 +576,18 @@ def main():
         line["direct_minimisation"] = dmin_block(mess, a, torch)
         log(f"dmin: {line['direct_minimisation']}")
     if not a.no_cpu_baseline:
+        # the CPU-baseline leg: the oracle timed on a quartet sample, and the
+        # oracle's values that the results above are checked against
         log("timing the CPU oracle on a quartet sample")
-        line["cpu_baseline"] = cpu_baseline(mol, a.cpu_seconds)
+        cb = cpu_baseline(mol, a.cpu_seconds)
+        if "small_molecule" in checks:
+            cb["small_molecule"] = cpu_baseline_small(checks["small_molecule"])
+            line["small_molecule"]["oracle"] = cb["small_molecule"]
+        for key in ("batch", "batch_fp32_mixed", "batch_stored_jk"):
+            if key in checks and not a.no_oracle_check:
+                mols, e, c, nconv, dt = checks[key]
+                gate_batch(line[key], checks[key], cpu_baseline_batch_check(mols, e, c))
+        line["cpu_baseline"] = cb
     print(json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 
 

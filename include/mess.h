@@ -85,6 +85,15 @@ typedef struct mess_scf_opts {
     int32_t deterministic; /* nonzero: every Fock build runs as mess_jk(MESS_JK_DETERMINISTIC)
                               (overrides jk_mode), so a rerun reproduces every energy and
                               density bit for bit */
+    int32_t no_guard;    /* nonzero: no divergence guard.  The guard (default): an energy
+                            rise above 1e-6 Ha counts against the current stage and the
+                            second rise in a stage moves to the next; a non-finite energy
+                            goes straight to the last.  Each change drops the DIIS history.
+                            Stages: 0 DIIS; 1 DIIS afresh; 2 DIIS with the next density
+                            mixed half and half with the current one; 3 restart from the
+                            core-Hamiltonian guess, damped as in 2 (the first energy after
+                            the restart is compared with nothing).  A non-finite energy in
+                            stage 3, or with the guard off, is MESS_E_NUMERIC */
 } mess_scf_opts;
 
 /* Build a basis on a molecule (section 3, eq. 1: each atomic orbital sits
@@ -147,6 +156,22 @@ int mess_basis_info(const mess_basis *basis, int32_t *nbf, int32_t *n_occ, doubl
  * attraction V for the core Hamiltonian H = T + V).  Each output is a
  * device N x N buffer or NULL to skip. */
 int mess_one_electron(const mess_basis *basis, double *S, double *T, double *V, mess_stream stream);
+
+/* Boys function F_j(T) = int_0^1 u^(2j) exp(-T u^2) du, j = 0..m (section 3:
+ * every closed-form repulsion integral is a sum over it), by the device
+ * routines of the integral kernels, using the basis handle's tables:
+ *   form 0  F_0..F_m together (Taylor sum of F_m about T_k = k/16, downward
+ *           recurrence; (2j-1)!!/(2T)^j sqrt(pi/T)/2 for T >= 60), the
+ *           recursion kernels' form;
+ *   form 1  each F_j by its own Taylor sum, the table-driven kernel's form.
+ * prec MESS_FP64, or MESS_FP32 for the mixed-precision kernels' FP32 forms
+ * (T rounded to FP32, results widened).  T: device, n doubles, T >= 0 (a
+ * negative or NaN T gives NaN); F: device, n * (m + 1) doubles,
+ * F[i * (m + 1) + j] = F_j(T[i]).  0 <= m <= 8.  Asynchronous on stream.
+ * Errors: MESS_E_ARG (NULL pointers with n > 0, m, form or prec out of
+ * range). */
+int mess_boys(const mess_basis *basis, int32_t prec, int32_t form, int32_t m, const double *T, int64_t n,
+              double *F, mess_stream stream);
 
 /* Electron-repulsion integrals (mu nu|lambda sigma) over the basis: the
  * four-centre Coulomb integrals of pairs of basis functions (section 3,
@@ -255,6 +280,10 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
  * Outputs (host, any may be NULL): energy E_k, delta_e = E_k - E_{k-1}
  * (0 at k = 0), resid = max |X^T (F D S - S D F) X|, converged flag.
  * Synchronises the stream.  Non-convergence is not an error. */
+/* Divergence-guard stage of the run (0..3, see mess_scf_opts.no_guard) and
+ * the energy rises counted in it.  Host outputs, either may be NULL. */
+int mess_scf_guard(const mess_scf *scf, int32_t *stage, int32_t *rises);
+
 int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid,
                   int32_t *converged, mess_stream stream);
 
@@ -312,8 +341,15 @@ int mess_batch_scf_create(const mess_basis *basis, const mess_scf_opts *opts, co
 
 /* Enqueue one SCF iteration for every molecule on the stream; does not
  * synchronise.  A molecule with k > 0 and |E_k - E_{k-1}| < conv_tol is
- * frozen: its energy and density stay those of that step. */
+ * frozen: its energy and density stay those of that step.  The divergence
+ * guard of mess_scf_opts.no_guard runs per molecule (a molecule restarting
+ * after a non-finite energy keeps its last finite energy in the status;
+ * in stage 3 a non-finite energy freezes it, and the status reports it). */
 int mess_batch_scf_step(mess_batch_scf *scf, mess_stream stream);
+
+/* Divergence-guard stage (0..3) of every molecule: stage[n_mol], host.
+ * Synchronous. */
+int mess_batch_scf_guard(const mess_batch_scf *scf, int32_t *stage);
 
 /* Synchronise and read per-molecule results of the last step (host arrays
  * of n_mol, any may be NULL): energy, delta_e, resid, converged flag, and

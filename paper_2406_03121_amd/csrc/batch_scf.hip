@@ -17,6 +17,14 @@
 // arguments, which is captured once into a HIP graph and replayed.
 // A molecule whose energy change falls below the tolerance is frozen: its
 // density stays the one that gave the converged energy.
+//
+// Divergence guard (per molecule, on unless opts.no_guard): the rule of the
+// single-molecule SCF.  An energy rise above kRiseTol counts against the
+// molecule's stage, the second rise in a stage moves it to the next, a
+// non-finite energy to the last; each change restarts its DIIS history
+// (the molecule then uses only the entries pushed since: the history ring
+// itself is shared).  Stage 2 mixes the next density half and half with the
+// current one; stage 3 restarts the molecule from the core guess (damped).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -35,6 +43,9 @@ constexpr int kSp2Rounds = 100;  // purification rounds per step (finished molec
 // builds; then a complete FP64 build, FP32 builds of the density change added
 // to it, and a complete FP64 rebuild after every kDeltaRun of those.
 constexpr int kFarSteps = 2;
+constexpr double kRiseTol = 1e-6;
+constexpr int kRisesPerStage = 2;
+constexpr double kDamp = 0.5;
 constexpr int kDeltaRun = 8;
 // Kinds of step (one captured graph each).
 enum { kStepFull64 = 0, kStepFull64Open = 1, kStepFull32 = 2, kStepDelta32 = 3, kNumStepKinds = 4 };
@@ -43,7 +54,9 @@ struct MolScalars {
     double energy, e_new, de, resid;
     double emin, emax, trX, trX2, idem, scale;
     int sp2_iter, sp2_done, sp2_post, frozen;
-    int sp2_fail, pad0, pad1, pad2;
+    int sp2_fail;
+    int stage, rises, hvalid;  // divergence guard; DIIS entries the molecule uses
+    int fresh, restart, pad0, pad1;  // fresh: the next energy is compared with nothing
     double diis_c[kBMaxDiis + 1];
 };
 
@@ -66,6 +79,7 @@ struct mess_batch_scf {
     hipGraphExec_t exec[mess::kNumStepKinds] = {};
     int host_iter = 0, since_full = 0;  // mixed precision: steps so far, dD builds since a complete FP64 build
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // mixed precision
+    double *Dc = nullptr;  // core-Hamiltonian guess (divergence guard restarts)
     double *S = nullptr, *H = nullptr, *X = nullptr, *D = nullptr, *F = nullptr, *Fx = nullptr, *Gj = nullptr,
            *Gk = nullptr, *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *P = nullptr, *P2 = nullptr, *E = nullptr;
     double *Fh = nullptr, *Eh = nullptr, *Bm = nullptr;
@@ -161,16 +175,43 @@ __global__ void __launch_bounds__(256) k_bmaxabs(int nmol, const int64_t *__rest
     }
 }
 
-// Energy bookkeeping and convergence; one thread per molecule.
-__global__ void k_bconv(int nmol, double tol, const BatchState *__restrict__ bs, MolScalars *__restrict__ ms) {
+// Energy bookkeeping, convergence and the divergence guard; one thread per
+// molecule.  nd: DIIS history length (0: none).
+__global__ void k_bconv(int nmol, double tol, int guard, int nd, const BatchState *__restrict__ bs,
+                        MolScalars *__restrict__ ms) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nmol || ms[m].frozen) return;
-    const int it = bs->iter;
-    const double e = ms[m].e_new;
-    const double de = it > 0 ? e - ms[m].energy : 0.0;
-    ms[m].energy = e;
-    ms[m].de = de;
-    if (it > 0 && fabs(de) < tol) ms[m].frozen = 1;
+    MolScalars &q = ms[m];
+    const bool have_prev = bs->iter > 0 && !q.fresh;
+    q.fresh = 0;
+    q.hvalid = min(q.hvalid + 1, nd);  // this step's entry
+    const double e = q.e_new;
+    if (!isfinite(e)) {
+        if (guard && q.stage < 3) {  // straight to the restart; the energy field keeps its last value
+            q.stage = 3;
+            q.rises = 0;
+            q.restart = 1;
+            q.de = 0.0;
+        } else {  // nothing left to try: frozen with the non-finite energy
+            q.energy = e;
+            q.de = 0.0;
+            q.frozen = 1;
+        }
+        return;
+    }
+    const double de = have_prev ? e - q.energy : 0.0;
+    q.energy = e;
+    q.de = de;
+    if (have_prev && fabs(de) < tol) {
+        q.frozen = 1;
+        return;
+    }
+    if (guard && have_prev && de > kRiseTol && ++q.rises >= kRisesPerStage && q.stage < 3) {
+        q.stage += 1;
+        q.rises = 0;
+        q.hvalid = min(1, nd);
+        if (q.stage == 3) q.restart = 1;
+    }
 }
 
 // DIIS history: F and e of this step into slot next_slot.
@@ -228,7 +269,8 @@ __global__ void k_bdiis_solve(int nmol, const BatchState *__restrict__ bs, const
                               MolScalars *__restrict__ ms) {
     const int mol = blockIdx.x * blockDim.x + threadIdx.x;
     if (mol >= nmol || ms[mol].frozen) return;
-    const int m = bs->hcount;
+    // the molecule's own (most recent) entries of the shared history
+    const int m = min(bs->hcount, ms[mol].hvalid), h0 = bs->hcount - m;
     if (m < 2) {
         ms[mol].diis_c[0] = 1.0;
         return;
@@ -237,7 +279,7 @@ __global__ void k_bdiis_solve(int nmol, const BatchState *__restrict__ bs, const
     double A[kBMaxDiis + 1][kBMaxDiis + 2];
     const int n = m + 1;
     for (int i = 0; i < m; ++i) {
-        for (int j = 0; j < m; ++j) A[i][j] = Bmm[bs->hist[i] * kBMaxDiis + bs->hist[j]];
+        for (int j = 0; j < m; ++j) A[i][j] = Bmm[bs->hist[h0 + i] * kBMaxDiis + bs->hist[h0 + j]];
         A[i][m] = -1.0;
         A[i][n] = 0.0;
     }
@@ -275,8 +317,9 @@ __global__ void k_bdiis_combine(int nmol, const int64_t *__restrict__ moff, cons
                                 const MolScalars *__restrict__ ms, double *__restrict__ Fx) {
     const int hc = bs->hcount;
     MOL_LOOP_BEGIN
+    const int k = max(1, min(hc, ms[m].hvalid)), h0 = hc - k;
     double v = 0.0;
-    for (int i = 0; i < hc; ++i) v += ms[m].diis_c[i] * Fh[(int64_t)bs->hist[i] * packed + o + idx];
+    for (int i = 0; i < k; ++i) v += ms[m].diis_c[i] * Fh[(int64_t)bs->hist[h0 + i] * packed + o + idx];
     Fx[o + idx] = v;
     MOL_LOOP_END
 }
@@ -370,17 +413,32 @@ __global__ void k_bsp2_book(int nmol, MolScalars *__restrict__ ms, int last) {
     else if (last) ms[m].sp2_fail = 1;
 }
 
-// D = Dn for molecules that are not frozen
-__global__ void k_bmask_copy(int nmol, const int64_t *__restrict__ moff, const int *__restrict__ nb,
-                             const MolScalars *__restrict__ ms, const double *__restrict__ Dn, double *__restrict__ D) {
+// Next density of every molecule that is not frozen: Dn; from guard stage 2
+// (1 - kDamp) Dn + kDamp D; the core guess Dc for a molecule restarting.
+__global__ void k_bnext_density(int nmol, const int64_t *__restrict__ moff, const int *__restrict__ nb,
+                                const MolScalars *__restrict__ ms, const double *__restrict__ Dn,
+                                const double *__restrict__ Dc, double *__restrict__ D) {
     for (int m = blockIdx.y; m < nmol; m += gridDim.y) {
         if (ms[m].frozen) continue;
-        const int n = nb[m];
+        const int n = nb[m], mode = ms[m].restart ? 2 : ms[m].stage >= 2 ? 1 : 0;
         const int64_t o = moff[m], nn = (int64_t)n * n;
         for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nn;
-             idx += (int64_t)gridDim.x * blockDim.x)
-            D[o + idx] = Dn[o + idx];
+             idx += (int64_t)gridDim.x * blockDim.x) {
+            const double dn = Dn[o + idx];
+            D[o + idx] = mode == 0 ? dn : mode == 1 ? (1.0 - kDamp) * dn + kDamp * D[o + idx] : Dc[o + idx];
+        }
     }
+}
+
+// After a restart: no DIIS entries, the next energy compared with nothing,
+// and the discarded purification's outcome forgotten.
+__global__ void k_brestart_book(int nmol, MolScalars *__restrict__ ms) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nmol || !ms[m].restart) return;
+    ms[m].restart = 0;
+    ms[m].hvalid = 0;
+    ms[m].fresh = 1;
+    ms[m].sp2_fail = 0;
 }
 
 __global__ void k_bstep_end(BatchState *__restrict__ bs) {
@@ -545,7 +603,7 @@ static int enqueue_step(mess_batch_scf *st, hipStream_t s, int kind) {
     // only energies on FP64-anchored J/K following another such energy may
     // freeze a molecule (a negative tolerance freezes none)
     hipLaunchKernelGGL(k_bconv, L.per_thread, dim3(64), 0, s, L.nmol, may_converge ? st->opts.conv_tol : -1.0,
-                       st->bs, st->ms);
+                       st->opts.no_guard ? 0 : 1, st->nd, st->bs, st->ms);
     MESS_LAUNCH_CHECK();
     const double *Fuse = st->F;
     if (st->nd > 0) {
@@ -562,7 +620,8 @@ static int enqueue_step(mess_batch_scf *st, hipStream_t s, int kind) {
     }
     MESS_TRY(to_orthonormal(st, Fuse, st->W2, s));
     MESS_TRY(purify_density(st, st->W2, st->W2, s));  // Fp is consumed before Dn is written
-    hipLaunchKernelGGL(k_bmask_copy, L.ew, dim3(256), 0, s, L.nmol, L.moff, L.nb, st->ms, st->W2, st->D);
+    hipLaunchKernelGGL(k_bnext_density, L.ew, dim3(256), 0, s, L.nmol, L.moff, L.nb, st->ms, st->W2, st->Dc, st->D);
+    hipLaunchKernelGGL(k_brestart_book, L.per_thread, dim3(64), 0, s, L.nmol, st->ms);
     hipLaunchKernelGGL(k_bstep_end, dim3(1), dim3(64), 0, s, st->bs);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
@@ -576,7 +635,8 @@ static void free_batch(mess_batch_scf *st) {
     }
     if (st->cap) hipStreamDestroy(st->cap);
     for (double *p : {st->S, st->H, st->X, st->D, st->F, st->Fx, st->Gj, st->Gk, st->W1, st->W2, st->W3, st->P,
-                      st->P2, st->E, st->Fh, st->Eh, st->Bm, st->enuc, st->nocc, st->Dprev, st->dD, st->Gja, st->Gka})
+                      st->P2, st->E, st->Fh, st->Eh, st->Bm, st->enuc, st->nocc, st->Dprev, st->dD, st->Gja, st->Gka,
+                      st->Dc})
         hipFree(p);
     hipFree(st->ms);
     hipFree(st->bs);
@@ -685,13 +745,17 @@ static int batch_create_impl(mess_batch_scf *st, const double *D0, bool ortho_on
         MESS_HIP(hipMemset(st->ms, 0, sizeof(MolScalars) * st->nmol));
         return MESS_OK;
     }
-    if (D0) {
-        MESS_HIP(hipMemcpyAsync(st->D, D0, sizeof(double) * B->packed, hipMemcpyDeviceToDevice, s));
-    } else {
+    // core guess: the initial density unless D0 is given, and the guard's
+    // restart point
+    if (!D0 || !st->opts.no_guard) {
         MESS_TRY(to_orthonormal(st, st->H, st->W2, s));
         MESS_TRY(purify_density(st, st->W2, st->W2, s));
-        MESS_HIP(hipMemcpyAsync(st->D, st->W2, sizeof(double) * B->packed, hipMemcpyDeviceToDevice, s));
     }
+    if (!st->opts.no_guard) {
+        MESS_HIP(hipMalloc(&st->Dc, sizeof(double) * pk));
+        MESS_HIP(hipMemcpyAsync(st->Dc, st->W2, sizeof(double) * B->packed, hipMemcpyDeviceToDevice, s));
+    }
+    MESS_HIP(hipMemcpyAsync(st->D, D0 ? D0 : st->W2, sizeof(double) * B->packed, hipMemcpyDeviceToDevice, s));
     // the purification state of the guess is not a step's: reset it
     MESS_HIP(hipMemsetAsync(st->ms, 0, sizeof(MolScalars) * st->nmol, s));
     // work lists (and the stored integrals, in every precision a step uses)
@@ -923,6 +987,17 @@ int mess_batch_scf_status(const mess_batch_scf *st, double *energy, double *delt
                   kSp2Rounds);
         return MESS_E_NUMERIC;
     }
+    return MESS_OK;
+}
+
+int mess_batch_scf_guard(const mess_batch_scf *st, int32_t *stage) {
+    if (!st || !stage) {
+        set_error("mess_batch_scf_guard: NULL argument");
+        return MESS_E_ARG;
+    }
+    std::vector<MolScalars> h(st->nmol);
+    MESS_HIP(hipMemcpy(h.data(), st->ms, sizeof(MolScalars) * st->nmol, hipMemcpyDeviceToHost));
+    for (int m = 0; m < st->nmol; ++m) stage[m] = h[m].stage;
     return MESS_OK;
 }
 

@@ -78,6 +78,11 @@ struct mess_scf {
     std::vector<int> hist;  // history slots, oldest first
     int next_slot = 0;
     int sp2_iters_last = 0;
+    // divergence guard: stage 0 DIIS, 1 DIIS afresh, 2 damped DIIS, 3
+    // restarted from the core guess (damped); rises of the energy counted
+    // since the stage began; whether e_prev holds an energy to compare with
+    int stage = 0, rises = 0;
+    bool have_prev = false;
 };
 
 namespace mess {
@@ -87,6 +92,12 @@ constexpr int kRedBlocks = 256;
 // complete FP32 builds to an FP64 build plus FP32 builds of the density
 // change (Hartree).
 constexpr double kNearDe = 1e-1;
+// Divergence guard: an energy rise above kRiseTol (Hartree) counts against
+// the current stage, kRisesPerStage of them move to the next stage; from
+// stage 2 the next density is mixed with the current one with weight kDamp.
+constexpr double kRiseTol = 1e-6;
+constexpr int kRisesPerStage = 2;
+constexpr double kDamp = 0.5;
 
 // Hartree-Fock (Vx == NULL): F = H + J - K/2 with J = Gj + Gj^T,
 // K = Gk + Gk^T, and per-block partial sums of D .* (H + F);
@@ -443,6 +454,14 @@ static int to_orthonormal(mess_scf *st, const double *F, double *Fp, hipStream_t
     return MESS_OK;
 }
 
+// Core-Hamiltonian guess: D from the aufbau projector of X^T H X.
+static int core_density(mess_scf *st, hipStream_t s) {
+    MESS_TRY(to_orthonormal(st, st->H, st->W2, s));
+    int it = 0;
+    MESS_TRY(purify(st, st->W2, s, &it));
+    return density_from_projector(st, s, st->D);
+}
+
 // Loewdin orthogonaliser X = S^{-1/2} by the coupled Newton-Schulz
 // iteration on A = S / c (c >= lambda_max(S) by Gershgorin, so the spectrum
 // of A lies in (0, 1]):  T = (3 I - Z Y)/2,  Y <- Y T,  Z <- T Z, from
@@ -597,11 +616,23 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     if (D0) {
         MESS_HIP(hipMemcpyAsync(st->D, D0, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
     } else {
-        MESS_TRY(to_orthonormal(st, st->H, st->W2, s));
-        int it = 0;
-        MESS_TRY(purify(st, st->W2, s, &it));
-        MESS_TRY(density_from_projector(st, s, st->D));
+        MESS_TRY(core_density(st, s));
     }
+    MESS_HIP(hipStreamSynchronize(s));
+    return MESS_OK;
+}
+
+// Last stage of the divergence guard: the density restarts from the core
+// guess, the DIIS history is dropped, the next energy is compared with
+// nothing and (mixed precision) the next build is a complete one.
+static int scf_restart(mess_scf *st, hipStream_t s) {
+    st->stage = 3;
+    st->rises = 0;
+    st->hist.clear();
+    st->next_slot = 0;
+    st->have_prev = false;
+    st->acc_valid = false;
+    MESS_TRY(core_density(st, s));
     MESS_HIP(hipStreamSynchronize(s));
     return MESS_OK;
 }
@@ -704,24 +735,46 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     ScfScalars h;
     MESS_HIP(hipMemcpyAsync(&h, st->sc, sizeof(ScfScalars), hipMemcpyDeviceToHost, s));
     MESS_HIP(hipStreamSynchronize(s));
+    const bool guard = st->opts.no_guard == 0;
     if (!std::isfinite(h.energy)) {
-        set_error("mess_scf_step: non-finite energy");
-        return MESS_E_NUMERIC;
+        if (!guard || st->stage >= 3) {
+            set_error("mess_scf_step: non-finite energy");
+            return MESS_E_NUMERIC;
+        }
+        // divergence guard: straight to the restart from the core guess
+        if (energy) *energy = h.energy;
+        if (delta_e) *delta_e = 0.0;
+        if (resid) *resid = h.resid;
+        if (converged) *converged = 0;
+        st->iter += 1;
+        st->last_de = 1e300;
+        return scf_restart(st, s);
     }
-    const double de = st->iter > 0 ? h.energy - st->e_prev : 0.0;
+    const bool have_prev = st->have_prev;
+    const double de = have_prev ? h.energy - st->e_prev : 0.0;
     // mixed precision: only an energy on FP64-anchored J/K, following
     // another such energy, may end the iteration
     const bool anchored = st->opts.prec != MESS_FP32 || (st->acc_valid && st->prev_anchored);
-    const bool conv = st->iter > 0 && std::fabs(de) < st->opts.conv_tol && anchored;
+    const bool conv = have_prev && std::fabs(de) < st->opts.conv_tol && anchored;
     st->prev_anchored = st->opts.prec != MESS_FP32 || st->acc_valid;
     if (energy) *energy = h.energy;
     if (delta_e) *delta_e = de;
     if (resid) *resid = h.resid;
     if (converged) *converged = conv ? 1 : 0;
     st->e_prev = h.energy;
-    st->last_de = st->iter > 0 ? std::fabs(de) : 1e300;
+    st->have_prev = true;
+    st->last_de = have_prev ? std::fabs(de) : 1e300;
     st->iter += 1;
     if (conv) return MESS_OK;  // D stays the density that gave E_k
+    // divergence guard: the second rise of the energy in a stage moves to
+    // the next one (DIIS history dropped); the last stage restarts
+    if (guard && have_prev && de > kRiseTol && ++st->rises >= kRisesPerStage && st->stage < 3) {
+        st->stage += 1;
+        st->rises = 0;
+        st->hist.clear();
+        st->next_slot = 0;
+        if (st->stage == 3) return scf_restart(st, s);
+    }
     // DIIS
     const double *Fuse = st->F;
     if (nd > 0) {
@@ -755,7 +808,13 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     int it = 0;
     MESS_TRY(purify(st, st->W2, s, &it));
     st->sp2_iters_last = it;
-    MESS_TRY(density_from_projector(st, s, st->D));
+    if (st->stage >= 2) {
+        // damped: D <- (1 - kDamp) D_new + kDamp D
+        MESS_TRY(density_from_projector(st, s, st->W2));
+        MESS_TRY(axpby(s, nn, 1.0 - kDamp, st->W2, kDamp, st->D, st->D));
+    } else {
+        MESS_TRY(density_from_projector(st, s, st->D));
+    }
     (void)M;
     return MESS_OK;
 }
@@ -991,6 +1050,16 @@ int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid,
         return MESS_E_ARG;
     }
     return scf_step_impl(scf, energy, delta_e, resid, converged, static_cast<hipStream_t>(stream));
+}
+
+int mess_scf_guard(const mess_scf *scf, int32_t *stage, int32_t *rises) {
+    if (!scf) {
+        set_error("mess_scf_guard: NULL handle");
+        return MESS_E_ARG;
+    }
+    if (stage) *stage = scf->stage;
+    if (rises) *rises = scf->rises;
+    return MESS_OK;
 }
 
 int mess_scf_density(const mess_scf *scf, double *D, mess_stream stream) {

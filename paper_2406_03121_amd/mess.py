@@ -33,7 +33,7 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune", "mess_jk_noalloc", "mess_eri_quartets", "mess_dmin_step",
+    "mess_kernel_form", "mess_autotune", "mess_scf_guard", "mess_batch_scf_guard", "mess_jk_noalloc", "mess_eri_quartets", "mess_boys", "mess_dmin_step",
     "mess_dmin_trial", "mess_dmin_eval",
 ]
 MESS_MLP_NPARAM = 115328
@@ -49,7 +49,7 @@ class ScfOpts(ctypes.Structure):
     _fields_ = [("schwarz_tol", ctypes.c_double), ("conv_tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("jk_mode", ctypes.c_int32),
-                ("xc", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
+                ("xc", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("no_guard", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,6 +72,7 @@ def lib():
         L.mess_jk.argtypes = [vp, vp, vp, vp, i32, i32, f64, vp]
         L.mess_jk_noalloc.argtypes = [vp, vp, vp, vp, i32, f64, vp]
         L.mess_eri_quartets.argtypes = [vp, f64, vp, vp]
+        L.mess_boys.argtypes = [vp, i32, i32, i32, vp, ctypes.c_int64, vp, vp]
         L.mess_dmin_step.argtypes = [vp, f64, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
         L.mess_dmin_trial.argtypes = [vp, vp, vp]
         L.mess_dmin_eval.argtypes = [vp, vp, ctypes.POINTER(f64), vp, vp]
@@ -83,6 +84,8 @@ def lib():
             L.mess_scf_fock.argtypes = [vp, vp, vp]
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
+            L.mess_scf_guard.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.mess_batch_scf_guard.argtypes = [vp, vp]
         i64 = ctypes.c_int64
         f32 = ctypes.c_float
         L.mess_mlp_create.argtypes = [vp, ctypes.POINTER(vp)]
@@ -250,6 +253,12 @@ def mess_eri_quartets(basis: Basis, schwarz_tol=0.0):
     return counts, shells[:int(counts.sum())]
 
 
+def mess_boys(basis: Basis, T, F, m, form=0, prec=MESS_FP64, stream=None):
+    """F[i, j] = F_j(T[i]), j = 0..m, on the device (T: float64 [n], F: float64 [n, m + 1])."""
+    _check(lib().mess_boys(basis.handle, int(prec), int(form), int(m), _ptr(T), int(T.numel()), _ptr(F),
+                           _stream(stream)), "mess_boys")
+
+
 def mess_jk(basis: Basis, D, J=None, K=None, mode=MESS_JK_DIRECT, prec=MESS_FP64, schwarz_tol=0.0,
             stream=None):
     _check(lib().mess_jk(basis.handle, _ptr(D), _ptr(J), _ptr(K), int(mode), int(prec), float(schwarz_tol),
@@ -297,9 +306,10 @@ class Scf:
 
 
 def mess_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
-                    prec=MESS_FP64, jk_mode=MESS_JK_DIRECT, xc=MESS_XC_HF, D0=None, deterministic=False) -> Scf:
+                    prec=MESS_FP64, jk_mode=MESS_JK_DIRECT, xc=MESS_XC_HF, D0=None, deterministic=False,
+                    guard=True) -> Scf:
     opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), int(prec),
-                   int(jk_mode), int(xc), 1 if deterministic else 0)
+                   int(jk_mode), int(xc), 1 if deterministic else 0, 0 if guard else 1)
     h = ctypes.c_void_p()
     _check(lib().mess_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), ctypes.byref(h)), "mess_scf_create")
     return Scf(h, basis)
@@ -322,6 +332,21 @@ def mess_dmin_eval(scf: Scf, Z, G=None, stream=None):
 
 def mess_dmin_trial(scf: Scf, Z, stream=None):
     _check(lib().mess_dmin_trial(scf.handle, _ptr(Z), _stream(stream)), "mess_dmin_trial")
+
+
+def mess_scf_guard(scf: Scf):
+    """(stage, rises) of the divergence guard."""
+    st, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mess_scf_guard(scf.handle, ctypes.byref(st), ctypes.byref(r)), "mess_scf_guard")
+    return st.value, r.value
+
+
+def mess_batch_scf_guard(scf):
+    """Per-molecule divergence-guard stages (numpy int32 [n_mol])."""
+    n = scf.basis.n_mol
+    st = np.zeros(max(1, n), np.int32)
+    _check(lib().mess_batch_scf_guard(scf.handle, st.ctypes.data_as(ctypes.c_void_p)), "mess_batch_scf_guard")
+    return st[:n]
 
 
 def mess_scf_step(scf: Scf, stream=None):
@@ -359,9 +384,10 @@ class BatchScf:
 
 
 def mess_batch_scf_create(basis: Basis, schwarz_tol=0.0, conv_tol=1e-8, max_iter=100, diis_size=8,
-                          jk_mode=MESS_JK_DIRECT, D0=None, use_graph=False, prec=MESS_FP64) -> BatchScf:
+                          jk_mode=MESS_JK_DIRECT, D0=None, use_graph=False, prec=MESS_FP64,
+                          guard=True) -> BatchScf:
     opts = ScfOpts(float(schwarz_tol), float(conv_tol), int(max_iter), int(diis_size), int(prec),
-                   int(jk_mode), MESS_XC_HF, 0)
+                   int(jk_mode), MESS_XC_HF, 0, 0 if guard else 1)
     h = ctypes.c_void_p()
     _check(lib().mess_batch_scf_create(basis.handle, ctypes.byref(opts), _ptr(D0), 1 if use_graph else 0,
                                        ctypes.byref(h)), "mess_batch_scf_create")

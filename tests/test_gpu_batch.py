@@ -3,6 +3,7 @@ by molecule, what a handle over that molecule alone gives (one-electron
 matrices, J/K, and the whole SCF trajectory), in the packed block-diagonal
 layout.  The single-molecule path is itself held to the oracle by the other
 GPU tests; the converged energies are also checked against the oracle."""
+import json
 import os
 import sys
 
@@ -16,8 +17,9 @@ from mess_inputs import generators as gen  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-# mol3to20_spd molecules whose SCF converges from the core guess (seed 1002,
-# for one, oscillates for 80 steps in both paths)
+# mol3to20_spd molecules whose SCF converges from the core guess without the
+# divergence guard stepping in (seeds 1002 and 1013, which need it, have a
+# test of their own below)
 SEEDS = (1000, 1001, 1003, 1004)
 
 
@@ -198,3 +200,57 @@ def test_batch_rejections(batch):
     with pytest.raises(mess.MessError) as ei:
         mess.mess_scf_create(B)
     assert ei.value.code == mess.MESS_E_ARG
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_scf_divergence_guard(use_graph):
+    """Seed 1002 (plain DIIS oscillates by Hartrees for good) and seed 1013
+    (its DIIS path climbs repeatedly) in one batch with two ordinary
+    molecules: every molecule converges; 1002 and 1013 end in the restart
+    stage and the others never leave stage 0; energies within 1e-6 Ha of the
+    oracle's guarded SCF (seed 1002: the committed oracle golden)."""
+    mess = need_gpu()
+    from oracle import scf as oscf
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mol3to20_seed1002_guard.json")))
+    seeds = (1002, 1013, 1003, 1007)
+    mols = [gen.batched_molecule(s) for s in seeds]
+    B = mess.mess_batch_create(mols)
+    announce(f"guard batch graph={use_graph}: nbf {[m.n_bf for m in mols]}")
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8, use_graph=use_graph)
+    for k in range(250):
+        mess.mess_batch_scf_step(bs)
+        st = mess.mess_batch_scf_status(bs)
+        if st["n_converged"] == B.n_mol:
+            break
+    stages = mess.mess_batch_scf_guard(bs)
+    announce(f"  converged {st['n_converged']}/{B.n_mol} after {k + 1} steps; stages {list(stages)}; "
+             f"E {list(st['energy'])}")
+    assert st["n_converged"] == B.n_mol
+    assert list(stages) == [3, 3, 0, 0]
+    assert abs(st["energy"][0] - g["guard"]["energy"]) < 1e-6
+    for m in (1, 2, 3):
+        ref = oscf.RHF(mols[m], jk="dense", conv_tol=1e-8, max_iter=200).run()
+        assert ref["converged"] and abs(st["energy"][m] - ref["energy"]) < 1e-6, m
+    bs.close()
+    # a non-finite initial block (the core guess elsewhere) restarts that
+    # molecule alone
+    n0 = B.mol_nbf[2]
+    Dp = zeros(B.packed)
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8)
+    mess.mess_batch_scf_density(bs, Dp)
+    bs.close()
+    Dh = host(Dp)
+    Dh[B.mol_moff[2]:B.mol_moff[2] + n0 * n0] = np.nan
+    bs = mess.mess_batch_scf_create(B, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8, use_graph=use_graph,
+                                    D0=dev(Dh))
+    for k in range(250):
+        mess.mess_batch_scf_step(bs)
+        st2 = mess.mess_batch_scf_status(bs)
+        if st2["n_converged"] == B.n_mol:
+            break
+    stages2 = mess.mess_batch_scf_guard(bs)
+    announce(f"  non-finite block 2: stages {list(stages2)}, E {list(st2['energy'])}")
+    assert st2["n_converged"] == B.n_mol and stages2[2] == 3 and stages2[3] == 0
+    assert abs(st2["energy"][2] - st["energy"][2]) < 1e-7
+    bs.close()
+    B.close()

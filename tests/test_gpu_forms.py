@@ -2,7 +2,9 @@
 the same parity bar: with the form of one class forced, dense ERIs within
 1e-12 * max(1, |x|) of the extended-precision oracle and direct J/K within
 1e-11 * max(1, |x|) of the oracle's defining sums, for a molecule holding
-every angular class."""
+every angular class.  FP32 table: with one class's FP32 form forced, FP32
+J/K within 2e-5 of max|J|, max|K| (the FP32 bar of the mixed-precision
+tests)."""
 import os
 import sys
 
@@ -18,14 +20,14 @@ from oracle import core  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 PC = ["ss", "ps", "pp", "ds", "dp", "dd"]
-FORMS = {1: "lane", 2: "rows", 3: "plane", 4: "coop", 5: "wave"}
+FORMS = {1: "lane", 2: "rows", 3: "plane", 4: "coop", 5: "wave", 6: "fp64"}
 
 
-def _cases():
+def _cases(forms):
     out = []
     for cb in range(6):
         for ck in range(cb + 1):
-            for f in FORMS:
+            for f in forms:
                 out.append((cb, ck, f))
     return out
 
@@ -40,12 +42,11 @@ def ref():
     return mol, eri, D, J, K
 
 
-@pytest.mark.parametrize("cb,ck,form", _cases())
+@pytest.mark.parametrize("cb,ck,form", _cases([1, 2, 3, 4, 5]))
 def test_form_parity(ref, cb, ck, form):
     mess = need_gpu()
     cls = mess.class_index(cb, ck)
-    import ctypes
-    if mess.lib().mess_kernel_form(cls, form, None) != mess.MESS_OK:
+    if mess.lib().mess_kernel_form(mess.MESS_FP64, cls, form, None) != mess.MESS_OK:
         pytest.skip(f"form {FORMS[form]} not built for ({PC[cb]}|{PC[ck]})")
     try:
         mol, eri, D, Jo, Ko = ref
@@ -70,3 +71,24 @@ def test_form_parity(ref, cb, ck, form):
         B.close()
     finally:
         mess.mess_kernel_form(cls, mess.MESS_FORM_AUTO)
+
+
+@pytest.mark.parametrize("cb,ck,form", _cases([1, 2, 3, 4, 5, 6]))
+def test_fp32_form_parity(ref, cb, ck, form):
+    mess = need_gpu()
+    cls = mess.class_index(cb, ck)
+    if mess.lib().mess_kernel_form(mess.MESS_FP32, cls, form, None) != mess.MESS_OK:
+        pytest.skip(f"FP32 form {FORMS[form]} not built for ({PC[cb]}|{PC[ck]})")
+    try:
+        mol, eri, D, Jo, Ko = ref
+        announce(f"fp32 form {FORMS[form]} for ({PC[cb]}|{PC[ck]})")
+        B = mess.basis_from_molecule(mol)
+        N = B.nbf
+        J, K = zeros(N, N), zeros(N, N)
+        mess.mess_jk(B, dev(D), J, K, prec=mess.MESS_FP32, schwarz_tol=0.0)
+        dJ = np.max(np.abs(host(J) - Jo)) / np.max(np.abs(Jo))
+        dK = np.max(np.abs(host(K) - Ko)) / np.max(np.abs(Ko))
+        assert dJ < 2e-5 and dK < 2e-5, (dJ, dK)
+        B.close()
+    finally:
+        mess.mess_kernel_form(cls, mess.MESS_FORM_AUTO, prec=mess.MESS_FP32)

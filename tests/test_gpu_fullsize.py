@@ -1,11 +1,14 @@
 """Full-size parity on the 60-atom water cluster (300 functions), in the
 launch configuration the benchmark times (direct J/K, Schwarz 1e-10).
 
-The oracle cannot build all of J/K at this size in seconds, so sampled
-elements are computed one by one from their defining sums (no screening):
-J[mu,nu] = sum (mu nu|ls) D[l,s], K[mu,nu] = sum (mu l|nu s) D[l,s].  The
-GPU runs unscreened (tau = 0) for exact parity, and the screened build is
-checked against it: every skipped quartet is below 1e-10 in magnitude.
+The oracle needs about half an hour per full J/K build at this size, so
+two kinds of check run here: (1) sampled elements computed one by one from
+their defining sums (no screening), J[mu,nu] = sum (mu nu|ls) D[l,s],
+K[mu,nu] = sum (mu l|nu s) D[l,s], against an unscreened GPU build; (2)
+every element of J and K of screened builds (direct, stored, deterministic,
+FP32) against the oracle's own screened builds stored once by a committed
+script that calls only the oracle (the seeded test density and the
+oracle's converged density).
 """
 import os
 import sys
@@ -74,3 +77,53 @@ def test_water60_scf_matches_golden():
     assert abs(es[-1] - ref["energy"]) < 1e-9, (es[-1], ref["energy"])
     for k in range(min(len(es), len(ref["energies"]))):
         assert abs(es[k] - ref["energies"][k]) < 1e-7 * abs(ref["energies"][k]), k
+
+
+GOLDEN_JK = os.path.join(os.path.dirname(__file__), "golden", "water60_spd_seed0_jk.npz")
+
+
+def _sym(upper, n):
+    M = np.zeros((n, n))
+    M[np.triu_indices(n)] = upper
+    return M + M.T - np.diag(np.diag(M))
+
+
+@pytest.mark.parametrize("density", ["d21", "dstar"])
+@pytest.mark.parametrize("mode", ["direct", "stored", "deterministic", "direct_fp32"])
+def test_water60_jk_every_element_vs_golden(density, mode):
+    """Every element of J and K at 300 functions (Schwarz 1e-10) against the
+    oracle's full builds stored by tests/golden/make_water60_jk_golden.py:
+    the seeded test density and the oracle's converged density D*.  FP64
+    modes within 1e-10 * max(1, |x|); the FP32 build within 2e-5 of max|J|,
+    max|K| (its error at D* is the one the mixed-precision SCF meets)."""
+    mess = need_gpu()
+    if not os.path.exists(GOLDEN_JK):
+        pytest.skip("golden not generated")
+    z = np.load(GOLDEN_JK)
+    mol = G.water_cluster(0)
+    N = mol.n_bf
+    if density == "d21":
+        D = random_density(N, seed=21)
+        Jo, Ko = _sym(z["d21_J"], N), _sym(z["d21_K"], N)
+    else:
+        D = _sym(z["dstar_D"], N)
+        Jo, Ko = _sym(z["dstar_J"], N), _sym(z["dstar_K"], N)
+    B = mess.basis_from_molecule(mol)
+    announce(f"water60 J/K every element: density {density}, {mode}")
+    J, K = zeros(N, N), zeros(N, N)
+    m = {"direct": mess.MESS_JK_DIRECT, "stored": mess.MESS_JK_STORED,
+         "deterministic": mess.MESS_JK_DETERMINISTIC, "direct_fp32": mess.MESS_JK_DIRECT}[mode]
+    prec = mess.MESS_FP32 if mode == "direct_fp32" else mess.MESS_FP64
+    mess.mess_jk(B, dev(D), J, K, mode=m, prec=prec, schwarz_tol=1e-10)
+    Jh, Kh = host(J), host(K)
+    if prec == mess.MESS_FP32:
+        dJ = np.max(np.abs(Jh - Jo)) / np.max(np.abs(Jo))
+        dK = np.max(np.abs(Kh - Ko)) / np.max(np.abs(Ko))
+        announce(f"  fp32: max|dJ|/max|J| = {dJ:.2e}, max|dK|/max|K| = {dK:.2e}")
+        assert dJ < 2e-5 and dK < 2e-5
+    else:
+        eJ = np.max(np.abs(Jh - Jo) / np.maximum(1.0, np.abs(Jo)))
+        eK = np.max(np.abs(Kh - Ko) / np.maximum(1.0, np.abs(Ko)))
+        announce(f"  worst |d|/max(1,|x|): J {eJ:.2e}, K {eK:.2e}")
+        assert eJ < 1e-10 and eK < 1e-10
+    B.close()

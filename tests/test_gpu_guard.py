@@ -1,0 +1,102 @@
+"""GPU parity of the SCF divergence guard (single-molecule path): the stages
+reached, the iterations where they begin, the energies on the way and the
+converged energy, against the oracle's guarded SCF.
+
+* batched-molecule seed 1013 (34 functions; its DIIS path climbs
+  repeatedly): the same stage starts as the oracle, every energy before the
+  restart within 1e-8 Ha of the oracle's, the converged energy within 2e-8;
+* seed 1002 (114 functions; plain DIIS oscillates by Hartrees for good):
+  converges, in stage 3, to the committed oracle golden within 1e-6 Ha;
+* a non-finite initial density: the guard restarts from the core guess and
+  the run converges to the ordinary energy; with the guard off the step
+  reports MESS_E_NUMERIC.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import announce, dev, need_gpu  # noqa: E402
+
+from mess_inputs import generators as G  # noqa: E402
+from oracle import scf as oscf  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "mol3to20_seed1002_guard.json")
+
+
+def _run(mess, B, steps, **kw):
+    st = mess.mess_scf_create(B, **kw)
+    es, stages, conv = [], [], False
+    for _ in range(steps):
+        stages.append(mess.mess_scf_guard(st)[0])
+        e, de, r, c = mess.mess_scf_step(st)
+        es.append(e)
+        if c:
+            conv = True
+            break
+    final = mess.mess_scf_guard(st)[0]
+    st.close()
+    return es, stages, conv, final
+
+
+def _starts(stages):
+    st = np.array(stages)
+    return [int(np.argmax(st == s)) for s in range(st.max() + 1)]
+
+
+def test_guard_stages_match_oracle():
+    mess = need_gpu()
+    mol = G.batched_molecule(1013)
+    ref = oscf.RHF(mol, jk="dense", conv_tol=1e-8, max_iter=150).run()
+    B = mess.basis_from_molecule(mol)
+    es, stages, conv, _ = _run(mess, B, 150, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8)
+    so, sg = _starts(ref["stages"]), _starts(stages)
+    announce(f"guard seed 1013: stage starts GPU {sg} oracle {so}; iterations {len(es)} vs {ref['iterations']}; "
+             f"E {es[-1]!r} vs {ref['energy']!r}")
+    assert sg == so and len(so) == 4
+    d = np.abs(np.array(es[:so[3] + 1]) - np.array(ref["energies"][:so[3] + 1]))
+    assert d.max() < 1e-8, d.max()
+    assert conv and abs(es[-1] - ref["energy"]) < 2e-8
+    B.close()
+
+
+def test_guard_converges_oscillating_molecule():
+    mess = need_gpu()
+    g = json.load(open(GOLDEN))
+    mol = G.batched_molecule(1002)
+    assert mol.n_bf == g["n_bf"]
+    B = mess.basis_from_molecule(mol)
+    es, stages, conv, final = _run(mess, B, 250, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8)
+    announce(f"guard seed 1002: converged {conv} after {len(es)} (oracle {g['guard']['iterations']}), "
+             f"stage starts {_starts(stages)} (oracle {g['guard']['stage_starts']}), E {es[-1]!r} vs "
+             f"{g['guard']['energy']!r}")
+    assert conv and final == 3
+    assert abs(es[-1] - g["guard"]["energy"]) < 1e-6
+    # without the guard it does not settle (as in the oracle)
+    es0, _, conv0, final0 = _run(mess, B, 100, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8, guard=False)
+    assert not conv0 and final0 == 0 and not g["no_guard"]["converged"]
+    B.close()
+
+
+def test_guard_restarts_after_non_finite_density():
+    mess = need_gpu()
+    mol = G.random_small_molecule(1)
+    B = mess.basis_from_molecule(mol)
+    es, _, conv, _ = _run(mess, B, 60, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8)
+    bad = dev(np.full((B.nbf, B.nbf), np.nan))
+    es2, stages2, conv2, final2 = _run(mess, B, 60, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8, D0=bad)
+    announce(f"non-finite D0: first energy {es2[0]}, then {es2[1]!r} (core guess {es[0]!r}), final stage {final2}")
+    assert np.isnan(es2[0]) and final2 == 3 and conv2
+    assert abs(es2[1] - es[0]) <= 1e-10 * abs(es[0])
+    assert abs(es2[-1] - es[-1]) < 1e-9
+    st = mess.mess_scf_create(B, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8, D0=bad, guard=False)
+    with pytest.raises(mess.MessError) as ei:
+        mess.mess_scf_step(st)
+    assert ei.value.code == mess.MESS_E_NUMERIC
+    st.close()
+    B.close()
