@@ -26,6 +26,8 @@ silent (all restated in the design notes):
 * LDA (xc="lda"): exchange from the Dirac-Slater functional on the
   molecular grid of ``lda.py`` instead of K:  F = H + J + V_x,
   E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc.
+* PBE (xc="pbe"): the PBE exchange-correlation of ``pbe.py`` on the same
+  grid:  F = H + J + V_xc,  E = Tr[D H] + 1/2 Tr[D J] + E_xc + E_nuc.
 """
 from __future__ import annotations
 
@@ -33,6 +35,7 @@ import numpy as np
 
 from . import core
 from . import lda as olda
+from . import pbe as opbe
 
 
 def canonical_orthogonaliser(S: np.ndarray, thresh: float = 1e-7) -> np.ndarray:
@@ -91,17 +94,20 @@ class RHF:
         self.guard = guard
         self.conv_tol, self.max_iter, self.fixed_iters = conv_tol, max_iter, fixed_iters
         self._eri = core.eri_dense(mol) if jk == "dense" else None
-        if xc not in ("hf", "lda"):
+        if xc not in ("hf", "lda", "pbe"):
             raise ValueError(xc)
         self.xc = xc
-        self._grid = olda.grid_points(mol) if xc == "lda" else None
+        self._grid = olda.grid_points(mol) if xc in ("lda", "pbe") else None
 
     def fock(self, D):
         """(F, E) at density D for the chosen exchange."""
         J, K = self.jk(D)
         if self.xc == "hf":
             return fock_and_energy(self.H, J, K, D, self.e_nuc)
-        Ex, Vx, _ = olda.lda_x(self.mol, D, grid=self._grid)
+        if self.xc == "pbe":
+            Ex, Vx = opbe.pbe_xc(self.mol, D, grid=self._grid)[:2]
+        else:
+            Ex, Vx, _ = olda.lda_x(self.mol, D, grid=self._grid)
         F = self.H + J + Vx
         E = float(np.sum(D * self.H)) + 0.5 * float(np.sum(D * J)) + Ex + self.e_nuc
         return F, E
