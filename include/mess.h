@@ -61,7 +61,7 @@ enum { MESS_FP64 = 0, MESS_FP32 = 1 };                       /* arithmetic of th
 enum { MESS_ERI_DENSE = 0, MESS_ERI_BLOCKS = 1 };            /* mess_eri output layout */
 enum { MESS_JK_DIRECT = 0, MESS_JK_STORED = 1,               /* mess_jk source of integrals */
        MESS_JK_DETERMINISTIC = 2 };                          /* stored blocks, exact accumulation */
-enum { MESS_XC_HF = 0, MESS_XC_LDA_X = 1 };                  /* exchange in the Fock matrix */
+enum { MESS_XC_HF = 0, MESS_XC_LDA_X = 1, MESS_XC_PBE = 2 };  /* exchange(-correlation) in the Fock matrix */
 
 typedef struct mess_scf_opts {
     double schwarz_tol;  /* skip quartet iff Q_ab Q_cd < tol; <= 0 keeps every quartet */
@@ -80,8 +80,10 @@ typedef struct mess_scf_opts {
                             eigen-problem and density in FP64; classes whose FP64 kernel is
                             faster run in FP64 (MESS_FORM_FP64) */
     int32_t jk_mode;     /* MESS_JK_DIRECT or MESS_JK_STORED */
-    int32_t xc;          /* MESS_XC_HF (F = H + J - K/2) or MESS_XC_LDA_X (F = H + J + V_x,
-                            E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; FP64 only; see mess_lda_x) */
+    int32_t xc;          /* MESS_XC_HF (F = H + J - K/2), MESS_XC_LDA_X (F = H + J + V_x,
+                            E = Tr[D H] + 1/2 Tr[D J] + E_x + E_nuc; see mess_lda_x) or
+                            MESS_XC_PBE (the same with V_xc, E_xc of mess_pbe_xc); the
+                            last two FP64 only */
     int32_t deterministic; /* nonzero: every Fock build runs as mess_jk(MESS_JK_DETERMINISTIC)
                               (overrides jk_mode), so a rerun reproduces every energy and
                               density bit for bit */
@@ -255,6 +257,29 @@ int mess_jk_noalloc(const mess_basis *basis, const double *D, double *J, double 
  * MESS_E_NOMEM. */
 int mess_lda_x(const mess_basis *basis, const double *D, double *Vx, double *Ex, double *rho,
                mess_stream stream);
+
+/* PBE exchange-correlation (the generalised-gradient functional the paper
+ * selects through its Hamiltonian's exchange-correlation option, section
+ * 5; Perdew, Burke and Ernzerhof 1996), closed shell, on the grid of
+ * mess_lda_x:
+ *   sigma = |grad rho|^2, grad rho_g = 2 sum_{mu nu} D_{mu nu} phi_mu grad phi_nu,
+ *   f = rho eps_x^unif F_x(s) + rho (eps_c^PW92(r_s) + H(r_s, t)),
+ *   E_xc = sum_g w_g f_g,
+ *   V_xc[mu][nu] = sum_g w_g [f_rho phi_mu phi_nu
+ *                   + 2 f_sigma grad rho . grad(phi_mu phi_nu)]
+ * with kappa = 0.804, beta = 0.06672455060314922, mu = beta pi^2/3,
+ * gamma = (1 - ln 2)/pi^2 and the Perdew-Wang (1992) paramagnetic
+ * correlation (A = 0.031091, a1 = 0.21370, b = 7.5957, 3.5876, 1.6382,
+ * 0.49294); points with rho < 1e-10 contribute nothing.  The basis
+ * gradients on the grid are built on the first call (24 N bytes per point
+ * beyond mess_lda_x's) and kept in the basis.
+ *   D: device N x N symmetric density.  Vxc: device N x N or NULL.
+ *   Exc: host scalar or NULL (non-NULL synchronises the stream).
+ *   rho: device [npts] or NULL; grad_rho: device [3][npts] or NULL.
+ * Errors: MESS_E_UNSUPPORTED for a batch of more than one molecule,
+ * MESS_E_NOMEM. */
+int mess_pbe_xc(const mess_basis *basis, const double *D, double *Vxc, double *Exc, double *rho,
+                double *grad_rho, mess_stream stream);
 
 /* The LDA grid: *npts points (host, may be NULL); xyzw (device, may be
  * NULL) receives [npts][4] = x, y, z (bohr) and weight, ordered by atom,

@@ -27,6 +27,7 @@ int jk_stored(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, 
 int jk_det(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, double tau, hipStream_t s);
 int zero_async(double *p, int64_t n, hipStream_t s);
 int lda_x_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev);
+int pbe_xc_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev);
 
 constexpr int kMaxDiis = 16;
 
@@ -61,7 +62,7 @@ struct mess_scf {
     mess::ScfScalars *sc = nullptr;
     double *partial = nullptr;                           // reduction partials
     double *Dprev = nullptr, *dD = nullptr, *Gja = nullptr, *Gka = nullptr;  // FP32 incremental builds
-    double *Vx = nullptr;                                // LDA exchange potential
+    double *Vx = nullptr;                                // LDA exchange / PBE exchange-correlation potential
     int *d_hs = nullptr;                                 // DIIS history slot list, kMaxDiis
     // direct minimisation (mess_dmin_step): trial matrix, QR factors, Adam
     // moments, gradient work (N x N each, built on the first call)
@@ -101,7 +102,7 @@ constexpr double kDamp = 0.5;
 
 // Hartree-Fock (Vx == NULL): F = H + J - K/2 with J = Gj + Gj^T,
 // K = Gk + Gk^T, and per-block partial sums of D .* (H + F);
-// LDA exchange: F = H + J + Vx and partial sums of D .* (2H + J), so that
+// LDA exchange or PBE exchange-correlation: F = H + J + Vx and partial sums of D .* (2H + J), so that
 // half the total is Tr[D H] + 1/2 Tr[D J] in both cases (deterministic
 // two-stage reduction).
 __global__ void __launch_bounds__(256) k_fock(int N, const double *__restrict__ H, const double *__restrict__ Gj,
@@ -590,7 +591,7 @@ static int scf_create_impl(mess_scf *st, const double *D0) {
     if (st->opts.prec == MESS_FP32)
         for (double **p : {&st->Dprev, &st->dD, &st->Gja, &st->Gka})
             MESS_HIP(hipMalloc(p, sizeof(double) * std::max<size_t>(nn, 16)));
-    if (st->opts.xc == MESS_XC_LDA_X) MESS_HIP(hipMalloc(&st->Vx, sizeof(double) * std::max<size_t>(nn, 16)));
+    if (st->opts.xc != MESS_XC_HF) MESS_HIP(hipMalloc(&st->Vx, sizeof(double) * std::max<size_t>(nn, 16)));
     MESS_HIP(hipMalloc(&st->sc, sizeof(ScfScalars)));
     MESS_HIP(hipMalloc(&st->partial, sizeof(double) * kRedBlocks));
     MESS_HIP(hipMemset(st->sc, 0, sizeof(ScfScalars)));
@@ -716,7 +717,8 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
         MESS_TRY(scf_jk(st, st->D, st->Gj, Gk, st->opts.prec, st->opts.schwarz_tol, s));
     }
     const double *ex = nullptr;
-    if (st->Vx) MESS_TRY(lda_x_async(B, st->D, st->Vx, s, &ex));
+    if (st->opts.xc == MESS_XC_LDA_X) MESS_TRY(lda_x_async(B, st->D, st->Vx, s, &ex));
+    if (st->opts.xc == MESS_XC_PBE) MESS_TRY(pbe_xc_async(B, st->D, st->Vx, s, &ex));
     hipLaunchKernelGGL(k_fock, dim3(kRedBlocks), dim3(256), 0, s, N, st->H, st->Gj, st->Gk, st->Vx, st->D, st->F,
                        st->partial);
     hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(256), 0, s, kRedBlocks, st->partial, B->enuc, ex, st->sc);
@@ -1019,12 +1021,12 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
         set_error("mess_scf_create: unknown precision %d", opts->prec);
         return MESS_E_UNSUPPORTED;
     }
-    if (opts->xc != MESS_XC_HF && opts->xc != MESS_XC_LDA_X) {
+    if (opts->xc != MESS_XC_HF && opts->xc != MESS_XC_LDA_X && opts->xc != MESS_XC_PBE) {
         set_error("mess_scf_create: unknown exchange form %d", opts->xc);
         return MESS_E_UNSUPPORTED;
     }
-    if (opts->xc == MESS_XC_LDA_X && opts->prec != MESS_FP64) {
-        set_error("mess_scf_create: LDA exchange runs in FP64 only");
+    if (opts->xc != MESS_XC_HF && opts->prec != MESS_FP64) {
+        set_error("mess_scf_create: LDA and PBE run in FP64 only");
         return MESS_E_UNSUPPORTED;
     }
     if (opts->diis_size < 0 || opts->diis_size > kMaxDiis || !(opts->conv_tol >= 0.0)) {

@@ -23,6 +23,22 @@
 // a second kernel forms V_x = PhiT diag(f) PhiT^T on 64 x 64 tiles of the
 // upper block triangle over chunks of points, adding tile partials into
 // V_x with FP64 atomics (2 N^2 flops per point in all).
+//
+// PBE exchange-correlation (the generalised-gradient functional the paper
+// selects for its DFT examples, section 5), closed shell, on the same grid:
+//   f(rho, sigma) = rho eps_x^unif F_x(s) + rho (eps_c^PW92(r_s) + H(r_s, t)),
+//   sigma = |grad rho|^2, grad rho = 2 sum_{mu nu} D_{mu nu} phi_mu grad phi_nu,
+//   E_xc = sum_g w_g f_g,
+//   V_xc[mu][nu] = sum_g w_g [f_rho phi_mu phi_nu
+//                             + 2 f_sigma grad rho . (phi_mu grad phi_nu + grad phi_mu phi_nu)],
+// with the partial derivatives f_rho, f_sigma written out analytically
+// (pbe_point); points with rho < 1e-10 add nothing.  The basis gradients
+// dPhiT[k][mu][g] (k = x, y, z) are built on the first PBE call.  Per
+// density: U = D PhiT per 64-point tile reduced against PhiT and the three
+// dPhiT (rho and grad rho in one pass, 2 N^2 + 6 N flops per point), the
+// functional per point, and V_xc = PhiT Z^T + Z PhiT^T with
+// Z[nu][g] = w (f_rho/2 phi_nu + 2 f_sigma grad rho . grad phi_nu) formed
+// while the tiles are staged (all tile pairs, 2 N^2 flops per point).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -46,6 +62,9 @@ struct XcShell {
 struct XcGrid {
     int64_t npts = 0, G = 0;
     int nbf = 0, nrho_blocks = 0;
+    double *dphiT = nullptr;  // [3][nbf][G] basis gradients (PBE only)
+    double *grad = nullptr;   // [3][G] grad rho (PBE)
+    double *hv = nullptr;     // [3][G] 2 w f_sigma grad rho (PBE)
     double *xyzw = nullptr;   // [G][4]
     double *phiT = nullptr;   // [nbf][G]
     double *f = nullptr;      // [G] w_g v_x(rho_g)
@@ -58,7 +77,7 @@ struct XcGrid {
 void free_xc(mess_basis *B) {
     XcGrid *X = static_cast<XcGrid *>(B->xc);
     if (!X) return;
-    for (double *p : {X->xyzw, X->phiT, X->f, X->rho, X->epart, X->ex, X->Vacc}) hipFree(p);
+    for (double *p : {X->xyzw, X->phiT, X->f, X->rho, X->epart, X->ex, X->Vacc, X->dphiT, X->grad, X->hv}) hipFree(p);
     delete X;
     B->xc = nullptr;
 }
@@ -179,6 +198,64 @@ __global__ void k_basis_values(int nsh, const XcShell *__restrict__ sh, const do
             o[3 * G] = dy * dy * rad;
             o[4 * G] = kSqrt3 * dy * dz * rad;
             o[5 * G] = dz * dz * rad;
+        }
+    }
+}
+
+// dPhiT[k][mu][g] = d phi_mu / d r_k at point g: one thread per point, loop
+// over shells; for x^a y^b z^c R(r^2), R = sum c_p e^{-alpha_p r^2},
+// d/dx = a x^(a-1) y^b z^c R - 2 x (x^a y^b z^c) sum c_p alpha_p e^{-alpha_p r^2}.
+__global__ void k_basis_grad(int nsh, const XcShell *__restrict__ sh, const double *__restrict__ alpha,
+                             const double *__restrict__ ct, int64_t npts, int64_t G, int nbf,
+                             const double *__restrict__ xyzw, double *__restrict__ dphiT) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const bool live = g < npts;
+    const double px = xyzw[4 * g], py = xyzw[4 * g + 1], pz = xyzw[4 * g + 2];
+    const int64_t plane = (int64_t)nbf * G;
+    for (int s = 0; s < nsh; ++s) {
+        const XcShell S = sh[s];
+        const double d[3] = {px - S.x, py - S.y, pz - S.z};
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double rad = 0.0, drad = 0.0;
+        if (live)
+            for (int p = 0; p < S.nprim; ++p) {
+                const double a = alpha[S.prim0 + p], e = a * r2;
+                if (e < 745.0) {
+                    const double t = ct[S.prim0 + p] * exp(-e);
+                    rad += t;
+                    drad += a * t;
+                }
+            }
+        const int nc = (S.l + 1) * (S.l + 2) / 2;
+        for (int c = 0; c < nc; ++c) {
+            // component exponents in the order x-major (xx, xy, xz, yy, yz, zz)
+            int e[3];
+            if (S.l == 0) {
+                e[0] = e[1] = e[2] = 0;
+            } else if (S.l == 1) {
+                e[0] = c == 0;
+                e[1] = c == 1;
+                e[2] = c == 2;
+            } else {
+                const int tab[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+                e[0] = tab[c][0];
+                e[1] = tab[c][1];
+                e[2] = tab[c][2];
+            }
+            const double sc = (S.l == 2 && (c == 1 || c == 2 || c == 4)) ? kSqrt3 : 1.0;
+            double mono = 1.0;
+            for (int k = 0; k < 3; ++k)
+                for (int q = 0; q < e[k]; ++q) mono *= d[k];
+            for (int k = 0; k < 3; ++k) {
+                double lower = 0.0;
+                if (e[k] > 0) {
+                    lower = e[k];
+                    for (int j = 0; j < 3; ++j)
+                        for (int q = 0; q < e[j] - (j == k); ++q) lower *= d[j];
+                }
+                dphiT[k * plane + (int64_t)(S.bf0 + c) * G + g] = sc * (lower * rad - 2.0 * d[k] * mono * drad);
+            }
         }
     }
 }
@@ -353,6 +430,230 @@ __global__ void k_lda_mirror(int N, const double *__restrict__ Vacc, double *__r
     }
 }
 
+// ------------------------------------------------------------------ PBE
+
+constexpr double kRhoMin = 1e-10;
+
+// f = rho eps_x^unif F_x + rho (eps_c + H) and its partial derivatives in
+// rho and sigma (closed shell, Hartree atomic units).
+//   exchange: s^2 = c_s sigma rho^(-8/3), c_s = 1 / (4 (3 pi^2)^(2/3)),
+//     F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa);
+//   correlation: Perdew-Wang eps_c(r_s), r_s = (3 / (4 pi rho))^(1/3);
+//     t^2 = c_t sigma rho^(-7/3), c_t = pi / (16 (3 pi^2)^(1/3));
+//     H = gamma ln(1 + (beta/gamma) t^2 R(A t^2)), R(y) = (1 + y)/(1 + y + y^2),
+//     A = (beta/gamma) / (exp(-eps_c/gamma) - 1).
+__device__ __forceinline__ void pbe_point(double rho, double sigma, double &f, double &fr, double &fs) {
+    if (!(rho >= kRhoMin)) {
+        f = fr = fs = 0.0;
+        return;
+    }
+    constexpr double kKappa = 0.804, kBeta = 0.06672455060314922;
+    constexpr double kMu = kBeta * M_PI * M_PI / 3.0;
+    constexpr double kGamma = 0.031090690869654895;  // (1 - ln 2) / pi^2
+    constexpr double kA = 0.031091, kA1 = 0.21370, kB1 = 7.5957, kB2 = 3.5876, kB3 = 1.6382, kB4 = 0.49294;
+    constexpr double kCx = -0.73855876638202240587;  // -(3/4)(3/pi)^(1/3)
+    constexpr double kCs = 0.026121172985233599;     // 1 / (4 (3 pi^2)^(2/3))
+    constexpr double kCt = 0.063468206097703704;     // pi / (16 (3 pi^2)^(1/3))
+    constexpr double kRs = 0.62035049089940001667;   // (3 / (4 pi))^(1/3)
+    const double r13 = cbrt(rho), r43 = rho * r13;
+    const double ir43 = 1.0 / r43, ir83 = ir43 * ir43;
+    // exchange
+    const double x = kCs * sigma * ir83;
+    const double den = 1.0 + kMu * x / kKappa;
+    const double Fx = 1.0 + kKappa - kKappa / den;
+    const double Fxp = kMu / (den * den);
+    const double ex = kCx * r43 * Fx;
+    const double exr = kCx * r13 * ((4.0 / 3.0) * Fx - (8.0 / 3.0) * x * Fxp);
+    const double exs = kCx * Fxp * kCs * ir43;
+    // Perdew-Wang correlation of the uniform gas
+    const double rs = kRs / r13, sq = sqrt(rs);
+    const double Q = 2.0 * kA * (kB1 * sq + kB2 * rs + kB3 * rs * sq + kB4 * rs * rs);
+    const double Qp = 2.0 * kA * (0.5 * kB1 / sq + kB2 + 1.5 * kB3 * sq + 2.0 * kB4 * rs);
+    const double Lg = log1p(1.0 / Q);
+    const double ec = -2.0 * kA * (1.0 + kA1 * rs) * Lg;
+    const double dec = -2.0 * kA * kA1 * Lg + 2.0 * kA * (1.0 + kA1 * rs) * Qp / (Q * Q + Q);
+    // gradient correction
+    const double u = kCt * sigma * ir43 / rho;  // t^2
+    const double E1 = expm1(-ec / kGamma);
+    const double Ap = (kBeta / kGamma) / E1;
+    const double y = Ap * u, d2 = 1.0 + y + y * y;
+    const double R = (1.0 + y) / d2, Rp = -y * (2.0 + y) / (d2 * d2);
+    const double Nn = (kBeta / kGamma) * u * R;
+    const double H = kGamma * log1p(Nn);
+    const double dHdN = kGamma / (1.0 + Nn);
+    const double dHdu = dHdN * (kBeta / kGamma) * (R + y * Rp);
+    const double dHdec = dHdN * (kBeta / kGamma) * u * u * Rp * (Ap * Ap * (E1 + 1.0) / kBeta);
+    f = ex + rho * (ec + H);
+    fr = exr + ec + H - (rs / 3.0) * dec * (1.0 + dHdec) - (7.0 / 3.0) * u * dHdu;
+    fs = exs + dHdu * kCt * ir43;
+}
+
+// rho and grad rho over a 64-point tile: U = D PhiT[:, tile] by 64-row
+// chunks as in k_lda_rho, reduced against PhiT (rho) and the three basis
+// gradient planes (grad rho = 2 sum_nu dPhiT[k][nu][g] U[nu][g]).
+__global__ void __launch_bounds__(256) k_gga_rho(int N, int64_t G, const double *__restrict__ D,
+                                                 const double *__restrict__ phiT, const double *__restrict__ dphiT,
+                                                 double *__restrict__ rho_out, double *__restrict__ grad_out) {
+    __shared__ double As[kXK][kXT + 1];
+    __shared__ double Bs[kXK][kXT + 1];
+    __shared__ double red[16][kXT + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int64_t g0 = (int64_t)blockIdx.x * kXT;
+    const int64_t plane = (int64_t)N * G;
+    double part[4][4] = {};
+    for (int nu0 = 0; nu0 < N; nu0 += kXT) {
+        double acc[4][4] = {};
+        for (int k0 = 0; k0 < N; k0 += kXK) {
+            for (int t = threadIdx.x; t < kXK * kXT; t += 256) {
+                const int kk = t % kXK, mm = t / kXK;
+                const int r = nu0 + mm, k = k0 + kk;
+                As[kk][mm] = (r < N && k < N) ? D[(int64_t)r * N + k] : 0.0;
+            }
+            for (int t = threadIdx.x; t < kXK * kXT; t += 256) {
+                const int kk = t / kXT, nn = t % kXT;
+                const int k = k0 + kk;
+                Bs[kk][nn] = k < N ? phiT[(int64_t)k * G + g0 + nn] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < kXK; ++kk) {
+                double a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int nu = nu0 + ty + 16 * i;
+            if (nu >= N) continue;
+            const int64_t o = (int64_t)nu * G + g0 + tx;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                part[0][j] = fma(phiT[o + 16 * j], acc[i][j], part[0][j]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) part[1 + k][j] = fma(dphiT[k * plane + o + 16 * j], acc[i][j], part[1 + k][j]);
+            }
+        }
+    }
+    // fixed-order reductions over the 16 row groups, one quantity at a time
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[ty][tx + 16 * j] = part[q][j];
+        __syncthreads();
+        if (threadIdx.x < kXT) {
+            double r = 0.0;
+            for (int k = 0; k < 16; ++k) r += red[k][threadIdx.x];
+            const int64_t g = g0 + threadIdx.x;
+            if (q == 0) rho_out[g] = r;
+            else grad_out[(q - 1) * G + g] = 2.0 * r;
+        }
+        __syncthreads();
+    }
+}
+
+// The functional per point: energy partial sums per 256-point block (fixed
+// order), f_g = w f_rho / 2 and hv[k][g] = 2 w f_sigma d_k rho.
+__global__ void __launch_bounds__(256) k_pbe_point(int64_t G, const double *__restrict__ xyzw,
+                                                   const double *__restrict__ rho, const double *__restrict__ grad,
+                                                   double *__restrict__ f, double *__restrict__ hv,
+                                                   double *__restrict__ epart) {
+    __shared__ double red[256];
+    const int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x;
+    double e = 0.0;
+    if (g < G) {
+        const double w = xyzw[4 * g + 3];
+        const double gx = grad[g], gy = grad[G + g], gz = grad[2 * G + g];
+        double fv, fr, fs;
+        pbe_point(rho[g], gx * gx + gy * gy + gz * gz, fv, fr, fs);
+        e = w * fv;
+        f[g] = 0.5 * w * fr;
+        const double h = 2.0 * w * fs;
+        hv[g] = h * gx;
+        hv[G + g] = h * gy;
+        hv[2 * G + g] = h * gz;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) epart[blockIdx.x] = red[0];
+}
+
+// Vacc[mu][nu] += sum_{g in chunk} PhiT[mu][g] Z[nu][g] for every tile pair
+// (bi, bj) = blockIdx.y, with Z[nu][g] = f_g PhiT[nu][g] + hv[.][g] . dPhiT[.][nu][g]
+// formed as the tile is staged; V = Vacc + Vacc^T afterwards.
+__global__ void __launch_bounds__(256) k_gga_v(int N, int64_t G, int nblk, const double *__restrict__ phiT,
+                                               const double *__restrict__ dphiT, const double *__restrict__ f,
+                                               const double *__restrict__ hv, double *__restrict__ Vacc) {
+    __shared__ double As[kXK][kXT + 1];
+    __shared__ double Bs[kXK][kXT + 1];
+    const int bi = blockIdx.y / nblk, bj = blockIdx.y % nblk;
+    const int row0 = bi * kXT, col0 = bj * kXT;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int64_t plane = (int64_t)N * G;
+    const int64_t gs = (int64_t)blockIdx.x * kVChunk;
+    const int64_t ge = gs + kVChunk < G ? gs + kVChunk : G;
+    double acc[4][4] = {};
+    for (int64_t k0 = gs; k0 < ge; k0 += kXK) {
+        for (int t = threadIdx.x; t < kXK * kXT; t += 256) {
+            const int kk = t % kXK, mm = t / kXK;
+            const int r = row0 + mm;
+            As[kk][mm] = r < N ? phiT[(int64_t)r * G + k0 + kk] : 0.0;
+        }
+        for (int t = threadIdx.x; t < kXK * kXT; t += 256) {
+            const int kk = t % kXK, nn = t / kXK;
+            const int c = col0 + nn;
+            const int64_t g = k0 + kk, o = (int64_t)c * G + g;
+            Bs[kk][nn] = c < N ? f[g] * phiT[o] + hv[g] * dphiT[o] + hv[G + g] * dphiT[plane + o] +
+                                     hv[2 * G + g] * dphiT[2 * plane + o]
+                               : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kXK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = row0 + ty + 16 * i;
+        if (r >= N) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = col0 + tx + 16 * j;
+            if (c < N) unsafeAtomicAdd(&Vacc[(int64_t)r * N + c], acc[i][j]);
+        }
+    }
+}
+
+// V = Vacc + Vacc^T (exactly symmetric)
+__global__ void k_gga_sym(int N, const double *__restrict__ Vacc, double *__restrict__ V) {
+    const int64_t NN = (int64_t)N * N;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / N), j = (int)(idx % N);
+        V[idx] = Vacc[idx] + Vacc[(int64_t)j * N + i];
+    }
+}
+
 int zero_async(double *p, int64_t n, hipStream_t s);
 
 // Grid and basis values, built once per basis (synchronous).
@@ -452,6 +753,81 @@ static int get_xc(mess_basis *B, XcGrid **out) {
     return MESS_OK;
 }
 
+// Basis gradients on the grid and the PBE per-point buffers, built on the
+// first PBE call (synchronous).
+static int ensure_gga(mess_basis *B, XcGrid *X) {
+    if (X->dphiT) return MESS_OK;
+    std::vector<XcShell> hs(B->nsh);
+    for (int s = 0; s < B->nsh; ++s) {
+        const int at = B->sh_atom[s];
+        hs[s] = XcShell{B->xyz[3 * at], B->xyz[3 * at + 1], B->xyz[3 * at + 2], B->sh_l[s], B->sh_prim0[s],
+                        B->sh_np[s], B->sh_bf0[s]};
+    }
+    const size_t np = B->alpha.size();
+    double *d_alpha = nullptr, *d_ct = nullptr;
+    XcShell *d_sh = nullptr;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
+    chk(hipMalloc(&X->dphiT, sizeof(double) * 3 * (size_t)X->nbf * X->G));
+    chk(hipMalloc(&X->grad, sizeof(double) * 3 * X->G));
+    chk(hipMalloc(&X->hv, sizeof(double) * 3 * X->G));
+    chk(hipMalloc(&d_alpha, sizeof(double) * np));
+    chk(hipMalloc(&d_ct, sizeof(double) * np));
+    chk(hipMalloc(&d_sh, sizeof(XcShell) * B->nsh));
+    if (e == hipSuccess) {
+        chk(hipMemcpy(d_alpha, B->alpha.data(), sizeof(double) * np, hipMemcpyHostToDevice));
+        chk(hipMemcpy(d_ct, B->ctilde.data(), sizeof(double) * np, hipMemcpyHostToDevice));
+        chk(hipMemcpy(d_sh, hs.data(), sizeof(XcShell) * B->nsh, hipMemcpyHostToDevice));
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_basis_grad, dim3((unsigned)((X->G + 255) / 256)), dim3(256), 0, nullptr, B->nsh, d_sh,
+                           d_alpha, d_ct, X->npts, X->G, X->nbf, X->xyzw, X->dphiT);
+        chk(hipGetLastError());
+        chk(hipDeviceSynchronize());
+    }
+    hipFree(d_alpha);
+    hipFree(d_ct);
+    hipFree(d_sh);
+    if (e != hipSuccess) {
+        for (double **p : {&X->dphiT, &X->grad, &X->hv}) {
+            hipFree(*p);
+            *p = nullptr;
+        }
+        set_error("PBE basis gradients: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? MESS_E_NOMEM : MESS_E_DEVICE;
+    }
+    return MESS_OK;
+}
+
+// PBE: V (device N x N, may be NULL) and the device scalar X->ex (E_xc)
+// from density D.
+int pbe_xc_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev) {
+    XcGrid *X = nullptr;
+    MESS_TRY(get_xc(B, &X));
+    MESS_TRY(ensure_gga(B, X));
+    const int N = X->nbf;
+    const unsigned npb = (unsigned)((X->G + 255) / 256);
+    hipLaunchKernelGGL(k_gga_rho, dim3((unsigned)X->nrho_blocks), dim3(256), 0, s, N, X->G, D, X->phiT, X->dphiT,
+                       X->rho, X->grad);
+    hipLaunchKernelGGL(k_pbe_point, dim3(npb), dim3(256), 0, s, X->G, X->xyzw, X->rho, X->grad, X->f, X->hv,
+                       X->epart);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (int)npb, X->epart, X->ex);
+    MESS_LAUNCH_CHECK();
+    if (V) {
+        const int nblk = (N + kXT - 1) / kXT;
+        const unsigned chunks = (unsigned)((X->G + kVChunk - 1) / kVChunk);
+        MESS_TRY(zero_async(X->Vacc, (int64_t)N * N, s));
+        hipLaunchKernelGGL(k_gga_v, dim3(chunks, nblk * nblk), dim3(256), 0, s, N, X->G, nblk, X->phiT, X->dphiT,
+                           X->f, X->hv, X->Vacc);
+        hipLaunchKernelGGL(k_gga_sym, dim3(256), dim3(256), 0, s, N, X->Vacc, V);
+        MESS_LAUNCH_CHECK();
+    }
+    if (ex_dev) *ex_dev = X->ex;
+    return MESS_OK;
+}
+
 // V (device N x N, may be NULL) and the device scalar X->ex from density D.
 int lda_x_async(mess_basis *B, const double *D, double *V, hipStream_t s, const double **ex_dev) {
     XcGrid *X = nullptr;
@@ -495,6 +871,29 @@ int mess_lda_x(const mess_basis *basis, const double *D, double *Vx, double *Ex,
     if (rho) MESS_HIP(hipMemcpyAsync(rho, X->rho, sizeof(double) * X->npts, hipMemcpyDeviceToDevice, s));
     if (Ex) {
         MESS_HIP(hipMemcpyAsync(Ex, ex, sizeof(double), hipMemcpyDeviceToHost, s));
+        MESS_HIP(hipStreamSynchronize(s));
+    }
+    return MESS_OK;
+}
+
+int mess_pbe_xc(const mess_basis *basis, const double *D, double *Vxc, double *Exc, double *rho, double *grad_rho,
+                mess_stream stream) {
+    if (!basis || !D) {
+        set_error("mess_pbe_xc: NULL basis or density");
+        return MESS_E_ARG;
+    }
+    auto *B = const_cast<mess_basis *>(basis);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double *ex = nullptr;
+    MESS_TRY(pbe_xc_async(B, D, Vxc, s, &ex));
+    XcGrid *X = static_cast<XcGrid *>(B->xc);
+    if (rho) MESS_HIP(hipMemcpyAsync(rho, X->rho, sizeof(double) * X->npts, hipMemcpyDeviceToDevice, s));
+    if (grad_rho)
+        for (int k = 0; k < 3; ++k)
+            MESS_HIP(hipMemcpyAsync(grad_rho + k * X->npts, X->grad + k * X->G, sizeof(double) * X->npts,
+                                    hipMemcpyDeviceToDevice, s));
+    if (Exc) {
+        MESS_HIP(hipMemcpyAsync(Exc, ex, sizeof(double), hipMemcpyDeviceToHost, s));
         MESS_HIP(hipStreamSynchronize(s));
     }
     return MESS_OK;

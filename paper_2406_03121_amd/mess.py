@@ -19,7 +19,7 @@ MESS_OK, MESS_E_ARG, MESS_E_UNSUPPORTED, MESS_E_NOMEM, MESS_E_DEVICE, MESS_E_NUM
 MESS_FP64, MESS_FP32 = 0, 1
 MESS_ERI_DENSE, MESS_ERI_BLOCKS = 0, 1
 MESS_JK_DIRECT, MESS_JK_STORED, MESS_JK_DETERMINISTIC = 0, 1, 2
-MESS_XC_HF, MESS_XC_LDA_X = 0, 1
+MESS_XC_HF, MESS_XC_LDA_X, MESS_XC_PBE = 0, 1, 2
 MESS_FORM_AUTO, MESS_FORM_LANE, MESS_FORM_ROWS, MESS_FORM_PLANE, MESS_FORM_COOP, MESS_FORM_WAVE, MESS_FORM_FP64 = range(7)
 
 EXPORTED = [
@@ -29,7 +29,7 @@ EXPORTED = [
     "mess_work_stats", "mess_prim_pairs", "mess_prof_enable", "mess_prof_read",
     "mess_batch_create", "mess_batch_info", "mess_batch_scf_create", "mess_batch_scf_step",
     "mess_batch_scf_status", "mess_batch_scf_density", "mess_batch_scf_destroy",
-    "mess_lda_x", "mess_grid",
+    "mess_lda_x", "mess_pbe_xc", "mess_grid",
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
@@ -102,6 +102,7 @@ def lib():
         L.mess_guess_project.argtypes = [vp, vp, vp]
         L.mess_guess_judge.argtypes = [vp, ctypes.POINTER(ScfOpts), vp, vp, vp]
         L.mess_lda_x.argtypes = [vp, vp, vp, ctypes.POINTER(f64), vp, vp]
+        L.mess_pbe_xc.argtypes = [vp, vp, vp, ctypes.POINTER(f64), vp, vp, vp]
         L.mess_grid.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
         L.mess_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.mess_batch_info.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -277,6 +278,14 @@ def mess_lda_x(basis: Basis, D, Vx=None, rho=None, stream=None):
     ex = ctypes.c_double()
     _check(lib().mess_lda_x(basis.handle, _ptr(D), _ptr(Vx), ctypes.byref(ex), _ptr(rho), _stream(stream)),
            "mess_lda_x")
+    return ex.value
+
+
+def mess_pbe_xc(basis: Basis, D, Vxc=None, rho=None, grad_rho=None, stream=None):
+    """E_xc (host float); fills Vxc (N x N), rho [npts] and grad_rho [3, npts] if given."""
+    ex = ctypes.c_double()
+    _check(lib().mess_pbe_xc(basis.handle, _ptr(D), _ptr(Vxc), ctypes.byref(ex), _ptr(rho), _ptr(grad_rho),
+                             _stream(stream)), "mess_pbe_xc")
     return ex.value
 
 
