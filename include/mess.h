@@ -305,6 +305,27 @@ int mess_scf_create(const mess_basis *basis, const mess_scf_opts *opts, const do
  * Outputs (host, any may be NULL): energy E_k, delta_e = E_k - E_{k-1}
  * (0 at k = 0), resid = max |X^T (F D S - S D F) X|, converged flag.
  * Synchronises the stream.  Non-convergence is not an error. */
+/* Nuclear gradient dE/dR of the closed-shell Hartree-Fock energy (the
+ * atomic forces the paper obtains by differentiating its energy, sections
+ * 1 and 4), analytic:
+ *   dE/dR_X = sum D dH/dR_X + 1/2 sum P d(mu nu|la si)/dR_X
+ *             - sum W dS/dR_X + dE_nuc/dR_X,
+ * W = D F D / 2, P = D_{mu nu} D_{la si} - (D_{mu la} D_{nu si} + D_{mu si} D_{nu la}) / 4,
+ * with the integral derivatives from Hermite expansions one order above
+ * the differentiated function.  Valid at a converged density (D and F of
+ * the same SCF iteration; the energy must be stationary in D).
+ *   D, F: device N x N.  schwarz_tol: shell quartets with Q_ab Q_cd below
+ *   it are left out (0 keeps all).  grad: host [n_atoms][3], Hartree/bohr.
+ * Synchronous.  Errors: MESS_E_ARG (NULL), MESS_E_UNSUPPORTED (a batch of
+ * more than one molecule), MESS_E_NOMEM. */
+int mess_hf_gradient(const mess_basis *basis, const double *D, const double *F, double schwarz_tol,
+                     double *grad, mess_stream stream);
+
+/* mess_hf_gradient at the handle's current density and Fock matrix, to be
+ * called after the step that reported convergence (Hartree-Fock only:
+ * MESS_E_UNSUPPORTED otherwise). */
+int mess_scf_gradient(const mess_scf *scf, double *grad, mess_stream stream);
+
 /* Divergence-guard stage of the run (0..3, see mess_scf_opts.no_guard) and
  * the energy rises counted in it.  Host outputs, either may be NULL. */
 int mess_scf_guard(const mess_scf *scf, int32_t *stage, int32_t *rises);

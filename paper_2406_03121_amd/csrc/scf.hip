@@ -1054,6 +1054,18 @@ int mess_scf_step(mess_scf *scf, double *energy, double *delta_e, double *resid,
     return scf_step_impl(scf, energy, delta_e, resid, converged, static_cast<hipStream_t>(stream));
 }
 
+int mess_scf_gradient(const mess_scf *scf, double *grad, mess_stream stream) {
+    if (!scf || !grad) {
+        set_error("mess_scf_gradient: NULL argument");
+        return MESS_E_ARG;
+    }
+    if (scf->opts.xc != MESS_XC_HF) {
+        set_error("mess_scf_gradient: the gradient is built for Hartree-Fock exchange");
+        return MESS_E_UNSUPPORTED;
+    }
+    return mess_hf_gradient(scf->basis, scf->D, scf->F, scf->opts.schwarz_tol, grad, stream);
+}
+
 int mess_scf_guard(const mess_scf *scf, int32_t *stage, int32_t *rises) {
     if (!scf) {
         set_error("mess_scf_guard: NULL handle");

@@ -33,7 +33,7 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune", "mess_scf_guard", "mess_batch_scf_guard", "mess_jk_noalloc", "mess_eri_quartets", "mess_boys", "mess_dmin_step",
+    "mess_kernel_form", "mess_autotune", "mess_hf_gradient", "mess_scf_gradient", "mess_scf_guard", "mess_batch_scf_guard", "mess_jk_noalloc", "mess_eri_quartets", "mess_boys", "mess_dmin_step",
     "mess_dmin_trial", "mess_dmin_eval",
 ]
 MESS_MLP_NPARAM = 115328
@@ -85,6 +85,8 @@ def lib():
             L.mess_scf_destroy.argtypes = [vp]
             L.mess_scf_destroy.restype = None
             L.mess_scf_guard.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.mess_hf_gradient.argtypes = [vp, vp, vp, f64, vp, vp]
+            L.mess_scf_gradient.argtypes = [vp, vp, vp]
             L.mess_batch_scf_guard.argtypes = [vp, vp]
         i64 = ctypes.c_int64
         f32 = ctypes.c_float
@@ -203,7 +205,9 @@ def mess_basis_create(Z, xyz, shell_atom, shell_l, shell_nprim, exps, coefs, cha
     h = ctypes.c_void_p()
     _check(lib().mess_basis_create(len(Z), pZ, pX, len(sl), pA, pL, pN, pE, pC, int(charge), ctypes.byref(h)),
            "mess_basis_create")
-    return Basis(h)
+    b = Basis(h)
+    b.n_atoms = len(Z)
+    return b
 
 
 def basis_from_molecule(mol) -> Basis:
@@ -229,7 +233,9 @@ def mess_batch_create(mols) -> Basis:
     h = ctypes.c_void_p()
     _check(lib().mess_batch_create(len(mols), pna, pns, pch, pZ, pX, pA, pL, pN, pE, pC, ctypes.byref(h)),
            "mess_batch_create")
-    return Basis(h)
+    b = Basis(h)
+    b.n_atoms = len(Z)
+    return b
 
 
 def mess_one_electron(basis: Basis, S=None, T=None, V=None, stream=None):
@@ -348,6 +354,22 @@ def mess_scf_guard(scf: Scf):
     st, r = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().mess_scf_guard(scf.handle, ctypes.byref(st), ctypes.byref(r)), "mess_scf_guard")
     return st.value, r.value
+
+
+def mess_hf_gradient(basis: Basis, D, F, schwarz_tol=0.0, stream=None):
+    """dE/dR (numpy [n_atoms, 3]) at the converged density D and Fock matrix F."""
+    g = np.zeros((basis.n_atoms, 3))
+    _check(lib().mess_hf_gradient(basis.handle, _ptr(D), _ptr(F), float(schwarz_tol),
+                                  g.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "mess_hf_gradient")
+    return g
+
+
+def mess_scf_gradient(scf: Scf, stream=None):
+    """dE/dR (numpy [n_atoms, 3]) of a converged SCF handle."""
+    g = np.zeros((scf.basis.n_atoms, 3))
+    _check(lib().mess_scf_gradient(scf.handle, g.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "mess_scf_gradient")
+    return g
 
 
 def mess_batch_scf_guard(scf):
