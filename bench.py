@@ -316,7 +316,7 @@ def small_block(mess, a, torch, n_seeds=64):
     """The 6-atom H/C/O s/p molecules (about 30 functions): latency of the
     full ERI tensor and of one direct J/K build (3 warm-ups, median of 10,
     seed 0), the 20-iteration plain Roothaan SCF (no DIIS, no guard) of every
-    seed.  Returns the figures and what the CPU-baseline leg checks."""
+    seed, and the analytic nuclear gradient at seed 0's converged SCF.  Returns the figures and what the CPU-baseline leg checks."""
     from mess_inputs import generators as G
 
     def median_ms(fn, reps=10, warm=3):
@@ -349,6 +349,14 @@ def small_block(mess, a, torch, n_seeds=64):
     jk_ms = median_ms(lambda: mess.mess_jk(B, D, J, K, schwarz_tol=0.0))
     scf_ms = median_ms(lambda: roothaan20(B), reps=5, warm=1)
     es = roothaan20(B)
+    # analytic nuclear gradient at the converged (DIIS) SCF
+    sc = mess.mess_scf_create(B, schwarz_tol=0.0, conv_tol=1e-10, diis_size=8)
+    for _ in range(100):
+        if mess.mess_scf_step(sc)[3]:
+            break
+    grad_ms = median_ms(lambda: mess.mess_scf_gradient(sc), reps=5, warm=1)
+    gnorm = float(np.abs(mess.mess_scf_gradient(sc)).max())
+    sc.close()
     torch.cuda.synchronize()
     check = (mol, eri.cpu().numpy(), J.cpu().numpy(), K.cpu().numpy(), es)
     B.close()
@@ -364,6 +372,7 @@ def small_block(mess, a, torch, n_seeds=64):
             "unique_shell_quartets": n_pairs * (n_pairs + 1) // 2,
             "eri_tensor_ms": eri_ms, "eri_per_s": N ** 4 / (eri_ms * 1e-3),
             "jk_ms": jk_ms, "scf20_ms": scf_ms, "energy_after_20_hartree": es[-1],
+            "gradient_ms": grad_ms, "max_abs_gradient": gnorm,
             "seeds": n_seeds, "scf20_all_seeds_s": t_all, "scf20_molecules_per_s": n_seeds / t_all}, check
 
 
