@@ -15,8 +15,9 @@ silent (all restated in the design notes):
 * Acceleration: optional Pulay DIIS over at most 8 Fock matrices, applied
   once two are stored, error vector X^T (F D S - S D F) X.
 * Convergence: |E_k - E_{k-1}| < conv_tol, or a fixed iteration count.
-* Divergence guard (on by default): a rise of the energy by more than
-  1e-6 Ha counts against the current stage; the second such rise since the
+* Divergence guard (on by default): from the 12th iteration on (index
+  k >= 12, so that DIIS may overshoot while it settles), a rise of the
+  energy by more than 1e-6 Ha counts against the current stage; the second such rise since the
   stage began moves to the next stage, and a non-finite energy jumps to the
   last.  Every stage change clears the DIIS history.  Stages: 0 DIIS;
   1 DIIS afresh; 2 DIIS with damping 0.5 (the next density mixed half and
@@ -132,6 +133,7 @@ class RHF:
 
     RISE_TOL = 1e-6
     RISES_PER_STAGE = 2
+    GUARD_FROM = 12
     DAMP = 0.5
 
     def run(self, D0=None, record=False):
@@ -157,7 +159,7 @@ class RHF:
                 up = 0
                 if not np.isfinite(E):
                     up = 3 - stage
-                elif e_prev is not None and E > e_prev + self.RISE_TOL:
+                elif e_prev is not None and k >= self.GUARD_FROM and E > e_prev + self.RISE_TOL:
                     rises += 1
                     if rises >= self.RISES_PER_STAGE:
                         up = 1

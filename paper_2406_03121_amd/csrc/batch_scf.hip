@@ -19,8 +19,8 @@
 // density stays the one that gave the converged energy.
 //
 // Divergence guard (per molecule, on unless opts.no_guard): the rule of the
-// single-molecule SCF.  An energy rise above kRiseTol counts against the
-// molecule's stage, the second rise in a stage moves it to the next, a
+// single-molecule SCF.  From iteration kGuardFrom on, an energy rise above
+// kRiseTol counts against the molecule's stage, the second rise in a stage moves it to the next, a
 // non-finite energy to the last; each change restarts its DIIS history
 // (the molecule then uses only the entries pushed since: the history ring
 // itself is shared).  Stage 2 mixes the next density half and half with the
@@ -45,6 +45,7 @@ constexpr int kSp2Rounds = 100;  // purification rounds per step (finished molec
 constexpr int kFarSteps = 2;
 constexpr double kRiseTol = 1e-6;
 constexpr int kRisesPerStage = 2;
+constexpr int kGuardFrom = 12;  // rises count from this iteration on
 constexpr double kDamp = 0.5;
 constexpr int kDeltaRun = 8;
 // Kinds of step (one captured graph each).
@@ -206,7 +207,8 @@ __global__ void k_bconv(int nmol, double tol, int guard, int nd, const BatchStat
         q.frozen = 1;
         return;
     }
-    if (guard && have_prev && de > kRiseTol && ++q.rises >= kRisesPerStage && q.stage < 3) {
+    if (guard && have_prev && bs->iter >= kGuardFrom && de > kRiseTol && ++q.rises >= kRisesPerStage &&
+        q.stage < 3) {
         q.stage += 1;
         q.rises = 0;
         q.hvalid = min(1, nd);

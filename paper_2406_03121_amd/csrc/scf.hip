@@ -93,11 +93,12 @@ constexpr int kRedBlocks = 256;
 // complete FP32 builds to an FP64 build plus FP32 builds of the density
 // change (Hartree).
 constexpr double kNearDe = 1e-1;
-// Divergence guard: an energy rise above kRiseTol (Hartree) counts against
+// Divergence guard: from iteration kGuardFrom on, an energy rise above kRiseTol (Hartree) counts against
 // the current stage, kRisesPerStage of them move to the next stage; from
 // stage 2 the next density is mixed with the current one with weight kDamp.
 constexpr double kRiseTol = 1e-6;
 constexpr int kRisesPerStage = 2;
+constexpr int kGuardFrom = 12;  // rises count from this iteration on (DIIS settles first)
 constexpr double kDamp = 0.5;
 
 // Hartree-Fock (Vx == NULL): F = H + J - K/2 with J = Gj + Gj^T,
@@ -770,7 +771,8 @@ static int scf_step_impl(mess_scf *st, double *energy, double *delta_e, double *
     if (conv) return MESS_OK;  // D stays the density that gave E_k
     // divergence guard: the second rise of the energy in a stage moves to
     // the next one (DIIS history dropped); the last stage restarts
-    if (guard && have_prev && de > kRiseTol && ++st->rises >= kRisesPerStage && st->stage < 3) {
+    if (guard && have_prev && st->iter - 1 >= kGuardFrom && de > kRiseTol && ++st->rises >= kRisesPerStage &&
+        st->stage < 3) {
         st->stage += 1;
         st->rises = 0;
         st->hist.clear();
