@@ -376,6 +376,48 @@ def small_block(mess, a, torch, n_seeds=64):
             "seeds": n_seeds, "scf20_all_seeds_s": t_all, "scf20_molecules_per_s": n_seeds / t_all}, check
 
 
+def dense_block(mess, a, torch, nd=64):
+    """J and K of 64 densities from the dense ERI tensor of a 105-function
+    molecule (batched seed 1000; tensor 970 MB in FP64), matrix-core and
+    vector forms, FP64 and FP32: time per J+K pair (median of 5 after 2
+    warm-ups, stream events) and algorithmic TFLOP/s (2 n^4 flops per
+    density for each of J and K) against the dense peaks (FP64 78.6, FP32
+    matrix cores 157.3, FP32 vector FMAs without packed math 78.6)."""
+    from mess_inputs import generators as G
+    mol = G.batched_molecule(1000)
+    B = mess.basis_from_molecule(mol)
+    n = B.nbf
+    out = {"workload": "mol3to20_spd/1000", "n_bf": n, "densities": nd}
+    rng = np.random.Generator(np.random.PCG64(3))
+    for prec, dt, name in ((mess.MESS_FP64, torch.float64, "fp64"), (mess.MESS_FP32, torch.float32, "fp32")):
+        eri = torch.zeros(n, n, n, n, dtype=torch.float64, device="cuda")
+        mess.mess_eri(B, eri, prec=prec, schwarz_tol=0.0)  # dense tensors are written as doubles
+        eri = eri.to(dt)
+        A = rng.normal(size=(nd, n, n)) / n
+        D = torch.tensor(A + A.transpose(0, 2, 1), dtype=dt, device="cuda")
+        J, K = torch.zeros_like(D), torch.zeros_like(D)
+        res = {}
+        for form, fname in ((mess.MESS_DENSE_MFMA, "mfma"), (mess.MESS_DENSE_VALU, "valu")):
+            for _ in range(2):
+                mess.mess_jk_dense(eri, n, D, J, K, prec=prec, form=form)
+            ts = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                mess.mess_jk_dense(eri, n, D, J, K, prec=prec, form=form)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            tf = 2 * 2.0 * n ** 4 * nd / (ms * 1e-3) / 1e12
+            peak = 157.3 if (name == "fp32" and fname == "mfma") else 78.6
+            res[fname] = {"ms": ms, "alg_tflops": tf, "frac": tf / peak}
+        out[name] = res
+        del eri
+    B.close()
+    return out
+
+
 def cpu_baseline_small(check):
     """CPU-baseline leg for the 6-atom molecule: the oracle's times (dense
     ERI tensor, one J/K contraction, 20 Roothaan iterations; one process) and
@@ -422,6 +464,7 @@ def main():
     ap.add_argument("--no-scan", action="store_true", help="skip the conformer scan")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of batch energies")
     ap.add_argument("--no-small", action="store_true", help="skip the 6-atom latency measurements")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-tensor J/K contraction")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "
@@ -565,6 +608,9 @@ def main():
     if not a.no_small:
         line["small_molecule"], checks["small_molecule"] = small_block(mess, a, torch)
         log(f"small molecule: {line['small_molecule']}")
+    if not a.no_dense:
+        line["dense_jk"] = dense_block(mess, a, torch)
+        log(f"dense jk: {line['dense_jk']}")
     if not a.no_lda:
         line["lda"] = lda_block(mess, mol, a, torch)
         log(f"lda: {line['lda']}")

@@ -159,6 +159,22 @@ int mess_basis_info(const mess_basis *basis, int32_t *nbf, int32_t *n_occ, doubl
  * device N x N buffer or NULL to skip. */
 int mess_one_electron(const mess_basis *basis, double *S, double *T, double *V, mess_stream stream);
 
+/* J and K of ndens densities from a dense ERI tensor (section 3: Coulomb
+ * and exchange matrices are contractions of the repulsion integrals with
+ * the density):
+ *   J[d][i][j] = sum_kl (ij|kl) D[d][k][l],  K[d][i][j] = sum_kl (ik|jl) D[d][k][l],
+ * as products over the composite indices (ij), (kl) of the n^2 x n^2 view
+ * of the tensor.  eri: device n^4 elements, row-major ((i n + j) n + k) n + l
+ * (mess_eri MESS_ERI_DENSE, full tensor); D, J, K: device [ndens][n][n]
+ * (J or K may be NULL).  prec MESS_FP64 (double arrays) or MESS_FP32 (float
+ * arrays, FP32 accumulation).  form MESS_DENSE_MFMA (matrix cores, 16x16x4
+ * products) or MESS_DENSE_VALU (vector FMAs, the same tiling).
+ * Asynchronous.  Errors: MESS_E_ARG (NULL eri or D, n < 1, ndens < 1,
+ * unknown prec or form). */
+enum { MESS_DENSE_VALU = 0, MESS_DENSE_MFMA = 1 };
+int mess_jk_dense(const void *eri, int32_t n, int32_t ndens, const void *D, void *J, void *K, int32_t prec,
+                  int32_t form, mess_stream stream);
+
 /* Boys function F_j(T) = int_0^1 u^(2j) exp(-T u^2) du, j = 0..m (section 3:
  * every closed-form repulsion integral is a sum over it), by the device
  * routines of the integral kernels, using the basis handle's tables:

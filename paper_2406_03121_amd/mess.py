@@ -33,7 +33,7 @@ EXPORTED = [
     "mess_mlp_create", "mess_mlp_destroy", "mess_mlp_params", "mess_mlp_forward", "mess_mlp_grad",
     "mess_mlp_train_step", "mess_guess_rows", "mess_guess_features", "mess_guess_targets",
     "mess_guess_assemble", "mess_guess_project", "mess_guess_judge",
-    "mess_kernel_form", "mess_autotune", "mess_hf_gradient", "mess_scf_gradient", "mess_scf_guard", "mess_batch_scf_guard", "mess_jk_noalloc", "mess_eri_quartets", "mess_boys", "mess_dmin_step",
+    "mess_kernel_form", "mess_autotune", "mess_hf_gradient", "mess_scf_gradient", "mess_scf_guard", "mess_batch_scf_guard", "mess_jk_noalloc", "mess_jk_dense", "mess_eri_quartets", "mess_boys", "mess_dmin_step",
     "mess_dmin_trial", "mess_dmin_eval",
 ]
 MESS_MLP_NPARAM = 115328
@@ -73,6 +73,7 @@ def lib():
         L.mess_jk_noalloc.argtypes = [vp, vp, vp, vp, i32, f64, vp]
         L.mess_eri_quartets.argtypes = [vp, f64, vp, vp]
         L.mess_boys.argtypes = [vp, i32, i32, i32, vp, ctypes.c_int64, vp, vp]
+        L.mess_jk_dense.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp]
         L.mess_dmin_step.argtypes = [vp, f64, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
         L.mess_dmin_trial.argtypes = [vp, vp, vp]
         L.mess_dmin_eval.argtypes = [vp, vp, ctypes.POINTER(f64), vp, vp]
@@ -258,6 +259,16 @@ def mess_eri_quartets(basis: Basis, schwarz_tol=0.0):
     _check(lib().mess_eri_quartets(basis.handle, float(schwarz_tol), None, shells.ctypes.data_as(ctypes.c_void_p)),
            "mess_eri_quartets")
     return counts, shells[:int(counts.sum())]
+
+
+MESS_DENSE_VALU, MESS_DENSE_MFMA = 0, 1
+
+
+def mess_jk_dense(eri, n, D, J=None, K=None, prec=MESS_FP64, form=MESS_DENSE_MFMA, stream=None):
+    """J, K [ndens, n, n] of the densities D [ndens, n, n] from the dense tensor eri (n^4)."""
+    nd = D.numel() // (n * n)
+    _check(lib().mess_jk_dense(_ptr(eri), int(n), int(nd), _ptr(D), _ptr(J), _ptr(K), int(prec), int(form),
+                               _stream(stream)), "mess_jk_dense")
 
 
 def mess_boys(basis: Basis, T, F, m, form=0, prec=MESS_FP64, stream=None):
