@@ -33,6 +33,14 @@ COOP_CLASSES = {(2, 2), (4, 2), (4, 4), (5, 2), (5, 3), (5, 4), (5, 5)}
 UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
 # primitive-lane kernels (plane.hip), one object per class and precision
 PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (4, 4), (4, 2), (2, 2)]
+# recursion passes over ket subtrees (fewer live values for the largest;
+# measured per build on the 60-atom cluster: (dd|dp) 8.76 -> 4.52 ms,
+# (dp|dp) 1.56 -> 1.44, (dd|pp) 1.15 -> 1.06)
+PLANE_PASSES = {(5, 4): 3, (5, 3): 3, (5, 2): 2, (4, 4): 3}
+# waves per SIMD asked of the compiler (default: its own choice, one wave
+# with 512 registers here); (dd|ds) with 3 passes runs faster at two waves
+# despite 260 B of spill per lane (7.07 -> 5.65 ms)
+PLANE_WAVES = {(5, 3): 2}
 # wave-per-primitive-quartet kernels (wave.hip)
 WAVE_CLASSES = [(5, 5), (5, 4), (5, 3)]
 
@@ -54,7 +62,9 @@ def _units():
             for cb, ck in PLANE_CLASSES:
                 for real in ("double", "float"):
                     units.append((src, os.path.join(OBJ, f"plane_{cb}{ck}_{real}.o"),
-                                  [f"-DMESS_PCB={cb}", f"-DMESS_PCK={ck}", f"-DMESS_PREAL={real}"]))
+                                  [f"-DMESS_PCB={cb}", f"-DMESS_PCK={ck}", f"-DMESS_PREAL={real}",
+                                   f"-DMESS_PLANE_PASSES={PLANE_PASSES.get((cb, ck), 1)}"] +
+                                  ([f"-DMESS_PLANE_WAVES={PLANE_WAVES[(cb, ck)]}"] if (cb, ck) in PLANE_WAVES else [])))
         else:
             units.append((src, os.path.join(OBJ, name + ".o"), []))
     # heaviest classes first so the parallel build finishes sooner

@@ -263,13 +263,38 @@ __host__ __device__ constexpr KetDfs<LCD> make_ket_dfs() {
 template <int LC, int LCD>
 inline constexpr KetDfs<LCD> kKetDfs = make_ket_dfs<LC, LCD>();
 
+// Second-level subtrees of the depth-first ket tree: f with |f| >= 2 is
+// built from the |f| = 2 component holding its first two directions in the
+// order x, y, z; groups xx xy xz yy yz zz = bits 0..5.  A |f| = 1 component
+// (p_x, p_y, p_z) is the parent of the groups below it: bits 0-2, 3-4, 5.
+__host__ __device__ constexpr int ket_dir_n(const Cart c, int k) {
+    // k-th direction (0-based) of f listed as x...x y...y z...z
+    return k < c.x ? 0 : (k < c.x + c.y ? 1 : 2);
+}
+__host__ __device__ constexpr int ket_group_mask(const Cart c) {
+    if (c.l() == 0) return 63;
+    const int d1 = ket_dir_n(c, 0);
+    if (c.l() == 1) return d1 == 0 ? 7 : (d1 == 1 ? 24 : 32);
+    const int d2 = ket_dir_n(c, 1);
+    constexpr int base[3] = {0, 3, 5};
+    return 1 << (base[d1] + d2 - d1);
+}
+
 // One primitive quartet: the recursions above with the ket components in
 // the depth-first order; every output [e0|f0] (la <= |e| <= la+lb,
 // lc <= |f| <= lc+ld) is handed to out(integral_constant<x>, value) as soon
 // as it is final, in the order rank(f) * NEA + (e - E0), where
 // x = (f - F0) * NEA + (e - E0).  AC = A - C (bra and ket anchor centres);
 // P - Q = AC + PA - QC is exact zero when all four shells share one atom.
-template <class Dm, typename Real, class Out>
+// SUB (a mask of the second-level groups above) restricts the ket recursion
+// to some subtrees of the depth-first tree: a class may be evaluated in
+// passes over disjoint group sets, each repeating the base and e-side
+// recursion (and the |f| = 1 parents it needs), so that one pass's
+// intermediates are dead before the next starts (fewer live values for the
+// largest classes).  A component is emitted by the pass holding the lowest
+// group below it, so with passes in increasing group order the outputs keep
+// their depth-first order.
+template <class Dm, typename Real, int SUB = 63, class Out>
 __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
                                                  const Real (&AC)[3], const BoysTabs &bt, Out &&out) {
     constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LC = Dm::LC, LCD = Dm::LCD;
@@ -311,7 +336,9 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
     }
     auto emit_f = [&](auto FI) {
         constexpr int f = decltype(FI)::value;
-        if constexpr (cart_of(f).l() >= LC) {
+        constexpr int gm = ket_group_mask(cart_of(f));
+        constexpr bool mine = (SUB & (gm & -gm)) != 0;  // lowest group below f
+        if constexpr (cart_of(f).l() >= LC && mine) {
             static_for<Dm::E0, NE>([&](auto EI) {
                 constexpr int e = decltype(EI)::value;
                 out(std::integral_constant<int, (f - Dm::F0) * Dm::NEA + (e - Dm::E0)>{}, V[f][e][0]);
@@ -326,7 +353,7 @@ __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const Pri
         const Real oo2q = Real(0.5) * Q.rp, rho_q = p * rpq, oo2pq = Real(0.5) * rpq;
         static_for<0, NF>([&](auto SI) {
             constexpr int f = kKetDfs<LC, LCD>.seq[decltype(SI)::value];
-            if constexpr (f > 0) {
+            if constexpr (f > 0 && (SUB & ket_group_mask(cart_of(f))) != 0) {
                 constexpr Cart cf = cart_of(f);
                 constexpr int nf = cf.l();
                 constexpr int j = last_dir(cf);

@@ -59,9 +59,23 @@ __constant__ PlaneBlocks<Dm, NACC> kPlaneBlocksDev = make_plane_blocks<Dm, NACC>
 
 template <class Dm>
 inline constexpr int kPlaneBlockSize = 32;
+// recursion passes per primitive quartet over ket subtrees: 2: x | y z;
+// 3: x | y | z (finer splits of the x subtree measured no fewer spills)
+#ifndef MESS_PLANE_PASSES
+#define MESS_PLANE_PASSES 1
+#endif
+template <class Dm>
+inline constexpr int kPlanePasses = MESS_PLANE_PASSES;
+
+// MESS_PLANE_WAVES=n asks for n waves per SIMD (register budget 512 / n)
+#if defined(MESS_PLANE_WAVES)
+#define MESS_PLANE_OCC __attribute__((amdgpu_waves_per_eu(MESS_PLANE_WAVES, MESS_PLANE_WAVES)))
+#else
+#define MESS_PLANE_OCC
+#endif
 
 template <class Dm, int MODE, typename Real>
-__global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
+__global__ void __launch_bounds__(64) MESS_PLANE_OCC k_plane(CoopArgs A, const PairInfo *__restrict__ pairs, int bra_off,
                                               int ket_off, int nbra, int same_class,
                                               const int64_t *__restrict__ rowstart, const int2 *__restrict__ rowmap, int64_t total,
                                               const PrimPairT<Real> *__restrict__ pp, BoysTabs bt,
@@ -132,10 +146,27 @@ __global__ void __launch_bounds__(64) k_plane(CoopArgs A, const PairInfo *__rest
                     part[b] += vb[b][0];
                 }
             };
-            if constexpr (SW)
-                prim_quartet<Dr, Real>(Q, P, AC, bt, emit);
-            else
-                prim_quartet<Dr, Real>(P, Q, AC, bt, emit);
+            // classes whose recursion outgrows the registers run it in
+            // passes over disjoint subtrees of the ket tree (outputs stay in
+            // order, so the reduction blocks are unchanged)
+            auto run = [&](auto SUBC) {
+                constexpr int SUB = decltype(SUBC)::value;
+                if constexpr (SW)
+                    prim_quartet<Dr, Real, SUB>(Q, P, AC, bt, emit);
+                else
+                    prim_quartet<Dr, Real, SUB>(P, Q, AC, bt, emit);
+            };
+            // passes over second-level ket groups (xx xy xz | yy yz | zz)
+            if constexpr (kPlanePasses<Dm> == 2) {
+                run(std::integral_constant<int, 7>{});
+                run(std::integral_constant<int, 56>{});
+            } else if constexpr (kPlanePasses<Dm> == 3) {
+                run(std::integral_constant<int, 7>{});
+                run(std::integral_constant<int, 24>{});
+                run(std::integral_constant<int, 32>{});
+            } else {
+                run(std::integral_constant<int, 63>{});
+            }
         }
         static_for<0, NPER>([&](auto I) {
             const int ps = BS * decltype(I)::value + lane;
