@@ -32,7 +32,7 @@ CLASSES = [(cb, ck) for cb in range(6) for ck in range(cb + 1)]
 COOP_CLASSES = {(2, 2), (4, 2), (4, 4), (5, 2), (5, 3), (5, 4), (5, 5)}
 UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
 # primitive-lane kernels (plane.hip), one object per class and precision
-PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (4, 4), (4, 2), (2, 2)]
+PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (5, 1), (4, 4), (4, 2), (2, 2)]
 # recursion passes over ket subtrees (fewer live values for the largest;
 # measured per build on the 60-atom cluster: (dd|dp) 8.76 -> 4.52 ms,
 # (dp|dp) 1.56 -> 1.44, (dd|pp) 1.15 -> 1.06)

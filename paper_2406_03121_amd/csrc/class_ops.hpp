@@ -26,6 +26,10 @@ struct ClassLaunch {
     int nmax = 0;                // largest molecule dimension (LDS rows)
 };
 
+// Direct J/K of class (cb, ck) through its cooperative tables (primitive-
+// lane, wave or table-driven kernel; coop.hip).
+int coop_jk(int cb, int ck, const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec);
+
 template <int CB, int CK>
 struct ClassOps {
     // Q[off + i] for the n pairs of class CB (requires CB == CK).

@@ -449,7 +449,7 @@ static std::pair<double, double> count_flops(int cb, int ck, bool swapped) {
 
 void class_flops(int cb, int ck, double *per_prim, double *per_quartet_jk, int prec) {
     const int la = pair_class_la(cb), lb = pair_class_lb(cb), lc = pair_class_la(ck), ld = pair_class_lb(ck);
-    const bool swapped = coop_class(cb, ck) && class_form(cb, ck, prec) == kFormPlane && swap_vrr(la, lb, lc, ld);
+    const bool swapped = plane_compiled(cb, ck) && class_form(cb, ck, prec) == kFormPlane && swap_vrr(la, lb, lc, ld);
     std::lock_guard<std::mutex> lk(g_flop_mutex);
     auto key = std::make_pair(cb * 8 + (swapped ? 1 : 0), ck);
     auto it = g_flops.find(key);
@@ -469,7 +469,7 @@ bool coop_class(int cb, int ck) {
 // True when class (cb, ck) needs no cooperative step tables or they are
 // already on the device (nothing left to allocate for its launches).
 bool coop_program_cached(int cb, int ck) {
-    if (!coop_class(cb, ck)) return true;
+    if (!coop_class(cb, ck) && !(plane_compiled(cb, ck) && class_form(cb, ck, MESS_FP64) == kFormPlane)) return true;
     std::lock_guard<std::mutex> lk(g_prog_mutex);
     return g_programs.count(std::make_pair(cb, ck)) != 0;
 }
@@ -642,6 +642,7 @@ static void launch_plane(int mode, int cb, int ck, int prec, const CoopArgs &A, 
     MESS_PL(5, 4)
     MESS_PL(5, 3)
     MESS_PL(5, 2)
+    MESS_PL(5, 1)
     MESS_PL(4, 4)
     MESS_PL(4, 2)
     MESS_PL(2, 2)

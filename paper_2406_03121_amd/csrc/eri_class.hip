@@ -56,6 +56,9 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
                                    int prec) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
+    // the primitive-lane form, where it is built and the form table picks it
+    if (plane_compiled(MESS_CB, MESS_CK) && class_form(MESS_CB, MESS_CK, prec) == kFormPlane)
+        return coop_jk(MESS_CB, MESS_CK, L, D, Gj, Gk, prec);
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
     if constexpr (MESS_CB != 2 && MESS_CK != 2 && (MESS_CB <= 3 || MESS_CK == 0)) {
         // one 256-thread block per bra segment, K rows of the bra functions

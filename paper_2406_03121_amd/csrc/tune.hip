@@ -34,7 +34,10 @@ int g_form[2][kNumClasses] = {};  // [precision][class]; kFormAuto: built-in def
 }  // namespace
 
 bool plane_compiled(int cb, int ck) {
-    return (cb == 5 && ck >= 2 && ck <= 4) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
+    // (dd|ps) is the one lane-kernel class the primitive-lane form beats
+    // (3.25 -> 2.75 ms per 60-atom build); (dp|ps), (dp|ds) and (ds|pp)
+    // measured 1.4-2x slower in it
+    return (cb == 5 && ck >= 1 && ck <= 4) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 2 && ck == 2);
 }
 
 bool wave_compiled(int cb, int ck) { return cb == 5 && ck >= 3; }
@@ -52,6 +55,7 @@ bool form_valid(int cb, int ck, int form, int prec) {
                (form == kFormWave && wave_compiled(cb, ck));
     if (form == kFormLane) return true;
     if (form == kFormRows) return rows_compiled(cb, ck);
+    if (form == kFormPlane) return plane_compiled(cb, ck);
     return false;
 }
 
@@ -65,6 +69,7 @@ static int default_form(int cb, int ck, int prec) {
         if (c == 0 || c == 1 || c == 3 || c == 4 || c == 8 || c == 10 || c == 11 || c == 15) return kFormFp64;
     }
     if (coop_class(cb, ck)) return (cb == 5 && ck == 5) ? kFormWave : kFormPlane;
+    if (cb == 5 && ck == 1 && prec == MESS_FP64) return kFormPlane;
     return rows_compiled(cb, ck) ? kFormRows : kFormLane;
 }
 
