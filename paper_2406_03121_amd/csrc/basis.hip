@@ -265,6 +265,10 @@ int fill_class_launch(const mess_basis *B, const ClassList &cl, hipStream_t s, C
     L.rowmap = cl.d_rowmap;
     L.segs = cl.d_segs;
     L.nseg = cl.d_segs ? cl.nseg : 0;
+    L.groups = cl.d_groups;
+    L.tiles = cl.d_tiles;
+    L.grows = cl.d_grows;
+    L.ngroups = cl.d_groups ? cl.ngroups : 0;
     L.nmax = B->nbf_max;
     L.total = cl.total;
     return MESS_OK;
@@ -292,6 +296,9 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
             const int boff = B->pair_class_off[cb], koff = B->pair_class_off[ck];
             const bool same = cb == ck;
             cl.h_rowstart.assign(1, 0);
+            const int G = kGroupBras[cb];
+            std::vector<int4> groups, tiles;
+            std::vector<int> grows;
             for (int m = 0; m < B->n_mol; ++m) {
                 // buckets of equal primitive count in the molecule's ket segment
                 std::vector<int2> bk;
@@ -303,6 +310,7 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                     k = e;
                 }
                 const int i0 = B->seg_off[cb][m], i1 = i0 + B->seg_cnt[cb][m];
+                const int mr0 = (int)cl.h_rowmap.size();
                 for (int i = i0; i < i1; ++i) {
                     const double qi = Q[boff + i];
                     const int64_t nbp = P[boff + i].npp;
@@ -323,6 +331,41 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                         cl.prim_quartets += nbp * cnt * P[koff + b.x].npp;
                     }
                 }
+                if (G > 1) {
+                    // rows of bra i: [first[i - i0], last[i - i0]) in bucket order
+                    const int mr1 = (int)cl.h_rowmap.size();
+                    std::vector<int> first(i1 - i0, -1), last(i1 - i0, -1);
+                    for (int r = mr0; r < mr1; ++r) {
+                        const int k = cl.h_rowmap[r].x - i0;
+                        if (first[k] < 0) first[k] = r;
+                        last[k] = r + 1;
+                    }
+                    for (int g0 = i0; g0 < i1; g0 += G) {
+                        const int ng = std::min(G, i1 - g0), t0 = (int)tiles.size();
+                        int ptr[8], kofs = 0;
+                        for (int g = 0; g < ng; ++g) ptr[g] = first[g0 + g - i0];
+                        for (const int2 &b : bk) {
+                            const int rb = (int)grows.size();
+                            int64_t maxc = 0;
+                            for (int g = 0; g < G; ++g) {
+                                int r = -1;
+                                if (g < ng && ptr[g] >= 0 && ptr[g] < last[g0 + g - i0] &&
+                                    cl.h_rowmap[ptr[g]].y == b.x) {
+                                    r = ptr[g]++;
+                                    maxc = std::max(maxc, cl.h_rowstart[r + 1] - cl.h_rowstart[r]);
+                                }
+                                grows.push_back(r);
+                            }
+                            if (maxc == 0) {
+                                grows.resize(rb);
+                                continue;
+                            }
+                            tiles.push_back(make_int4(rb, b.x, (int)maxc, kofs));
+                            kofs += (int)maxc;
+                        }
+                        if ((int)tiles.size() > t0) groups.push_back(make_int4(t0, (int)tiles.size(), g0, ng));
+                    }
+                }
             }
             cl.nrow = (int)cl.h_rowmap.size();
             cl.total = cl.h_rowstart.back();
@@ -340,6 +383,25 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
                     r0 = r1;
                 }
             cl.nseg = (int)segs.size();
+            if (cl.total >= ((int64_t)1 << 31)) groups.clear();
+            cl.ngroups = (int)groups.size();
+            if (cl.ngroups > 0 &&
+                (hipMalloc(&cl.d_groups, sizeof(int4) * groups.size()) != hipSuccess ||
+                 hipMalloc(&cl.d_tiles, sizeof(int4) * tiles.size()) != hipSuccess ||
+                 hipMalloc(&cl.d_grows, sizeof(int) * grows.size()) != hipSuccess ||
+                 hipMemcpy(cl.d_groups, groups.data(), sizeof(int4) * groups.size(), hipMemcpyHostToDevice) !=
+                     hipSuccess ||
+                 hipMemcpy(cl.d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice) !=
+                     hipSuccess ||
+                 hipMemcpy(cl.d_grows, grows.data(), sizeof(int) * grows.size(), hipMemcpyHostToDevice) !=
+                     hipSuccess)) {
+                hipFree(cl.d_groups);
+                hipFree(cl.d_tiles);
+                hipFree(cl.d_grows);
+                set_error("hipMalloc(work list groups) failed");
+                rc = MESS_E_NOMEM;
+                break;
+            }
             if (cl.nrow > 0) {
                 if (hipMalloc(&cl.d_rowstart, sizeof(int64_t) * (cl.nrow + 1)) != hipSuccess ||
                     hipMalloc(&cl.d_rowmap, sizeof(int2) * cl.nrow) != hipSuccess ||
@@ -365,6 +427,9 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
             if (cl.d_rowmap) hipFree(cl.d_rowmap);
             if (cl.d_segs) hipFree(cl.d_segs);
+            hipFree(cl.d_groups);
+            hipFree(cl.d_tiles);
+            hipFree(cl.d_grows);
         }
         delete W;
         return rc;
@@ -381,6 +446,9 @@ static void free_basis(mess_basis *B) {
             if (cl.d_rowstart) hipFree(cl.d_rowstart);
             if (cl.d_rowmap) hipFree(cl.d_rowmap);
             if (cl.d_segs) hipFree(cl.d_segs);
+            hipFree(cl.d_groups);
+            hipFree(cl.d_tiles);
+            hipFree(cl.d_grows);
         }
         delete kv.second;
     }

@@ -24,6 +24,10 @@ struct ClassLaunch {
     const int4 *segs = nullptr;  // {first row, first quartet, end quartet, end row}
     int nseg = 0;
     int nmax = 0;                // largest molecule dimension (LDS rows)
+    // grouped stored digestion (NULL: by segments)
+    const int4 *groups = nullptr, *tiles = nullptr;
+    const int *grows = nullptr;
+    int ngroups = 0;
 };
 
 // Direct J/K of class (cb, ck) through its cooperative tables (primitive-

@@ -113,6 +113,25 @@ int ClassOps<MESS_CB, MESS_CK>::jk_stored(const ClassLaunch &L, const void *base
                                           double *Gj, double *Gk) {
     using Dm = ClassOf<MESS_CB, MESS_CK>;
     if (L.total <= 0) return MESS_OK;
+    constexpr int G = kGroupBras[MESS_CB];
+    if constexpr (G > 1) {
+        // groups of G bras: J[c,d] reduced over the group before its atomic
+        const size_t lg = sizeof(double) * ((size_t)G * (Dm::NA + Dm::NB) * L.nmax + G * Dm::NA * Dm::NB) +
+                          sizeof(int) * G * (Dm::NA + Dm::NB);
+        if (L.groups && L.ngroups > 0 && lg <= 48 * 1024) {
+            const unsigned g = (unsigned)std::min(L.ngroups, 1 << 20);
+            if (prec == MESS_FP32)
+                hipLaunchKernelGGL((k_jk_group<Dm, float, G>), dim3(g), dim3(256), lg, L.stream, L.pairs, L.bra_off,
+                                   L.ket_off, L.same_class, L.rowstart, L.groups, L.ngroups, L.tiles, L.grows,
+                                   static_cast<const float *>(base), L.total, D, Gj, Gk);
+            else
+                hipLaunchKernelGGL((k_jk_group<Dm, double, G>), dim3(g), dim3(256), lg, L.stream, L.pairs, L.bra_off,
+                                   L.ket_off, L.same_class, L.rowstart, L.groups, L.ngroups, L.tiles, L.grows,
+                                   static_cast<const double *>(base), L.total, D, Gj, Gk);
+            MESS_LAUNCH_CHECK();
+            return MESS_OK;
+        }
+    }
     const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
     if (L.segs && L.nseg > 0 && lds <= 48 * 1024) {
         const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);

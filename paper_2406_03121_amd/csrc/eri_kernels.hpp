@@ -332,6 +332,172 @@ __global__ void __launch_bounds__(256) k_jk_rows(const PairInfo *__restrict__ pa
     }
 }
 
+// J/K from stored blocks by groups of G consecutive bras of one molecule
+// (sorted neighbours: similar primitive counts and Schwarz factors, so their
+// ket prefixes nearly coincide).  A group's quartets are laid out as tiles,
+// one per ket bucket, each a G x (longest row) rectangle whose rows are the
+// bras' work-list rows; one 256-thread block takes a group, a thread a ket
+// of a tile, and the thread loops over the G bras.  Every sum that indexes
+// a ket alone (J[c,d]) is then reduced over the G bras in registers before
+// its one global atomic; sums of a bra (J[a,b]) stay in registers for the
+// whole group, the exchange rows of the G bras' functions in LDS (flushed
+// once per group).  The ket's pair record and density block are read once
+// per G quartets.  Store reads stay coalesced: consecutive threads take
+// consecutive kets of one row.
+template <class Dm, typename Real, int G>
+__global__ void __launch_bounds__(256) k_jk_group(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                  int same_class, const int64_t *__restrict__ rowstart,
+                                                  const int4 *__restrict__ groups, int ngroups,
+                                                  const int4 *__restrict__ tiles, const int *__restrict__ grows,
+                                                  const Real *__restrict__ base, int64_t total,
+                                                  const double *__restrict__ Dall, double *__restrict__ Gjall,
+                                                  double *__restrict__ Gkall) {
+    constexpr int NA = Dm::NA, NB = Dm::NB, NC = Dm::NC, ND = Dm::ND, NR = NA + NB;
+    extern __shared__ double lds[];
+    for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+        const int4 gr = groups[gi];
+        const int ng = gr.w;
+        const PairInfo first = pairs[bra_off + gr.z];
+        const int N = first.mN;
+        const double *D = Dall + first.moff;
+        double *Gj = Gjall ? Gjall + first.moff : nullptr;
+        double *Gk = Gkall ? Gkall + first.moff : nullptr;
+        // LDS: exchange rows of bra g (its a functions, then its b
+        // functions) at (g NR + row) N, J[a,b] of the bras after them, then
+        // the function index of every row slot
+        double *Jab = lds + G * NR * N;
+        int *rowfn = reinterpret_cast<int *>(Jab + G * NA * NB);
+        for (int e = threadIdx.x; e < G * NR * N + G * NA * NB; e += 256) lds[e] = 0.0;
+        int a0[G], b0[G], bi[G];
+        Real fb[G], Dab[G][NA][NB], jab[G][NA][NB];
+        static_for<0, G>([&](auto Gi) {
+            constexpr int g = decltype(Gi)::value;
+            const bool on = g < ng;
+            const PairInfo p = pairs[bra_off + gr.z + (on ? g : 0)];
+            a0[g] = p.bfa;
+            b0[g] = p.bfb;
+            bi[g] = on ? gr.z + g : -1;
+            fb[g] = on ? (p.sa == p.sb ? Real(0.5) : Real(1)) : Real(0);
+            static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                Dab[g][A][B] = Real(D[(int64_t)(a0[g] + A) * N + b0[g] + B]);
+                jab[g][A][B] = Real(0);
+            }); });
+            if ((int)threadIdx.x < NR) rowfn[g * NR + threadIdx.x] = threadIdx.x < NA ? a0[g] + threadIdx.x : b0[g] + threadIdx.x - NA;
+        });
+        __syncthreads();
+        const int4 lt = tiles[gr.y - 1];
+        const int nk = lt.w + lt.z;
+        int t = gr.x;
+        int4 tl = tiles[t];
+        int64_t rs[G];
+        int cnt[G];
+        auto load_tile = [&]() {
+            static_for<0, G>([&](auto Gi) {
+                constexpr int g = decltype(Gi)::value;
+                const int r = grows[tl.x + g];
+                rs[g] = r >= 0 ? rowstart[r] : 0;
+                cnt[g] = r >= 0 ? (int)(rowstart[r + 1] - rs[g]) : 0;
+            });
+        };
+        load_tile();
+        for (int idx = threadIdx.x; idx < nk; idx += 256) {
+            if (t + 1 < gr.y && tiles[t + 1].w <= idx) {
+                do ++t; while (t + 1 < gr.y && tiles[t + 1].w <= idx);
+                tl = tiles[t];
+                load_tile();
+            }
+            const int k = idx - tl.w;
+            const int j = tl.y + k;
+            const PairInfo ket = pairs[ket_off + j];
+            const int c0 = ket.bfa, d0 = ket.bfb;
+            const Real fk = ket.sa == ket.sb ? Real(0.5) : Real(1);
+            Real Dcd[NC][ND], jcd[NC][ND];
+            static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+                Dcd[C][Dd] = Real(D[(int64_t)(c0 + C) * N + d0 + Dd]);
+                jcd[C][Dd] = Real(0);
+            }); });
+            static_for<0, G>([&](auto Gi) {
+                constexpr int g = decltype(Gi)::value;
+                if (k < cnt[g]) {
+                    const int64_t q = rs[g] + k;
+                    Real out[Dm::NOUT];
+                    static_for<0, Dm::NOUT>([&](auto I) { out[I] = base[(int64_t)decltype(I)::value * total + q]; });
+                    Real fac = fb[g] * fk;
+                    if (same_class && bi[g] == j) fac *= Real(0.5);
+                    auto O = [&](int a, int b, int c, int d) -> Real { return out[((a * NB + b) * NC + c) * ND + d]; };
+                    if (Gj) {
+                        static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                            Real s = Real(0);
+                            static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dcd[C][Dd]; }); });
+                            jab[g][A][B] += fac * s;
+                        }); });
+                        static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+                            Real s = Real(0);
+                            static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) { s += O(A, B, C, Dd) * Dab[g][A][B]; }); });
+                            jcd[C][Dd] += fac * s;
+                        }); });
+                    }
+                    if (Gk) {
+                        auto Dv = [&](int r, int c) -> Real { return Real(D[(int64_t)r * N + c]); };
+                        double *Ka = lds + g * NR * N, *Kb = Ka + NA * N;
+                        Real Dbd[NB][ND], Dad[NA][ND], Dbc[NB][NC], Dac[NA][NC];
+                        static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { Dbd[B][Dd] = Dv(b0[g] + B, d0 + Dd); }); });
+                        static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { Dad[A][Dd] = Dv(a0[g] + A, d0 + Dd); }); });
+                        static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { Dbc[B][C] = Dv(b0[g] + B, c0 + C); }); });
+                        static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { Dac[A][C] = Dv(a0[g] + A, c0 + C); }); });
+                        static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) {
+                            Real s = Real(0);
+                            static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dbd[B][Dd]; }); });
+                            __hip_atomic_fetch_add(&Ka[A * N + c0 + C], (double)(fac * s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }); });
+                        static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) {
+                            Real s = Real(0);
+                            static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) { s += O(A, B, C, Dd) * Dad[A][Dd]; }); });
+                            __hip_atomic_fetch_add(&Kb[B * N + c0 + C], (double)(fac * s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }); });
+                        static_for<0, NA>([&](auto A) { static_for<0, ND>([&](auto Dd) {
+                            Real s = Real(0);
+                            static_for<0, NB>([&](auto B) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dbc[B][C]; }); });
+                            __hip_atomic_fetch_add(&Ka[A * N + d0 + Dd], (double)(fac * s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }); });
+                        static_for<0, NB>([&](auto B) { static_for<0, ND>([&](auto Dd) {
+                            Real s = Real(0);
+                            static_for<0, NA>([&](auto A) { static_for<0, NC>([&](auto C) { s += O(A, B, C, Dd) * Dac[A][C]; }); });
+                            __hip_atomic_fetch_add(&Kb[B * N + d0 + Dd], (double)(fac * s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }); });
+                    }
+                }
+            });
+            if (Gj)
+                static_for<0, NC>([&](auto C) { static_for<0, ND>([&](auto Dd) {
+                    if (jcd[C][Dd] != Real(0)) unsafeAtomicAdd(&Gj[(int64_t)(c0 + C) * N + d0 + Dd], 2.0 * (double)jcd[C][Dd]);
+                }); });
+        }
+        if (Gj)
+            static_for<0, G>([&](auto Gi) {
+                constexpr int g = decltype(Gi)::value;
+                static_for<0, NA>([&](auto A) { static_for<0, NB>([&](auto B) {
+                    double v = (double)jab[g][A][B];
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                    if ((threadIdx.x & 63) == 0)
+                        __hip_atomic_fetch_add(&Jab[(g * NA + A) * NB + B], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }); });
+            });
+        __syncthreads();
+        if (Gk)
+            for (int e = threadIdx.x; e < ng * NR * N; e += 256) {
+                const double v = lds[e];
+                if (v != 0.0) unsafeAtomicAdd(&Gk[(int64_t)rowfn[e / N] * N + e % N], v);
+            }
+        if (Gj)
+            for (int e = threadIdx.x; e < ng * NA * NB; e += 256) {
+                const int g = e / (NA * NB), ab = e % (NA * NB);
+                unsafeAtomicAdd(&Gj[(int64_t)rowfn[g * NR + ab / NB] * N + rowfn[g * NR + NA + ab % NB]], 2.0 * Jab[e]);
+            }
+        __syncthreads();  // LDS reused by the next group
+    }
+}
+
 // J/K from stored blocks for classes whose block is too large to hold in
 // registers: the same bra-row segments (K rows of the bra functions in
 // LDS, J[a,b] in registers, one flush per segment), with the block of each

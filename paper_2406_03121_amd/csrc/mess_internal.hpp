@@ -178,8 +178,25 @@ struct ClassList {
     // the list has 2^31 quartets or more
     int4 *d_segs = nullptr;
     int nseg = 0;
+    // groups of kGroupBras[cb] consecutive bras of one molecule for the
+    // grouped stored digestion: per group {first tile, end tile, first bra,
+    // bras}; per tile (one ket bucket of the group) {offset of its
+    // kGroupBras[cb] row indices in d_grows (-1: no row), first ket index,
+    // longest row, ket offset of the tile within its group}; NULL when
+    // kGroupBras[cb] is 1 or the list has 2^31 quartets or more
+    int4 *d_groups = nullptr, *d_tiles = nullptr;
+    int *d_grows = nullptr;
+    int ngroups = 0;
 };
 constexpr int64_t kSegLen = 512;
+// bras per group of the grouped stored digestion, by bra pair class (ss ps
+// pp ds dp dd), within 48 KB of LDS for the group's exchange rows (NA + NB
+// rows per bra) at 300 functions; 1: by segments.  Measured per build on
+// the 60-atom cluster (segments -> groups): (ss|ss) 0.91 -> 0.30 ms, (ps|ss)
+// 0.57 -> 0.30, (ds|ss) 0.61 -> 0.47, (ds|ds) 0.46 -> 0.30; pp bras in
+// threes and dp bras in pairs ran slower ((pp|ss) 0.09 -> 0.20, (dp|ds)
+// 0.24 -> 0.34: fewer blocks per CU fit the larger LDS rows)
+constexpr int kGroupBras[6] = {8, 4, 1, 2, 1, 1};
 
 // Index 0..20 of the class (cb >= ck).
 inline int class_index(int cb, int ck) { return cb * (cb + 1) / 2 + ck; }
