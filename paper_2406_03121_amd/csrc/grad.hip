@@ -32,11 +32,12 @@
 //
 // One-electron part: one lane per ordered shell pair (a, b), derivatives
 // with respect to a's centre only (the (b, a) lane supplies b's).  Two-
-// electron part: one lane per unique Schwarz-surviving shell quartet, with
-// its permutation multiplicity.  Both loop over every primitive (no
-// primitive screening) and add into the gradient with FP64 atomics.  This
-// path runs once per geometry; it is written for clarity of the Hermite
-// algebra, with its intermediates in per-lane arrays, not for speed.
+// electron part: one wave per unique Schwarz-surviving shell quartet (with
+// its permutation multiplicity), its lanes over the quartet's primitive
+// quartets, summed over the wave.  Both take every primitive (no primitive
+// screening) and add into the gradient with FP64 atomics.  This path runs
+// once per geometry; it is written for clarity of the Hermite algebra, with
+// its intermediates in per-lane arrays, not for speed.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -271,9 +272,9 @@ __global__ void __launch_bounds__(64) k_grad_2e(int64_t nq, const int4 *__restri
                                                 const GShell *__restrict__ sh, const double *__restrict__ alpha,
                                                 const double *__restrict__ ct, const double *__restrict__ tab, int N,
                                                 const double *__restrict__ D, double *__restrict__ grad) {
-    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (lane >= nq) return;
-    const int4 q = quartets[lane];
+    const int lane = threadIdx.x;
+    for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+    const int4 q = quartets[qi];
     const GShell S[4] = {sh[q.x], sh[q.y], sh[q.z], sh[q.w]};
     const double mult = (q.x == q.y ? 1.0 : 2.0) * (q.z == q.w ? 1.0 : 2.0) * ((q.x == q.z && q.y == q.w) ? 1.0 : 2.0);
     const int la = S[0].l, lb = S[1].l, lc = S[2].l, ld = S[3].l;
@@ -288,8 +289,11 @@ __global__ void __launch_bounds__(64) k_grad_2e(int64_t nq, const int4 *__restri
     double g[9] = {};  // d/dA, d/dB, d/dC (x, y, z each)
     const double c[4][3] = {{S[0].x, S[0].y, S[0].z}, {S[1].x, S[1].y, S[1].z}, {S[2].x, S[2].y, S[2].z},
                             {S[3].x, S[3].y, S[3].z}};
-    for (int p0 = 0; p0 < S[0].nprim; ++p0)
-        for (int p1 = 0; p1 < S[1].nprim; ++p1) {
+    // lane k takes primitive quartets k, k + 64, ... of this shell quartet
+    const int n1 = S[1].nprim, n2 = S[2].nprim, n3 = S[3].nprim;
+    const int npq = S[0].nprim * n1 * n2 * n3;
+    for (int kq = lane; kq < npq; kq += 64) {
+            const int p3 = kq % n3, p2 = (kq / n3) % n2, p1 = (kq / (n3 * n2)) % n1, p0 = kq / (n3 * n2 * n1);
             const double a = alpha[S[0].prim0 + p0], b = alpha[S[1].prim0 + p1];
             const double p = a + b;
             double ab2 = 0.0, P[3];
@@ -300,8 +304,7 @@ __global__ void __launch_bounds__(64) k_grad_2e(int64_t nq, const int4 *__restri
             const double Kab = exp(-a * b / p * ab2);
             for (int k = 0; k < 3; ++k) md_e(Ib, Jb, 0.5 / p, P[k] - c[0][k], P[k] - c[1][k], Eb[k]);
             const double cab = ct[S[0].prim0 + p0] * ct[S[1].prim0 + p1];
-            for (int p2 = 0; p2 < S[2].nprim; ++p2)
-                for (int p3 = 0; p3 < S[3].nprim; ++p3) {
+            {
                     const double cx = alpha[S[2].prim0 + p2], d = alpha[S[3].prim0 + p3];
                     const double qq = cx + d;
                     double cd2 = 0.0, Q[3];
@@ -409,11 +412,16 @@ __global__ void __launch_bounds__(64) k_grad_2e(int64_t nq, const int4 *__restri
                     }
                 }
         }
-    for (int k = 0; k < 3; ++k) {
-        atomicAdd(&grad[3 * S[0].atom + k], g[k]);
-        atomicAdd(&grad[3 * S[1].atom + k], g[3 + k]);
-        atomicAdd(&grad[3 * S[2].atom + k], g[6 + k]);
-        atomicAdd(&grad[3 * S[3].atom + k], -(g[k] + g[3 + k] + g[6 + k]));
+    // sums over the wave's primitive quartets
+    for (int k = 0; k < 9; ++k)
+        for (int off = 32; off > 0; off >>= 1) g[k] += __shfl_xor(g[k], off, 64);
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            atomicAdd(&grad[3 * S[0].atom + k], g[k]);
+            atomicAdd(&grad[3 * S[1].atom + k], g[3 + k]);
+            atomicAdd(&grad[3 * S[2].atom + k], g[6 + k]);
+            atomicAdd(&grad[3 * S[3].atom + k], -(g[k] + g[3 + k] + g[6 + k]));
+        }
     }
 }
 
@@ -498,7 +506,7 @@ extern "C" int mess_hf_gradient(const mess_basis *basis, const double *D, const 
         hipLaunchKernelGGL(k_grad_1e, dim3((unsigned)((nsh * nsh + 63) / 64)), dim3(64), 0, s, nsh, d_sh, d_alpha, d_ct,
                            nat, B->d_xyz, B->d_Zd, B->d_boys, N, D, d_W, d_g);
         if (nq)
-            hipLaunchKernelGGL(k_grad_2e, dim3((unsigned)((nq + 63) / 64)), dim3(64), 0, s, nq, d_q, d_sh, d_alpha,
+            hipLaunchKernelGGL(k_grad_2e, dim3((unsigned)std::min<int64_t>(nq, 1 << 20)), dim3(64), 0, s, nq, d_q, d_sh, d_alpha,
                                d_ct, B->d_boys, N, D, d_g);
         hipLaunchKernelGGL(k_grad_nuc, dim3((unsigned)((nat + 63) / 64)), dim3(64), 0, s, nat, B->d_xyz, B->d_Zd, d_g);
         if (hipGetLastError() != hipSuccess) fail(MESS_E_DEVICE, "kernel launch failed");
