@@ -208,21 +208,44 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
 
 // Rank of each pair within its (class, molecule) segment by descending
 // primitive-pair count, then descending Q (ties by index);
-// perm[off + seg_lo + rank] = local index.
-__global__ void k_rank_desc(const double *__restrict__ Q, const PairInfo *__restrict__ pairs, int off, int n,
-                            const int *__restrict__ seg_lo, const int *__restrict__ seg_hi, int *__restrict__ perm) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double qi = Q[off + i];
-    const int ni = pairs[off + i].npp;
-    const int lo = seg_lo[off + i], hi = seg_hi[off + i];
-    int rank = 0;
-    for (int j = lo; j < hi; ++j) {
-        const double qj = Q[off + j];
-        const int nj = pairs[off + j].npp;
-        rank += (nj > ni) || (nj == ni && ((qj > qi) || (qj == qi && j < i)));
+// perm[off + seg_lo + rank] = local index.  The block's pairs lie in
+// consecutive segments, so their union [seg_lo of the first, seg_hi of the
+// last) is staged through LDS in tiles of 256 and each thread counts the
+// tile entries of its own segment.
+__global__ void __launch_bounds__(256) k_rank_desc(const double *__restrict__ Q, const PairInfo *__restrict__ pairs,
+                                                   int off, int n, const int *__restrict__ seg_lo,
+                                                   const int *__restrict__ seg_hi, int *__restrict__ perm) {
+    __shared__ double qs[256];
+    __shared__ int ns[256];
+    const int first = blockIdx.x * 256, last = min(n - 1, first + 255);
+    const int i = first + threadIdx.x;
+    const bool on = i < n;
+    const int blo = seg_lo[off + first], bhi = seg_hi[off + last];
+    double qi = 0.0;
+    int ni = 0, lo = 0, hi = 0;
+    if (on) {
+        qi = Q[off + i];
+        ni = pairs[off + i].npp;
+        lo = seg_lo[off + i];
+        hi = seg_hi[off + i];
     }
-    perm[off + lo + rank] = i;
+    int rank = 0;
+    for (int j0 = blo; j0 < bhi; j0 += 256) {
+        const int j = j0 + threadIdx.x;
+        if (j < bhi) {
+            qs[threadIdx.x] = Q[off + j];
+            ns[threadIdx.x] = pairs[off + j].npp;
+        }
+        __syncthreads();
+        const int jb = max(lo, j0), je = min(hi, min(bhi, j0 + 256));
+        for (int jj = jb; jj < je; ++jj) {
+            const double qj = qs[jj - j0];
+            const int nj = ns[jj - j0];
+            rank += (nj > ni) || (nj == ni && ((qj > qi) || (qj == qi && jj < i)));
+        }
+        __syncthreads();
+    }
+    if (on) perm[off + lo + rank] = i;
 }
 
 __global__ void k_gather_pairs(int off, int n, const int *__restrict__ perm,

@@ -9,12 +9,13 @@ namespace mess {
 
 // ------------------------------------------------------------------ GEMM
 //
-// 64 x 64 output tile per 256-thread block, 4 x 4 per thread, K in steps of
-// 16 staged through LDS.  FP64 vector FMA: on gfx950 the FP64 matrix cores
-// have the same peak rate as the vector units, and these products are small
-// (N <= ~1000), so the tile is sized for latency, not for MFMA.  Below
-// 512 x 512 outputs a 32 x 32 tile (2 x 2 per thread) gives four times as
-// many blocks; every output is the same k-ordered FMA chain in both.
+// Single products (gemm): one wave per 16 x 16 output tile on the FP64
+// matrix cores (v_mfma_f64_16x16x4), operands read straight from global
+// memory in the instruction's lane layout (these products are small and
+// cached: N <= ~1000), K unrolled by 16 so that the loads of four steps are
+// in flight together.  Batched block-diagonal products (gemm_blocks): 64 x
+// 64 output tile per 256-thread block, 4 x 4 per thread, K in steps of 16
+// staged through LDS with FP64 vector FMAs.
 
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
@@ -74,11 +75,52 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, con
     }
 }
 
-template <bool TA, bool TB, int TM>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                              int lda, const double *__restrict__ B, int ldb, double beta,
-                                              double *__restrict__ C, int ldc) {
-    gemm_tile<TA, TB, TM>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.y * TM, blockIdx.x * TM);
+typedef double lg_double4 __attribute__((ext_vector_type(4)));
+
+// C = alpha op(A) op(B) + beta C, one 64-lane wave per 16 x 16 tile.  Lane
+// l supplies A(row0 + l % 16, k + l / 16) and B(k + l / 16, col0 + l % 16)
+// for each step of 4 in k, and holds C(row0 + l / 16 + 4 q, col0 + l % 16)
+// in element q of the accumulator (the FP64 instruction's lane layout).
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(64) k_gemm_mfma(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                                  int lda, const double *__restrict__ B, int ldb, double beta,
+                                                  double *__restrict__ C, int ldc) {
+    const int l = threadIdx.x;
+    const int row0 = blockIdx.y * 16, col0 = blockIdx.x * 16;
+    const int ar = row0 + l % 16, bc = col0 + l % 16, kq = l / 16;
+    const bool aon = ar < M, bon = bc < N;
+    auto ldA = [&](int k) -> double {
+        return (aon && k < K) ? (TA ? A[(int64_t)k * lda + ar] : A[(int64_t)ar * lda + k]) : 0.0;
+    };
+    auto ldB = [&](int k) -> double {
+        return (bon && k < K) ? (TB ? B[(int64_t)bc * ldb + k] : B[(int64_t)k * ldb + bc]) : 0.0;
+    };
+    // four independent accumulation chains (steps 4 st + 16 i), summed at
+    // the end, so consecutive matrix instructions do not wait on each other
+    lg_double4 acc[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) acc[st] = {0.0, 0.0, 0.0, 0.0};
+    int k0 = 0;
+    for (; k0 + 16 <= K; k0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            a[st] = ldA(k0 + 4 * st + kq);
+            b[st] = ldB(k0 + 4 * st + kq);
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) acc[st] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], acc[st], 0, 0, 0);
+    }
+    for (; k0 < K; k0 += 4) acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ldA(k0 + kq), ldB(k0 + kq), acc[0], 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = row0 + l / 16 + 4 * q, c = col0 + l % 16;
+        if (r < M && c < N) {
+            double v = alpha * ((acc[0][q] + acc[1][q]) + (acc[2][q] + acc[3][q]));
+            if (beta != 0.0) v += beta * C[(int64_t)r * ldc + c];
+            C[(int64_t)r * ldc + c] = v;
+        }
+    }
 }
 
 // Batched square products over a packed block-diagonal layout: block m is
@@ -101,23 +143,15 @@ __global__ void __launch_bounds__(256) k_gemm_blocks(int nmol, const int64_t *__
 int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
          const double *B, int ldb, double beta, double *C, int ldc) {
     if (M <= 0 || N <= 0) return MESS_OK;
-    const bool small = (int64_t)M * N <= 512 * 512;
-    const int tm = small ? 32 : kTM;
-    dim3 grid((N + tm - 1) / tm, (M + tm - 1) / tm), blk(256);
-#define MESS_GEMM(TA_, TB_)                                                                                     \
-    do {                                                                                                        \
-        if (small)                                                                                              \
-            hipLaunchKernelGGL((k_gemm<TA_, TB_, 32>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, \
-                               ldc);                                                                            \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_gemm<TA_, TB_, kTM>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta,  \
-                               C, ldc);                                                                         \
-    } while (0)
-    if (!ta && !tb) MESS_GEMM(false, false);
-    else if (ta && !tb) MESS_GEMM(true, false);
-    else if (!ta && tb) MESS_GEMM(false, true);
-    else MESS_GEMM(true, true);
-#undef MESS_GEMM
+    const dim3 grid((N + 15) / 16, (M + 15) / 16), blk(64);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((k_gemm_mfma<false, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((k_gemm_mfma<true, false>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((k_gemm_mfma<false, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<true, true>), grid, blk, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     MESS_LAUNCH_CHECK();
     return MESS_OK;
 }
