@@ -34,6 +34,12 @@ struct ClassLaunch {
 // lane, wave or table-driven kernel; coop.hip).
 int coop_jk(int cb, int ck, const ClassLaunch &L, const double *D, double *Gj, double *Gk, int prec);
 
+// Stored-block layout (coop.hip): true when class (cb, ck) keeps its blocks
+// quartet-major for J/K streaming (element e of quartet t at t NOUT + e)
+// instead of structure-of-arrays (e total + t); to_aos converts a region.
+bool stored_aos_class(int cb, int ck);
+int to_aos(const void *soa, void *aos, int nout, int64_t total, int prec, hipStream_t s);
+
 template <int CB, int CK>
 struct ClassOps {
     // Q[off + i] for the n pairs of class CB (requires CB == CK).

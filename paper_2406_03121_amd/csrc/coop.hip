@@ -778,6 +778,128 @@ __global__ void __launch_bounds__(64) k_jk_stored_wave(const PairInfo *__restric
     }
 }
 
+// Classes whose stored blocks are kept quartet-major (the block of quartet
+// t contiguous at base[t NOUT]) and streamed by k_jk_stored_aos: the ones
+// with few quartets per bra, where a bra segment leaves most of a block's
+// threads idle and the launch has fewer blocks than the chip has CUs.
+// (dd|ds) has enough quartets that its per-quartet atomics would cost more
+// than the segment kernel's LDS rows save.
+bool stored_aos_class(int cb, int ck) {
+    return (cb == 2 && ck == 2) || (cb == 4 && (ck == 2 || ck == 4)) || (cb == 5 && (ck == 2 || ck == 4 || ck == 5));
+}
+
+// J/K from quartet-major stored blocks: one wave per quartet copies its
+// block (contiguous, coalesced) and the six density sub-blocks it touches
+// into LDS, then its lanes take the output elements of the six digestion
+// families (J[a,b], J[c,d], K[a,c], K[b,c], K[a,d], K[b,d]), each a sum
+// over the block from LDS, added to J/K with one FP64 atomic.
+template <typename Real>
+__global__ void __launch_bounds__(64) k_jk_stored_aos(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
+                                                     int nbra, int same_class, const int64_t *__restrict__ rowstart,
+                                                     const int2 *__restrict__ rowmap, int64_t total, int NA, int NB,
+                                                     int NC, int ND, const Real *__restrict__ base,
+                                                     const double *__restrict__ Dall, double *__restrict__ Gjall,
+                                                     double *__restrict__ Gkall) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int nout = NA * NB * NC * ND;
+    const int nab = NA * NB, ncd = NC * ND;
+    // LDS: block, then D[c,d], D[a,b], D[b,d], D[a,d], D[b,c], D[a,c]
+    double *O = lds, *Dcd = O + nout, *Dab = Dcd + ncd, *Dbd = Dab + nab, *Dad = Dbd + NB * ND,
+           *Dbc = Dad + NA * ND, *Dac = Dbc + NB * NC;
+    const int nden = ncd + nab + NB * ND + NA * ND + NB * NC + NA * NC;
+    for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
+        const int2 ij = quartet_pairs(rowstart, rowmap, nbra, q);
+        const PairInfo bra = pairs[bra_off + ij.x];
+        const PairInfo ket = pairs[ket_off + ij.y];
+        double fac = 1.0;
+        if (bra.sa == bra.sb) fac *= 0.5;
+        if (ket.sa == ket.sb) fac *= 0.5;
+        if (same_class && ij.x == ij.y) fac *= 0.5;
+        const int N = bra.mN, a0 = bra.bfa, b0 = bra.bfb, c0 = ket.bfa, d0 = ket.bfb;
+        const double *D = Dall + bra.moff;
+        double *Gj = Gjall ? Gjall + bra.moff : nullptr;
+        double *Gk = Gkall ? Gkall + bra.moff : nullptr;
+        const Real *src = base + q * nout;
+        for (int e = lane; e < nout; e += 64) O[e] = (double)src[e];
+        for (int e = lane; e < nden; e += 64) {
+            int r = e, row, col;
+            if (r < ncd) { row = c0 + r / ND; col = d0 + r % ND; }
+            else if ((r -= ncd) < nab) { row = a0 + r / NB; col = b0 + r % NB; }
+            else if ((r -= nab) < NB * ND) { row = b0 + r / ND; col = d0 + r % ND; }
+            else if ((r -= NB * ND) < NA * ND) { row = a0 + r / ND; col = d0 + r % ND; }
+            else if ((r -= NA * ND) < NB * NC) { row = b0 + r / NC; col = c0 + r % NC; }
+            else { r -= NB * NC; row = a0 + r / NC; col = c0 + r % NC; }
+            Dcd[e] = D[(int64_t)row * N + col];
+        }
+        __syncthreads();
+        auto At = [&](int a, int b, int c, int d) { return O[((a * NB + b) * NC + c) * ND + d]; };
+        const int t_ab = Gj ? nab : 0, t_cd = Gj ? ncd : 0;
+        const int t_ac = Gk ? NA * NC : 0, t_bc = Gk ? NB * NC : 0, t_ad = Gk ? NA * ND : 0, t_bd = Gk ? NB * ND : 0;
+        const int ntgt = t_ab + t_cd + t_ac + t_bc + t_ad + t_bd;
+        for (int t = lane; t < ntgt; t += 64) {
+            int r = t;
+            double sum = 0.0;
+            if (r < t_ab) {
+                const int a = r / NB, b = r % NB;
+                for (int c = 0; c < NC; ++c)
+                    for (int d = 0; d < ND; ++d) sum += At(a, b, c, d) * Dcd[c * ND + d];
+                unsafeAtomicAdd(&Gj[(int64_t)(a0 + a) * N + b0 + b], 2.0 * fac * sum);
+            } else if ((r -= t_ab) < t_cd) {
+                const int c = r / ND, d = r % ND;
+                for (int a = 0; a < NA; ++a)
+                    for (int b = 0; b < NB; ++b) sum += At(a, b, c, d) * Dab[a * NB + b];
+                unsafeAtomicAdd(&Gj[(int64_t)(c0 + c) * N + d0 + d], 2.0 * fac * sum);
+            } else if ((r -= t_cd) < t_ac) {
+                const int a = r / NC, c = r % NC;
+                for (int b = 0; b < NB; ++b)
+                    for (int d = 0; d < ND; ++d) sum += At(a, b, c, d) * Dbd[b * ND + d];
+                unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + c0 + c], fac * sum);
+            } else if ((r -= t_ac) < t_bc) {
+                const int b = r / NC, c = r % NC;
+                for (int a = 0; a < NA; ++a)
+                    for (int d = 0; d < ND; ++d) sum += At(a, b, c, d) * Dad[a * ND + d];
+                unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + c0 + c], fac * sum);
+            } else if ((r -= t_bc) < t_ad) {
+                const int a = r / ND, d = r % ND;
+                for (int b = 0; b < NB; ++b)
+                    for (int c = 0; c < NC; ++c) sum += At(a, b, c, d) * Dbc[b * NC + c];
+                unsafeAtomicAdd(&Gk[(int64_t)(a0 + a) * N + d0 + d], fac * sum);
+            } else {
+                r -= t_ad;
+                const int b = r / ND, d = r % ND;
+                for (int a = 0; a < NA; ++a)
+                    for (int c = 0; c < NC; ++c) sum += At(a, b, c, d) * Dac[a * NC + c];
+                unsafeAtomicAdd(&Gk[(int64_t)(b0 + b) * N + d0 + d], fac * sum);
+            }
+        }
+        __syncthreads();  // LDS reused by the next quartet
+    }
+}
+
+// Quartet-major copy of a structure-of-arrays block region (once per store).
+template <typename Real>
+__global__ void k_to_aos(const Real *__restrict__ soa, Real *__restrict__ aos, int nout, int64_t total) {
+    const int64_t n = (int64_t)nout * total;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i / nout;
+        const int e = (int)(i % nout);
+        aos[i] = soa[(int64_t)e * total + t];
+    }
+}
+
+int to_aos(const void *soa, void *aos, int nout, int64_t total, int prec, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(((int64_t)nout * total + 255) / 256, 1 << 16);
+    if (prec == MESS_FP32)
+        hipLaunchKernelGGL(k_to_aos<float>, dim3(g), dim3(256), 0, s, static_cast<const float *>(soa),
+                           static_cast<float *>(aos), nout, total);
+    else
+        hipLaunchKernelGGL(k_to_aos<double>, dim3(g), dim3(256), 0, s, static_cast<const double *>(soa),
+                           static_cast<double *>(aos), nout, total);
+    MESS_LAUNCH_CHECK();
+    return MESS_OK;
+}
+
 int coop_store(int cb, int ck, const ClassLaunch &L, void *base, int prec) {
     return coop_launch(prec == MESS_FP32 ? kModeStore32 : kModeStore64, cb, ck, L, L.total,
                        static_cast<double *>(base), nullptr, nullptr, prec);
@@ -790,6 +912,19 @@ int coop_jk_stored(int cb, int ck, const ClassLaunch &L, const void *base, int p
     if (g > (1 << 20)) g = 1 << 20;
     const int NA = ncart(pair_class_la(cb)), NB = ncart(pair_class_lb(cb)), NC = ncart(pair_class_la(ck)),
               ND = ncart(pair_class_lb(ck));
+    if (stored_aos_class(cb, ck)) {
+        const size_t la = sizeof(double) * ((size_t)NA * NB * NC * ND + NA * NB + NC * ND + (NA + NB) * (NC + ND));
+        if (prec == MESS_FP32)
+            hipLaunchKernelGGL(k_jk_stored_aos<float>, dim3((unsigned)g), dim3(64), la, L.stream, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.total, NA, NB, NC, ND,
+                               static_cast<const float *>(base), D, Gj, Gk);
+        else
+            hipLaunchKernelGGL(k_jk_stored_aos<double>, dim3((unsigned)g), dim3(64), la, L.stream, L.pairs, L.bra_off,
+                               L.ket_off, L.nbra, L.same_class, L.rowstart, L.rowmap, L.total, NA, NB, NC, ND,
+                               static_cast<const double *>(base), D, Gj, Gk);
+        MESS_LAUNCH_CHECK();
+        return MESS_OK;
+    }
     // bra-row segments with K and density rows in LDS when they fit; (dd|dd)
     // keeps the wave-per-quartet form (measured faster: the streamed form
     // needs more registers than a lane has for its 36-element J and density

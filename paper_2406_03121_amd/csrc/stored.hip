@@ -1,9 +1,11 @@
 // mess_jk(MESS_JK_STORED): the unique, Schwarz-screened shell-quartet blocks
 // are computed once per (basis, precision, threshold) into device memory,
 // one structure-of-arrays region per angular class (element k of quartet t
-// at base[k * nq + t]), and every later call streams them into J/K.
-// The same blocks are what mess_eri(MESS_ERI_BLOCKS) exports, and what the
-// deterministic J/K mode digests with exact fixed-point accumulation.
+// at base[k * nq + t]; quartet-major, base[t * NOUT + k], for the classes
+// stored_aos_class names), and every later call streams them into J/K.
+// The same blocks are what mess_eri(MESS_ERI_BLOCKS) exports (always
+// structure-of-arrays), and what the deterministic J/K mode digests with
+// exact fixed-point accumulation.
 #include <algorithm>
 
 #include "class_ops.hpp"
@@ -72,6 +74,24 @@ static int get_stored(mess_basis *B, int prec, double tau, hipStream_t s, WorkLi
             return ClassOps<decltype(CB)::value, decltype(CK)::value>::store(L, p, prec);
         });
         if (rc != MESS_OK) break;
+        if (stored_aos_class(cl.cb, cl.ck)) {
+            // kept quartet-major: copy, then release the structure-of-arrays region
+            void *a = nullptr;
+            if (hipMalloc(&a, nbytes) != hipSuccess) {
+                set_error("mess_jk(STORED): cannot allocate %lld bytes for class (%d,%d)", (long long)nbytes, cl.cb,
+                          cl.ck);
+                rc = MESS_E_NOMEM;
+                break;
+            }
+            rc = to_aos(p, a, nout_of(cl.cb, cl.ck), cl.total, prec, s);
+            if (rc == MESS_OK && hipStreamSynchronize(s) != hipSuccess) {
+                set_error("mess_jk(STORED): block transpose failed");
+                rc = MESS_E_DEVICE;
+            }
+            hipFree(rc == MESS_OK ? p : a);
+            if (rc != MESS_OK) break;
+            E->base.back() = a;
+        }
     }
     if (rc != MESS_OK) {
         for (void *p : E->base)
@@ -212,7 +232,7 @@ template <typename Real>
 __global__ void __launch_bounds__(64) k_jk_det(const PairInfo *__restrict__ pairs, int bra_off, int ket_off,
                                                int nbra, int same_class, const int64_t *__restrict__ rowstart,
                                                const int2 *__restrict__ rowmap, int64_t total, int NA, int NB,
-                                               int NC, int ND, const Real *__restrict__ base,
+                                               int NC, int ND, const Real *__restrict__ base, int64_t es, int64_t qs,
                                                const double *__restrict__ D, unsigned long long *__restrict__ Aj,
                                                unsigned long long *__restrict__ Ak, int *__restrict__ flag) {
     const int lane = threadIdx.x;
@@ -227,7 +247,7 @@ __global__ void __launch_bounds__(64) k_jk_det(const PairInfo *__restrict__ pair
         const int N = bra.mN;
         const double *Dm = D + bra.moff;
         auto O = [&](int a, int b, int c, int d) {
-            return (double)base[(int64_t)(((a * NB + b) * NC + c) * ND + d) * total + q];
+            return (double)base[(int64_t)(((a * NB + b) * NC + c) * ND + d) * es + q * qs];
         };
         auto Dv = [&](int r, int c) { return Dm[(int64_t)r * N + c]; };
         const int a0 = bra.bfa, b0 = bra.bfb, c0 = ket.bfa, d0 = ket.bfb;
@@ -312,17 +332,21 @@ int jk_det(mess_basis *B, const double *D, double *Gj, double *Gk, int prec, dou
         const int NA = ncart(pair_class_la(cl.cb)), NB = ncart(pair_class_lb(cl.cb)),
                   NC = ncart(pair_class_la(cl.ck)), ND = ncart(pair_class_lb(cl.ck));
         const unsigned g = (unsigned)std::min<int64_t>(cl.total, 1 << 20);
+        // element stride and quartet stride of the class's stored layout
+        const bool aos = stored_aos_class(cl.cb, cl.ck);
+        const int64_t es = aos ? 1 : cl.total, qs = aos ? (int64_t)NA * NB * NC * ND : 1;
         const PairInfo *pairs = B->d_pairs;
         const int boff = B->pair_class_off[cl.cb], koff = B->pair_class_off[cl.ck];
         if (prec == MESS_FP32)
             hipLaunchKernelGGL(k_jk_det<float>, dim3(g), dim3(64), 0, s, pairs, boff, koff, cl.nrow, cl.cb == cl.ck,
                                cl.d_rowstart, cl.d_rowmap, cl.total, NA, NB, NC, ND,
-                               static_cast<const float *>(E->base[c]), D, Gj ? Aj : nullptr, Gk ? Ak : nullptr, flag);
+                               static_cast<const float *>(E->base[c]), es, qs, D, Gj ? Aj : nullptr, Gk ? Ak : nullptr,
+                               flag);
         else
             hipLaunchKernelGGL(k_jk_det<double>, dim3(g), dim3(64), 0, s, pairs, boff, koff, cl.nrow, cl.cb == cl.ck,
                                cl.d_rowstart, cl.d_rowmap, cl.total, NA, NB, NC, ND,
-                               static_cast<const double *>(E->base[c]), D, Gj ? Aj : nullptr, Gk ? Ak : nullptr,
-                               flag);
+                               static_cast<const double *>(E->base[c]), es, qs, D, Gj ? Aj : nullptr,
+                               Gk ? Ak : nullptr, flag);
         MESS_LAUNCH_CHECK();
     }
     const unsigned gf = (unsigned)std::min<int64_t>((B->packed + 255) / 256, 65536);
