@@ -1,8 +1,11 @@
 // Basis creation (normalisation, device tables), shell pairs, Schwarz
 // factors and unique shell-quartet work lists.
+#include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <thread>
 
 #include "class_ops.hpp"
 #include "mess_internal.hpp"
@@ -119,32 +122,60 @@ static PrimScreen screen_prim_pairs(const std::vector<int2> &pairs_ab, const dou
         }
     }
     const double c0 = std::pow(2.0, 0.25) * std::pow(kPi, 1.25);
-    auto bound = [&](int sa, int sb, int u, int v) {
-        const double *A = xyz + 3 * sh_atom[sa], *B = xyz + 3 * sh_atom[sb];
+    // p^{-5/4} = 1 / (p p^{1/4}) from two square roots (the bound's
+    // rounding is immaterial next to its slack)
+    auto bound = [&](const double *A, const double *B, int pu, int pv) {
         const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
-        const int pu = sh_prim0[sa] + u, pv = sh_prim0[sb] + v;
         const double p = ap[pu] + ap[pv];
-        return w[pu] * w[pv] * std::exp(-ap[pu] * ap[pv] / p * r2) * c0 * std::pow(p, -1.25);
+        return w[pu] * w[pv] * std::exp(-ap[pu] * ap[pv] / p * r2) * c0 / (p * std::sqrt(std::sqrt(p)));
     };
-    double umax = 0.0;
+    // every primitive pair's bound once, then the cut against the largest
+    std::vector<double> bnd;
+    std::vector<int> boff(pairs_ab.size() + 1, 0);
+    for (size_t i = 0; i < pairs_ab.size(); ++i) boff[i + 1] = boff[i] + sh_np[pairs_ab[i].x] * sh_np[pairs_ab[i].y];
+    bnd.resize(boff.back());
     int nppmax = 1;
-    for (const int2 &q : pairs_ab) {
-        nppmax = std::max(nppmax, sh_np[q.x] * sh_np[q.y]);
-        for (int u = 0; u < sh_np[q.x]; ++u)
-            for (int v = 0; v < sh_np[q.y]; ++v) umax = std::max(umax, bound(q.x, q.y, u, v));
+    for (const int2 &q : pairs_ab) nppmax = std::max(nppmax, sh_np[q.x] * sh_np[q.y]);
+    // the bounds on host threads (contiguous ranges of pairs), then their maximum
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<double> tmax(nt, 0.0);
+    {
+        std::vector<std::thread> pool;
+        const size_t np = pairs_ab.size(), chunk = (np + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t)
+            pool.emplace_back([&, t]() {
+                double m = 0.0;
+                for (size_t i = t * chunk; i < std::min(np, (t + 1) * chunk); ++i) {
+                    const int2 q = pairs_ab[i];
+                    const double *A = xyz + 3 * sh_atom[q.x], *B = xyz + 3 * sh_atom[q.y];
+                    double *b = bnd.data() + boff[i];
+                    for (int u = 0; u < sh_np[q.x]; ++u)
+                        for (int v = 0; v < sh_np[q.y]; ++v) {
+                            const double x = bound(A, B, sh_prim0[q.x] + u, sh_prim0[q.y] + v);
+                            b[u * sh_np[q.y] + v] = x;
+                            m = std::max(m, x);
+                        }
+                }
+                tmax[t] = m;
+            });
+        for (auto &th : pool) th.join();
     }
+    double umax = 0.0;
+    for (double m : tmax) umax = std::max(umax, m);
     const double eps = 1e-14 / (2.0 * (double)nppmax * (double)nppmax);
     PrimScreen S;
     S.pp0.reserve(pairs_ab.size());
     S.npp.reserve(pairs_ab.size());
-    for (const int2 &q : pairs_ab) {
+    for (size_t i = 0; i < pairs_ab.size(); ++i) {
+        const int2 q = pairs_ab[i];
+        const double *bq = bnd.data() + boff[i];
         const int k0 = (int)S.uv.size();
         S.pp0.push_back(k0);
         double best = -1.0;
         int bu = 0, bv = 0;
         for (int u = 0; u < sh_np[q.x]; ++u)
             for (int v = 0; v < sh_np[q.y]; ++v) {
-                const double b = bound(q.x, q.y, u, v);
+                const double b = bq[u * sh_np[q.y] + v];
                 if (b * umax >= eps) S.uv.push_back(make_ushort2((unsigned short)u, (unsigned short)v));
                 if (b > best) {
                     best = b;
@@ -207,20 +238,25 @@ __global__ void k_build_pairs(int n, const int2 *__restrict__ ab, const int *__r
 }
 
 // Rank of each pair within its (class, molecule) segment by descending
-// primitive-pair count, then descending Q (ties by index);
-// perm[off + seg_lo + rank] = local index.  The block's pairs lie in
-// consecutive segments, so their union [seg_lo of the first, seg_hi of the
-// last) is staged through LDS in tiles of 256 and each thread counts the
-// tile entries of its own segment.
-__global__ void __launch_bounds__(256) k_rank_desc(const double *__restrict__ Q, const PairInfo *__restrict__ pairs,
-                                                   int off, int n, const int *__restrict__ seg_lo,
-                                                   const int *__restrict__ seg_hi, int *__restrict__ perm) {
+// primitive-pair count, then descending Q (ties by index), then
+// perm[off + seg_lo + rank] = local index.  The pairs of a block of 256 lie
+// in consecutive segments, so their union [seg_lo of the first, seg_hi of
+// the last) is cut into chunks of kRankChunk (blockIdx.y), staged through
+// LDS in tiles of 256; each thread counts the entries of its own segment
+// that precede it and adds its count to cnt[i].
+constexpr int kRankChunk = 1024;
+
+__global__ void __launch_bounds__(256) k_rank_count(const double *__restrict__ Q, const PairInfo *__restrict__ pairs,
+                                                    int off, int n, const int *__restrict__ seg_lo,
+                                                    const int *__restrict__ seg_hi, int *__restrict__ cnt) {
     __shared__ double qs[256];
     __shared__ int ns[256];
     const int first = blockIdx.x * 256, last = min(n - 1, first + 255);
     const int i = first + threadIdx.x;
     const bool on = i < n;
     const int blo = seg_lo[off + first], bhi = seg_hi[off + last];
+    const int c0 = blo + blockIdx.y * kRankChunk, c1 = min(bhi, c0 + kRankChunk);
+    if (c0 >= c1) return;  // uniform over the block
     double qi = 0.0;
     int ni = 0, lo = 0, hi = 0;
     if (on) {
@@ -230,14 +266,14 @@ __global__ void __launch_bounds__(256) k_rank_desc(const double *__restrict__ Q,
         hi = seg_hi[off + i];
     }
     int rank = 0;
-    for (int j0 = blo; j0 < bhi; j0 += 256) {
+    for (int j0 = c0; j0 < c1; j0 += 256) {
         const int j = j0 + threadIdx.x;
-        if (j < bhi) {
+        if (j < c1) {
             qs[threadIdx.x] = Q[off + j];
             ns[threadIdx.x] = pairs[off + j].npp;
         }
         __syncthreads();
-        const int jb = max(lo, j0), je = min(hi, min(bhi, j0 + 256));
+        const int jb = max(lo, j0), je = min(hi, min(c1, j0 + 256));
         for (int jj = jb; jj < je; ++jj) {
             const double qj = qs[jj - j0];
             const int nj = ns[jj - j0];
@@ -245,7 +281,20 @@ __global__ void __launch_bounds__(256) k_rank_desc(const double *__restrict__ Q,
         }
         __syncthreads();
     }
-    if (on) perm[off + lo + rank] = i;
+    if (on && rank) atomicAdd(&cnt[off + i], rank);
+}
+
+__global__ void k_rank_scatter(int off, int n, const int *__restrict__ seg_lo, const int *__restrict__ cnt,
+                               int *__restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[off + seg_lo[off + i] + cnt[off + i]] = i;
+}
+
+__global__ void k_pp_to_f32(int64_t n, const PrimPair *__restrict__ pp, PrimPairF *__restrict__ ppf) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const PrimPair h = pp[i];
+        ppf[i] = PrimPairF{(float)h.PAx, (float)h.PAy, (float)h.PAz, (float)h.p, (float)h.K, (float)h.rp, (float)h.Kr, 0.0f};
+    }
 }
 
 __global__ void k_gather_pairs(int off, int n, const int *__restrict__ perm,
@@ -307,12 +356,19 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
     }
     auto *W = new WorkLists();
     W->tau = tau;
+    // per class: host lists waiting for the single device copy
+    struct Staged {
+        std::vector<int4> segs, groups, tiles;
+        std::vector<int> grows;
+    };
     const std::vector<PairInfo> &P = B->pairs_host;
     const std::vector<double> &Q = B->pairQ_host;
     int rc = MESS_OK;
-    for (int cb = 0; cb < kNumPairClasses && rc == MESS_OK; ++cb)
-        for (int ck = 0; ck <= cb && rc == MESS_OK; ++ck) {
-            ClassList cl;
+    // the 21 classes are independent: built on host threads, kept in class order
+    std::vector<ClassList> built(kNumClasses);
+    std::vector<Staged> staged(kNumClasses);
+    auto build_class = [&](int cb, int ck) {
+            ClassList &cl = built[class_index(cb, ck)];
             cl.cb = cb;
             cl.ck = ck;
             cl.nbra = B->pair_class_off[cb + 1] - B->pair_class_off[cb];
@@ -408,52 +464,96 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
             cl.nseg = (int)segs.size();
             if (cl.total >= ((int64_t)1 << 31)) groups.clear();
             cl.ngroups = (int)groups.size();
-            if (cl.ngroups > 0 &&
-                (hipMalloc(&cl.d_groups, sizeof(int4) * groups.size()) != hipSuccess ||
-                 hipMalloc(&cl.d_tiles, sizeof(int4) * tiles.size()) != hipSuccess ||
-                 hipMalloc(&cl.d_grows, sizeof(int) * grows.size()) != hipSuccess ||
-                 hipMemcpy(cl.d_groups, groups.data(), sizeof(int4) * groups.size(), hipMemcpyHostToDevice) !=
-                     hipSuccess ||
-                 hipMemcpy(cl.d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice) !=
-                     hipSuccess ||
-                 hipMemcpy(cl.d_grows, grows.data(), sizeof(int) * grows.size(), hipMemcpyHostToDevice) !=
-                     hipSuccess)) {
-                hipFree(cl.d_groups);
-                hipFree(cl.d_tiles);
-                hipFree(cl.d_grows);
-                set_error("hipMalloc(work list groups) failed");
-                rc = MESS_E_NOMEM;
-                break;
-            }
-            if (cl.nrow > 0) {
-                if (hipMalloc(&cl.d_rowstart, sizeof(int64_t) * (cl.nrow + 1)) != hipSuccess ||
-                    hipMalloc(&cl.d_rowmap, sizeof(int2) * cl.nrow) != hipSuccess ||
-                    (cl.nseg > 0 && hipMalloc(&cl.d_segs, sizeof(int4) * cl.nseg) != hipSuccess) ||
-                    (cl.nseg > 0 && hipMemcpy(cl.d_segs, segs.data(), sizeof(int4) * cl.nseg,
-                                              hipMemcpyHostToDevice) != hipSuccess) ||
-                    hipMemcpy(cl.d_rowstart, cl.h_rowstart.data(), sizeof(int64_t) * (cl.nrow + 1),
-                              hipMemcpyHostToDevice) != hipSuccess ||
-                    hipMemcpy(cl.d_rowmap, cl.h_rowmap.data(), sizeof(int2) * cl.nrow, hipMemcpyHostToDevice) !=
-                        hipSuccess) {
-                    hipFree(cl.d_rowstart);
-                    hipFree(cl.d_rowmap);
-                    hipFree(cl.d_segs);
-                    set_error("hipMalloc(work list) failed");
-                    rc = MESS_E_NOMEM;
-                    break;
+            staged[class_index(cb, ck)] = Staged{std::move(segs), std::move(groups), std::move(tiles), std::move(grows)};
+    };
+    {
+        std::vector<std::thread> pool;
+        std::atomic<int> next{0};
+        const int nt = (int)std::min<unsigned>(kNumClasses, std::max(1u, std::thread::hardware_concurrency()));
+        for (int t = 0; t < nt; ++t)
+            pool.emplace_back([&]() {
+                for (int c = next++; c < kNumClasses; c = next++) {
+                    int cb = 0;
+                    while ((cb + 1) * (cb + 2) / 2 <= c) ++cb;
+                    build_class(cb, c - cb * (cb + 1) / 2);
                 }
+            });
+        for (auto &th : pool) th.join();
+    }
+    // class order: cb ascending, ck ascending within (the fixed order of W->classes)
+    for (int cb = 0; cb < kNumPairClasses; ++cb)
+        for (int ck = 0; ck <= cb; ++ck) W->classes.push_back(std::move(built[class_index(cb, ck)]));
+    {
+        std::vector<Staged> ordered;
+        for (int cb = 0; cb < kNumPairClasses; ++cb)
+            for (int ck = 0; ck <= cb; ++ck) ordered.push_back(std::move(staged[class_index(cb, ck)]));
+        staged.swap(ordered);
+    }
+    // every class's lists in one device buffer (one allocation, one copy)
+    size_t bytes = 0;
+    auto take = [&](size_t n) {
+        const size_t o = bytes;
+        bytes += (n + 255) / 256 * 256;
+        return o;
+    };
+    std::vector<std::array<size_t, 6>> offs(W->classes.size());
+    for (size_t c = 0; c < W->classes.size(); ++c) {
+        const ClassList &cl = W->classes[c];
+        const Staged &st = staged[c];
+        if (cl.nrow > 0) {
+            offs[c][0] = take(sizeof(int64_t) * (cl.nrow + 1));
+            offs[c][1] = take(sizeof(int2) * cl.nrow);
+        }
+        if (cl.nseg > 0) offs[c][2] = take(sizeof(int4) * cl.nseg);
+        if (cl.ngroups > 0) {
+            offs[c][3] = take(sizeof(int4) * st.groups.size());
+            offs[c][4] = take(sizeof(int4) * st.tiles.size());
+            offs[c][5] = take(sizeof(int) * st.grows.size());
+        }
+    }
+    if (bytes > 0) {
+        std::vector<char> host(bytes);
+        for (size_t c = 0; c < W->classes.size(); ++c) {
+            const ClassList &cl = W->classes[c];
+            const Staged &st = staged[c];
+            if (cl.nrow > 0) {
+                std::memcpy(host.data() + offs[c][0], cl.h_rowstart.data(), sizeof(int64_t) * (cl.nrow + 1));
+                std::memcpy(host.data() + offs[c][1], cl.h_rowmap.data(), sizeof(int2) * cl.nrow);
             }
-            W->classes.push_back(cl);
+            if (cl.nseg > 0) std::memcpy(host.data() + offs[c][2], st.segs.data(), sizeof(int4) * cl.nseg);
+            if (cl.ngroups > 0) {
+                std::memcpy(host.data() + offs[c][3], st.groups.data(), sizeof(int4) * st.groups.size());
+                std::memcpy(host.data() + offs[c][4], st.tiles.data(), sizeof(int4) * st.tiles.size());
+                std::memcpy(host.data() + offs[c][5], st.grows.data(), sizeof(int) * st.grows.size());
+            }
         }
+        if (hipMalloc(&W->dbuf, bytes) != hipSuccess) {
+            W->dbuf = nullptr;
+            set_error("hipMalloc(work list, %zu bytes) failed", bytes);
+            rc = MESS_E_NOMEM;
+        } else if (hipMemcpy(W->dbuf, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("work list copy to the device failed");
+            rc = MESS_E_DEVICE;
+        }
+    }
+    if (rc == MESS_OK) {
+        char *base = static_cast<char *>(W->dbuf);
+        for (size_t c = 0; c < W->classes.size(); ++c) {
+            ClassList &cl = W->classes[c];
+            if (cl.nrow > 0) {
+                cl.d_rowstart = reinterpret_cast<int64_t *>(base + offs[c][0]);
+                cl.d_rowmap = reinterpret_cast<int2 *>(base + offs[c][1]);
+            }
+            if (cl.nseg > 0) cl.d_segs = reinterpret_cast<int4 *>(base + offs[c][2]);
+            if (cl.ngroups > 0) {
+                cl.d_groups = reinterpret_cast<int4 *>(base + offs[c][3]);
+                cl.d_tiles = reinterpret_cast<int4 *>(base + offs[c][4]);
+                cl.d_grows = reinterpret_cast<int *>(base + offs[c][5]);
+            }
+        }
+    }
     if (rc != MESS_OK) {
-        for (auto &cl : W->classes) {
-            if (cl.d_rowstart) hipFree(cl.d_rowstart);
-            if (cl.d_rowmap) hipFree(cl.d_rowmap);
-            if (cl.d_segs) hipFree(cl.d_segs);
-            hipFree(cl.d_groups);
-            hipFree(cl.d_tiles);
-            hipFree(cl.d_grows);
-        }
+        hipFree(W->dbuf);
         delete W;
         return rc;
     }
@@ -465,14 +565,7 @@ int get_work_lists(mess_basis *B, double tau, hipStream_t s, WorkLists **out) {
 static void free_basis(mess_basis *B) {
     if (!B) return;
     for (auto &kv : B->lists) {
-        for (auto &cl : kv.second->classes) {
-            if (cl.d_rowstart) hipFree(cl.d_rowstart);
-            if (cl.d_rowmap) hipFree(cl.d_rowmap);
-            if (cl.d_segs) hipFree(cl.d_segs);
-            hipFree(cl.d_groups);
-            hipFree(cl.d_tiles);
-            hipFree(cl.d_grows);
-        }
+        hipFree(kv.second->dbuf);
         delete kv.second;
     }
     void free_stored(mess_basis *);
@@ -709,14 +802,14 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     }
 
     int2 *d_ab = nullptr;
-    int *d_pp0 = nullptr, *d_npp = nullptr, *d_perm = nullptr, *d_seglo = nullptr, *d_seghi = nullptr;
+    int *d_pp0 = nullptr, *d_npp = nullptr, *d_perm = nullptr, *d_cnt = nullptr, *d_seglo = nullptr, *d_seghi = nullptr;
     ushort2 *d_uv = nullptr;
     ShellDev *d_sh = nullptr;
     double *d_alpha = nullptr, *d_ct = nullptr, *d_Qraw = nullptr;
     PairInfo *d_pairs_raw = nullptr;
     int rc = MESS_OK;
     auto cleanup = [&]() {
-        hipFree(d_ab); hipFree(d_pp0); hipFree(d_npp); hipFree(d_uv); hipFree(d_seglo); hipFree(d_seghi); hipFree(d_perm); hipFree(d_sh);
+        hipFree(d_ab); hipFree(d_pp0); hipFree(d_npp); hipFree(d_uv); hipFree(d_seglo); hipFree(d_seghi); hipFree(d_perm); hipFree(d_cnt); hipFree(d_sh);
         hipFree(d_alpha); hipFree(d_ct); hipFree(d_Qraw); hipFree(d_pairs_raw);
     };
 #define MESS_HIPC(call)                                                                         \
@@ -736,6 +829,8 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     MESS_HIPC(hipMalloc(&d_seglo, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_seghi, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_perm, sizeof(int) * np_));
+    MESS_HIPC(hipMalloc(&d_cnt, sizeof(int) * np_));
+    MESS_HIPC(hipMemset(d_cnt, 0, sizeof(int) * np_));
     MESS_HIPC(hipMalloc(&d_sh, sizeof(ShellDev) * n_shells));
     MESS_HIPC(hipMalloc(&d_alpha, sizeof(double) * nprim));
     MESS_HIPC(hipMalloc(&d_ct, sizeof(double) * nprim));
@@ -776,8 +871,14 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
     for (int c = 0; c < kNumPairClasses; ++c) {
         const int off = B->pair_class_off[c], n = B->pair_class_off[c + 1] - off;
         if (n == 0) continue;
-        hipLaunchKernelGGL(k_rank_desc, dim3((n + 255) / 256), dim3(256), 0, s, d_Qraw, d_pairs_raw, off, n, d_seglo,
-                           d_seghi, d_perm);
+        // chunks along y: the longest block span of this class, in kRankChunk
+        int span = 0;
+        for (int f = 0; f < n; f += 256)
+            span = std::max(span, seg_hi[off + std::min(n - 1, f + 255)] - seg_lo[off + f]);
+        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((span + kRankChunk - 1) / kRankChunk));
+        hipLaunchKernelGGL(k_rank_count, grid, dim3(256), 0, s, d_Qraw, d_pairs_raw, off, n, d_seglo, d_seghi, d_cnt);
+        hipLaunchKernelGGL(k_rank_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, off, n, d_seglo, d_cnt,
+                           d_perm);
         hipLaunchKernelGGL(k_gather_pairs, dim3((n + 255) / 256), dim3(256), 0, s, off, n, d_perm, d_pairs_raw,
                            d_Qraw, B->d_pairs, B->d_pairQ);
     }
@@ -793,16 +894,11 @@ static int create_impl(int n_mol, const int32_t *mol_natom, const int32_t *mol_n
             return MESS_E_NUMERIC;
         }
     // FP32 copy of the primitive-pair table
-    {
-        std::vector<PrimPair> h(npp);
-        MESS_HIPC(hipMemcpy(h.data(), B->d_pp, sizeof(PrimPair) * npp, hipMemcpyDeviceToHost));
-        std::vector<PrimPairF> hf(npp);
-        for (int i = 0; i < npp; ++i)
-            hf[i] = PrimPairF{(float)h[i].PAx, (float)h[i].PAy, (float)h[i].PAz, (float)h[i].p,
-                              (float)h[i].K, (float)h[i].rp, (float)h[i].Kr, 0.0f};
-        MESS_HIPC(hipMalloc(&B->d_ppf, sizeof(PrimPairF) * npp));
-        MESS_HIPC(hipMemcpy(B->d_ppf, hf.data(), sizeof(PrimPairF) * npp, hipMemcpyHostToDevice));
-    }
+    MESS_HIPC(hipMalloc(&B->d_ppf, sizeof(PrimPairF) * npp));
+    hipLaunchKernelGGL(k_pp_to_f32, dim3((unsigned)std::min<int64_t>(((int64_t)npp + 255) / 256, 65536)), dim3(256), 0,
+                       s, (int64_t)npp, B->d_pp, B->d_ppf);
+    MESS_HIPC(hipGetLastError());
+    MESS_HIPC(hipStreamSynchronize(s));
     MESS_HIPC(hipMalloc(&B->scratch_jk, sizeof(double) * 2 * (size_t)B->packed));
 #undef MESS_HIPC
     cleanup();

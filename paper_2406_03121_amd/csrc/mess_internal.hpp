@@ -232,6 +232,7 @@ void prof_record(hipStream_t s, int cls, bool begin, int64_t quartets, int64_t p
 struct WorkLists {
     double tau = -1.0;
     std::vector<ClassList> classes;  // 21 (cb >= ck), in a fixed order
+    void *dbuf = nullptr;            // one device allocation holding every class's lists
 };
 
 struct StoredEri;  // mess_jk(STORED) cache

@@ -1,5 +1,6 @@
 // One-electron integrals: overlap S (paper eq. 3), kinetic T and nuclear
-// attraction V, one lane per ordered shell pair.
+// attraction V, one wave per ordered shell pair (pairs listed per angular
+// class, one launch per class), its lanes over the molecule's nuclei.
 //   1-D overlaps (Obara-Saika):  s_{00} = sqrt(pi/p),
 //     s_{i+1,j} = PA s_{ij} + (i s_{i-1,j} + j s_{i,j-1}) / (2p),
 //     s_{i,j+1} = PB s_{ij} + (i s_{i-1,j} + j s_{i,j-1}) / (2p);
@@ -8,6 +9,8 @@
 //   nuclear attraction (Obara-Saika), per nucleus C:
 //     [e+1_i]^(m) = PA_i [e]^(m) - PC_i [e]^(m+1) + e_i/(2p) ([e-1_i]^(m) - [e-1_i]^(m+1)),
 //     [0]^(m) = 2 pi / p  K_ab F_m(p |PC|^2),  then the HRR to (a|b).
+#include <algorithm>
+
 #include "eri_hgp.hpp"
 #include "mess_internal.hpp"
 
@@ -20,6 +23,9 @@ struct ShellLite {
     int at0, nat;              // the molecule's nuclei
 };
 
+// Every lane forms the pair's overlap and kinetic sums (lane 0 stores
+// them); lane k takes nuclei k, k + 64, ... of the nuclear attraction, whose
+// e-side sums are added over the wave before the horizontal recursion.
 template <int LA, int LB>
 __global__ void __launch_bounds__(64) k_one_electron(int npairs, const int2 *__restrict__ ab,
                                                      const ShellLite *__restrict__ sh,
@@ -31,11 +37,10 @@ __global__ void __launch_bounds__(64) k_one_electron(int npairs, const int2 *__r
                                                      const double *__restrict__ etab,
                                                      double *__restrict__ S, double *__restrict__ T,
                                                      double *__restrict__ V) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npairs) return;
+    const int lane = threadIdx.x;
+    for (int t = blockIdx.x; t < npairs; t += gridDim.x) {
     const int2 q = ab[t];
     const ShellLite A = sh[q.x], B = sh[q.y];
-    if (A.l != LA || B.l != LB) return;
     const int N = A.mN;
     constexpr int NA = ncart(LA), NB = ncart(LB), LAB = LA + LB;
     constexpr int E0 = cart_off(LA), NE = cart_off(LAB + 1);
@@ -94,7 +99,7 @@ __global__ void __launch_bounds__(64) k_one_electron(int npairs, const int2 *__r
                 });
             });
             // nuclear attraction
-            for (int c = A.at0; c < A.at0 + A.nat; ++c) {
+            for (int c = A.at0 + lane; c < A.at0 + A.nat; c += 64) {
                 const double PC[3] = {(A.x - xyz[3 * c]) + PA[0], (A.y - xyz[3 * c + 1]) + PA[1],
                                       (A.z - xyz[3 * c + 2]) + PA[2]};
                 const double Tb = p * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
@@ -123,18 +128,24 @@ __global__ void __launch_bounds__(64) k_one_electron(int npairs, const int2 *__r
             }
         }
     }
-    double vout[NA * NB];
-    hrr_1<LA, LB>(vacc, AB, vout);
-    static_for<0, NA>([&](auto IA) {
-        static_for<0, NB>([&](auto IB) {
-            constexpr int ia = decltype(IA)::value, ib = decltype(IB)::value;
-            constexpr double sc = comp_scale<LA>(ia) * comp_scale<LB>(ib);
-            const int64_t idx = A.moff + (int64_t)(A.bf0 + ia) * N + B.bf0 + ib;
-            if (S) S[idx] = sc * sacc[ia * NB + ib];
-            if (T) T[idx] = sc * tacc[ia * NB + ib];
-            if (V) V[idx] = sc * vout[ia * NB + ib];
-        });
+    static_for<0, NE - E0>([&](auto I) {
+        for (int off = 32; off > 0; off >>= 1) vacc[I] += __shfl_xor(vacc[I], off, 64);
     });
+    if (lane == 0) {
+        double vout[NA * NB];
+        hrr_1<LA, LB>(vacc, AB, vout);
+        static_for<0, NA>([&](auto IA) {
+            static_for<0, NB>([&](auto IB) {
+                constexpr int ia = decltype(IA)::value, ib = decltype(IB)::value;
+                constexpr double sc = comp_scale<LA>(ia) * comp_scale<LB>(ib);
+                const int64_t idx = A.moff + (int64_t)(A.bf0 + ia) * N + B.bf0 + ib;
+                if (S) S[idx] = sc * sacc[ia * NB + ib];
+                if (T) T[idx] = sc * tacc[ia * NB + ib];
+                if (V) V[idx] = sc * vout[ia * NB + ib];
+            });
+        });
+    }
+    }
 }
 
 }  // namespace mess
@@ -149,7 +160,7 @@ extern "C" int mess_one_electron(const mess_basis *B, double *S, double *T, doub
     if (!S && !T && !V) return MESS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<ShellLite> h(B->nsh);
-    std::vector<int2> pairs;
+    std::vector<int2> by_class[9];  // ordered pairs by (l_a, l_b)
     for (int m = 0; m < B->n_mol; ++m) {
         const int s0 = B->mol_sh0[m], s1 = s0 + B->mol_nsh[m];
         for (int i = s0; i < s1; ++i) {
@@ -157,8 +168,14 @@ extern "C" int mess_one_electron(const mess_basis *B, double *S, double *T, doub
             h[i] = ShellLite{B->xyz[3 * a],         B->xyz[3 * a + 1],     B->xyz[3 * a + 2], B->sh_l[i],
                              B->sh_prim0[i],        B->sh_np[i],           B->sh_bf0[i] - B->mol_bf0[m],
                              (int)B->mol_moff[m],   B->mol_nbf[m],         B->mol_atom0[m],   B->mol_natom[m]};
-            for (int j = s0; j < s1; ++j) pairs.push_back(make_int2(i, j));
+            for (int j = s0; j < s1; ++j) by_class[3 * B->sh_l[i] + B->sh_l[j]].push_back(make_int2(i, j));
         }
+    }
+    std::vector<int2> pairs;
+    int coff[10] = {0};
+    for (int c = 0; c < 9; ++c) {
+        pairs.insert(pairs.end(), by_class[c].begin(), by_class[c].end());
+        coff[c + 1] = (int)pairs.size();
     }
     const int npairs = (int)pairs.size();
     int2 *d_ab = nullptr;
@@ -180,10 +197,11 @@ extern "C" int mess_one_electron(const mess_basis *B, double *S, double *T, doub
         rc = MESS_E_DEVICE;
     }
     if (rc == MESS_OK) {
-        dim3 g((npairs + 63) / 64), blk(64);
-#define MESS_ONEE(la, lb)                                                                                  \
-    hipLaunchKernelGGL((k_one_electron<la, lb>), g, blk, 0, s, npairs, d_ab, d_sh, d_alpha, d_ct, B->d_xyz, \
-                       B->d_Zd, B->d_boys, B->d_boys_exp, S, T, V);
+#define MESS_ONEE(la, lb)                                                                                     \
+    if (const int n = coff[3 * la + lb + 1] - coff[3 * la + lb])                                               \
+        hipLaunchKernelGGL((k_one_electron<la, lb>), dim3((unsigned)std::min(n, 1 << 20)), dim3(64), 0, s, n,     \
+                           d_ab + coff[3 * la + lb], d_sh, d_alpha, d_ct, B->d_xyz, B->d_Zd, B->d_boys,            \
+                           B->d_boys_exp, S, T, V);
         MESS_ONEE(0, 0) MESS_ONEE(0, 1) MESS_ONEE(0, 2)
         MESS_ONEE(1, 0) MESS_ONEE(1, 1) MESS_ONEE(1, 2)
         MESS_ONEE(2, 0) MESS_ONEE(2, 1) MESS_ONEE(2, 2)
