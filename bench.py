@@ -231,6 +231,10 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
                                     jk_mode=jk_mode, prec=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if a.mark_steps > 0:
+        time.sleep(a.mark_steps)
+        t0 += time.perf_counter() - t1  # the idle mark is in no figure
+        t1 = time.perf_counter()
     conv_hist = []
     for k in range(a.batch_steps):
         mess.mess_batch_scf_step(bs)
@@ -465,6 +469,9 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the oracle check of batch energies")
     ap.add_argument("--no-small", action="store_true", help="skip the 6-atom latency measurements")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-tensor J/K contraction")
+    ap.add_argument("--mark-steps", type=float, default=0.0,
+                    help="idle seconds before the timed steps of the batch blocks, so that a kernel trace shows "
+                         "where they begin (outside the timed region)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU split of the "

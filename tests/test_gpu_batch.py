@@ -208,7 +208,11 @@ def test_batched_scf_divergence_guard(use_graph):
     (its DIIS path climbs repeatedly) in one batch with two ordinary
     molecules: every molecule converges; 1002 and 1013 end in the restart
     stage and the others never leave stage 0; energies within 1e-6 Ha of the
-    oracle's guarded SCF (seed 1002: the committed oracle golden)."""
+    oracle's guarded SCF (seed 1002: the committed oracle golden).  In the
+    restart stage seed 1002 wanders between -17 and -22 Ha before it settles
+    (the oracle: 100 of its 125 iterations), and when it settles depends on
+    rounding (runs here took 119 and 210 steps, one more than 250), so the
+    step cap is far above that."""
     mess = need_gpu()
     from oracle import scf as oscf
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mol3to20_seed1002_guard.json")))
@@ -217,7 +221,8 @@ def test_batched_scf_divergence_guard(use_graph):
     B = mess.mess_batch_create(mols)
     announce(f"guard batch graph={use_graph}: nbf {[m.n_bf for m in mols]}")
     bs = mess.mess_batch_scf_create(B, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8, use_graph=use_graph)
-    for k in range(250):
+    cap = 1000
+    for k in range(cap):
         mess.mess_batch_scf_step(bs)
         st = mess.mess_batch_scf_status(bs)
         if st["n_converged"] == B.n_mol:
@@ -243,7 +248,7 @@ def test_batched_scf_divergence_guard(use_graph):
     Dh[B.mol_moff[2]:B.mol_moff[2] + n0 * n0] = np.nan
     bs = mess.mess_batch_scf_create(B, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8, use_graph=use_graph,
                                     D0=dev(Dh))
-    for k in range(250):
+    for k in range(cap):
         mess.mess_batch_scf_step(bs)
         st2 = mess.mess_batch_scf_status(bs)
         if st2["n_converged"] == B.n_mol:

@@ -8,7 +8,9 @@ converged energy, against the oracle's guarded SCF.
   amplification of rounding in DIIS, bounded here by 1e-3 Ha), the
   converged energy within 2e-8;
 * seed 1002 (114 functions; plain DIIS oscillates by Hartrees for good):
-  converges, in stage 3, to the committed oracle golden within 1e-6 Ha;
+  converges, in stage 3, to the committed oracle golden within 1e-6 Ha
+  (stage 3 wanders before it settles, after a number of iterations that
+  depends on rounding, so the cap is far above the oracle's 125);
 * a non-finite initial density: the guard restarts from the core guess and
   the run converges to the ordinary energy; with the guard off the step
   reports MESS_E_NUMERIC.
@@ -78,7 +80,7 @@ def test_guard_converges_oscillating_molecule():
     mol = G.batched_molecule(1002)
     assert mol.n_bf == g["n_bf"]
     B = mess.basis_from_molecule(mol)
-    es, stages, conv, final = _run(mess, B, 250, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8)
+    es, stages, conv, final = _run(mess, B, 1000, schwarz_tol=0.0, conv_tol=1e-8, diis_size=8)
     announce(f"guard seed 1002: converged {conv} after {len(es)} (oracle {g['guard']['iterations']}), "
              f"stage starts {_starts(stages)} (oracle {g['guard']['stage_starts']}), E {es[-1]!r} vs "
              f"{g['guard']['energy']!r}")
