@@ -93,7 +93,8 @@ def _sym(upper, n):
 # heavy cancellation that no FP32 build (nor the mixed-precision SCF, which
 # builds FP32 J/K only of near-converged densities and their changes) meets
 # to 2e-5 of max|J| (measured 6.6e-4 there)
-CASES = [(d, m) for d in ("d21", "dstar") for m in ("direct", "stored", "deterministic")] + [("dstar", "direct_fp32")]
+CASES = [(d, m) for d in ("d21", "dstar") for m in ("direct", "stored", "deterministic")] + \
+    [("dstar", "direct_fp32"), ("dstar", "stored_fp32")]
 
 
 @pytest.mark.parametrize("density,mode", CASES)
@@ -102,7 +103,7 @@ def test_water60_jk_every_element_vs_golden(density, mode):
     oracle's full builds stored by tests/golden/make_water60_jk_golden.py:
     the seeded test density and the oracle's converged density D*.  FP64
     modes within 1e-14 sum|D| (the primitive-pair screening bound) plus
-    1e-11 * max(1, |x|); the FP32 build within 2e-5 of max|J|, max|K| (its
+    1e-11 * max(1, |x|); the FP32 builds (direct, stored) within 2e-5 of max|J|, max|K| (its
     error at D* is the one the mixed-precision SCF meets)."""
     mess = need_gpu()
     if not os.path.exists(GOLDEN_JK):
@@ -120,8 +121,9 @@ def test_water60_jk_every_element_vs_golden(density, mode):
     announce(f"water60 J/K every element: density {density}, {mode}")
     J, K = zeros(N, N), zeros(N, N)
     m = {"direct": mess.MESS_JK_DIRECT, "stored": mess.MESS_JK_STORED,
-         "deterministic": mess.MESS_JK_DETERMINISTIC, "direct_fp32": mess.MESS_JK_DIRECT}[mode]
-    prec = mess.MESS_FP32 if mode == "direct_fp32" else mess.MESS_FP64
+         "deterministic": mess.MESS_JK_DETERMINISTIC, "direct_fp32": mess.MESS_JK_DIRECT,
+         "stored_fp32": mess.MESS_JK_STORED}[mode]
+    prec = mess.MESS_FP32 if mode.endswith("_fp32") else mess.MESS_FP64
     mess.mess_jk(B, dev(D), J, K, mode=m, prec=prec, schwarz_tol=1e-10)
     Jh, Kh = host(J), host(K)
     if prec == mess.MESS_FP32:
