@@ -34,12 +34,15 @@ UNROLLED_CLASSES = [c for c in CLASSES if c not in COOP_CLASSES]
 # primitive-lane kernels (plane.hip), one object per class and precision
 PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (5, 1), (4, 4), (4, 2), (2, 2)]
 # recursion passes over ket subtrees (fewer live values for the largest;
-# measured per build on the 60-atom cluster: (dd|dp) 8.76 -> 4.52 ms,
-# (dp|dp) 1.56 -> 1.44, (dd|pp) 1.15 -> 1.06)
-PLANE_PASSES = {(5, 4): 3, (5, 3): 3, (5, 2): 2, (4, 4): 3}
+# measured per build on the 60-atom cluster, one pass -> three (x | y | z)
+# -> six (one per second-level ket component): (dd|dp) 8.76 -> 4.52 ->
+# 3.27 ms (spill 1.6 KB -> 640 -> 152 B per lane), (dd|ds) at two waves
+# 7.07 -> 5.65 -> 5.20 (260 -> 148 B), (dp|dp) 1.56 -> 1.44 -> 1.43,
+# (dd|pp) 1.15 -> 1.06 (two passes) -> 1.05)
+PLANE_PASSES = {(5, 4): 6, (5, 3): 6, (5, 2): 6, (4, 4): 6}
 # waves per SIMD asked of the compiler (default: its own choice, one wave
-# with 512 registers here); (dd|ds) with 3 passes runs faster at two waves
-# despite 260 B of spill per lane (7.07 -> 5.65 ms)
+# with 512 registers here); (dd|ds) runs faster at two waves despite its
+# spill (six passes: 5.26 ms at one wave, 5.20 at two)
 PLANE_WAVES = {(5, 3): 2}
 # wave-per-primitive-quartet kernels (wave.hip)
 WAVE_CLASSES = [(5, 5), (5, 4), (5, 3)]

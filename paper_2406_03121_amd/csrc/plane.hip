@@ -60,7 +60,8 @@ __constant__ PlaneBlocks<Dm, NACC> kPlaneBlocksDev = make_plane_blocks<Dm, NACC>
 template <class Dm>
 inline constexpr int kPlaneBlockSize = 32;
 // recursion passes per primitive quartet over ket subtrees: 2: x | y z;
-// 3: x | y | z (finer splits of the x subtree measured no fewer spills)
+// 3: x | y | z; 6: one pass per second-level component (xx, xy, xz, yy,
+// yz, zz), the fewest live values for the most repeated work
 #ifndef MESS_PLANE_PASSES
 #define MESS_PLANE_PASSES 1
 #endif
@@ -163,6 +164,13 @@ __global__ void __launch_bounds__(64) MESS_PLANE_OCC k_plane(CoopArgs A, const P
             } else if constexpr (kPlanePasses<Dm> == 3) {
                 run(std::integral_constant<int, 7>{});
                 run(std::integral_constant<int, 24>{});
+                run(std::integral_constant<int, 32>{});
+            } else if constexpr (kPlanePasses<Dm> == 6) {
+                run(std::integral_constant<int, 1>{});
+                run(std::integral_constant<int, 2>{});
+                run(std::integral_constant<int, 4>{});
+                run(std::integral_constant<int, 8>{});
+                run(std::integral_constant<int, 16>{});
                 run(std::integral_constant<int, 32>{});
             } else {
                 run(std::integral_constant<int, 63>{});
