@@ -220,7 +220,8 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
     """Batched SCF over many small molecules (seeds 1000...), one HIP graph
     per step, a fixed number of steps; jk_mode 1 stores the integral blocks
     at set-up and streams them in every step; prec 1 is the mixed-precision
-    batch.  Returns the figures and what the CPU-baseline leg checks
+    batch.  Direct-J/K batches first let the autotuner choose the kernel
+    forms on the batch (unless --no-tune).  Returns the figures and what the CPU-baseline leg checks
     (converged molecules count toward molecules/s in proportion to the share
     of an oracle-checked sample within 1e-6 Ha)."""
     from mess_inputs import generators as G
@@ -231,6 +232,23 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
                                     jk_mode=jk_mode, prec=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    tuned = None
+    if not a.no_tune and jk_mode == 0:
+        # the library's autotuner on the batch itself (its best forms differ
+        # from the 60-atom cluster's for a few classes), in the arithmetic the
+        # steps use; a one-time choice, kept out of the set-up and rate figures
+        D = torch.zeros(B.packed, dtype=torch.float64, device="cuda")
+        mess.mess_batch_scf_density(bs, D)
+        tuned = {}
+        for p, name in ((mess.MESS_FP64, "fp64"), (mess.MESS_FP32, "fp32")):
+            if p == mess.MESS_FP32 and prec != mess.MESS_FP32:
+                continue
+            forms, _ = mess.mess_autotune(B, D, schwarz_tol=a.tau, reps=2, prec=p)
+            tuned[name] = {CLASS_NAMES[c]: FORM_NAMES.get(int(forms[c]), str(int(forms[c]))) for c in range(21)}
+        torch.cuda.synchronize()
+        tuned["s"] = time.perf_counter() - t1
+        t0 += tuned["s"]
+        t1 = time.perf_counter()
     if a.mark_steps > 0:
         time.sleep(a.mark_steps)
         t0 += time.perf_counter() - t1  # the idle mark is in no figure
@@ -252,6 +270,8 @@ def batch_block(mess, a, torch, jk_mode=0, prec=0):
            "converged_molecules_per_s_unchecked": conv_hist[-1] / (t2 - t0),
            "converged_molecules_per_s": None,
            "shell_quartets_per_s": q * a.batch_steps / (t2 - t1)}
+    if tuned is not None:
+        out["autotune"] = tuned
     # kept for the oracle check of the CPU-baseline leg
     check = (mols, st["energy"].copy(), st["converged"].copy(), conv_hist[-1], t2 - t0)
     return out, check
