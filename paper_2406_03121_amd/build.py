@@ -44,6 +44,11 @@ PLANE_PASSES = {(5, 4): 6, (5, 3): 6, (5, 2): 6, (4, 4): 6}
 # with 512 registers here); (dd|ds) runs faster at two waves despite its
 # spill (six passes: 5.26 ms at one wave, 5.20 at two)
 PLANE_WAVES = {(5, 3): 2}
+# the FP32 kernels need half the registers, so more of their waves fit a
+# SIMD (measured per 60-atom FP32 build: (dd|ds) 4.22 -> 3.27 ms at three
+# waves, (dd|dp) 2.60 -> 1.43 at two, (dp|pp) 0.55 -> 0.41, (dp|dp) 0.80 ->
+# 0.71, (dd|pp) 0.54 -> 0.47 at three)
+PLANE_WAVES_F32 = {(5, 3): 3, (5, 4): 2, (5, 2): 3, (4, 2): 3, (4, 4): 3}
 # wave-per-primitive-quartet kernels (wave.hip)
 WAVE_CLASSES = [(5, 5), (5, 4), (5, 3)]
 
@@ -64,10 +69,11 @@ def _units():
         elif name == "plane":
             for cb, ck in PLANE_CLASSES:
                 for real in ("double", "float"):
+                    waves = {**PLANE_WAVES, **PLANE_WAVES_F32} if real == "float" else PLANE_WAVES
                     units.append((src, os.path.join(OBJ, f"plane_{cb}{ck}_{real}.o"),
                                   [f"-DMESS_PCB={cb}", f"-DMESS_PCK={ck}", f"-DMESS_PREAL={real}",
                                    f"-DMESS_PLANE_PASSES={PLANE_PASSES.get((cb, ck), 1)}"] +
-                                  ([f"-DMESS_PLANE_WAVES={PLANE_WAVES[(cb, ck)]}"] if (cb, ck) in PLANE_WAVES else [])))
+                                  ([f"-DMESS_PLANE_WAVES={waves[(cb, ck)]}"] if (cb, ck) in waves else [])))
         else:
             units.append((src, os.path.join(OBJ, name + ".o"), []))
     # heaviest classes first so the parallel build finishes sooner
@@ -83,7 +89,8 @@ def _units():
 
 
 def _headers_mtime():
-    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    # this file too: its per-class flags (passes, waves) change the objects
+    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h")) + [__file__]
     return max(os.path.getmtime(h) for h in hs)
 
 
