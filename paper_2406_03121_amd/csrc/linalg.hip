@@ -9,84 +9,25 @@ namespace mess {
 
 // ------------------------------------------------------------------ GEMM
 //
-// Single products (gemm): one wave per 16 x 16 output tile on the FP64
-// matrix cores (v_mfma_f64_16x16x4), operands read straight from global
-// memory in the instruction's lane layout (these products are small and
-// cached: N <= ~1000), K unrolled by 16 so that the loads of four steps are
-// in flight together.  Batched block-diagonal products (gemm_blocks): 64 x
-// 64 output tile per 256-thread block, 4 x 4 per thread, K in steps of 16
-// staged through LDS with FP64 vector FMAs.
-
-constexpr int kTM = 64, kTN = 64, kTK = 16;
-
-// One output tile (rows row0.., columns col0..) of C = alpha op(A) op(B) + beta C,
-// TM x TM outputs per 256-thread block.
-template <bool TA, bool TB, int TM = kTM>
-__device__ __forceinline__ void gemm_tile(int M, int N, int K, double alpha, const double *__restrict__ A, int lda,
-                                          const double *__restrict__ B, int ldb, double beta,
-                                          double *__restrict__ C, int ldc, int row0, int col0) {
-    constexpr int kTM = TM, kTN = TM, R = TM / 16;
-    __shared__ double As[kTK][kTM + 1];
-    __shared__ double Bs[kTK][kTN + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[R][R] = {};
-    for (int k0 = 0; k0 < K; k0 += kTK) {
-        for (int t = threadIdx.x; t < kTK * kTM; t += 256) {
-            const int kk = t / kTM, mm = t % kTM;
-            const int gr = row0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gr < M && gk < K) v = TA ? A[(int64_t)gk * lda + gr] : A[(int64_t)gr * lda + gk];
-            As[kk][mm] = v;
-        }
-        for (int t = threadIdx.x; t < kTK * kTN; t += 256) {
-            const int kk = t / kTN, nn = t % kTN;
-            const int gc = col0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gc < N && gk < K) v = TB ? B[(int64_t)gc * ldb + gk] : B[(int64_t)gk * ldb + gc];
-            Bs[kk][nn] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kTK; ++kk) {
-            double a[R], b[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < R; ++j) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < R; ++i)
-#pragma unroll
-                for (int j = 0; j < R; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int r = row0 + ty + 16 * i;
-        if (r >= M) continue;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int c = col0 + tx + 16 * j;
-            if (c >= N) continue;
-            double v = alpha * acc[i][j];
-            if (beta != 0.0) v += beta * C[(int64_t)r * ldc + c];
-            C[(int64_t)r * ldc + c] = v;
-        }
-    }
-}
+// One wave per 16 x 16 output tile on the FP64 matrix cores
+// (v_mfma_f64_16x16x4), operands read straight from global memory in the
+// instruction's lane layout (these products are small and cached: N <=
+// ~1000), K unrolled by 16 so that the loads of four steps are in flight
+// together; batched block-diagonal products (gemm_blocks) run the same tile
+// code over every molecule's blocks.
 
 typedef double lg_double4 __attribute__((ext_vector_type(4)));
 
-// C = alpha op(A) op(B) + beta C, one 64-lane wave per 16 x 16 tile.  Lane
-// l supplies A(row0 + l % 16, k + l / 16) and B(k + l / 16, col0 + l % 16)
-// for each step of 4 in k, and holds C(row0 + l / 16 + 4 q, col0 + l % 16)
-// in element q of the accumulator (the FP64 instruction's lane layout).
+// One 16 x 16 tile (rows row0.., columns col0..) of C = alpha op(A) op(B) +
+// beta C by one 64-lane wave.  Lane l supplies A(row0 + l % 16, k + l / 16)
+// and B(k + l / 16, col0 + l % 16) for each step of 4 in k, and holds
+// C(row0 + l / 16 + 4 q, col0 + l % 16) in element q of the accumulator
+// (the FP64 instruction's lane layout).
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(64) k_gemm_mfma(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                                  int lda, const double *__restrict__ B, int ldb, double beta,
-                                                  double *__restrict__ C, int ldc) {
+__device__ __forceinline__ void gemm_tile_mfma(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                               int lda, const double *__restrict__ B, int ldb, double beta,
+                                               double *__restrict__ C, int ldc, int row0, int col0) {
     const int l = threadIdx.x;
-    const int row0 = blockIdx.y * 16, col0 = blockIdx.x * 16;
     const int ar = row0 + l % 16, bc = col0 + l % 16, kq = l / 16;
     const bool aon = ar < M, bon = bc < N;
     auto ldA = [&](int k) -> double {
@@ -123,20 +64,28 @@ __global__ void __launch_bounds__(64) k_gemm_mfma(int M, int N, int K, double al
     }
 }
 
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(64) k_gemm_mfma(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                                  int lda, const double *__restrict__ B, int ldb, double beta,
+                                                  double *__restrict__ C, int ldc) {
+    gemm_tile_mfma<TA, TB>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, blockIdx.y * 16, blockIdx.x * 16);
+}
+
 // Batched square products over a packed block-diagonal layout: block m is
 // n_m x n_m at offset off[m] in A, B and C; blockIdx.z strides over blocks.
-// Each block's product is computed exactly as gemm() computes it.
+// Each block's product is computed exactly as gemm() computes it (the same
+// tile code, so a molecule of a batch gets the same bits as alone).
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) k_gemm_blocks(int nmol, const int64_t *__restrict__ off,
-                                                     const int *__restrict__ nb, double alpha,
-                                                     const double *__restrict__ A, const double *__restrict__ B,
-                                                     double beta, double *__restrict__ C) {
+__global__ void __launch_bounds__(64) k_gemm_blocks(int nmol, const int64_t *__restrict__ off,
+                                                    const int *__restrict__ nb, double alpha,
+                                                    const double *__restrict__ A, const double *__restrict__ B,
+                                                    double beta, double *__restrict__ C) {
     for (int m = blockIdx.z; m < nmol; m += gridDim.z) {
         const int n = nb[m];
-        const int row0 = blockIdx.y * kTM, col0 = blockIdx.x * kTN;
-        if (row0 >= n || col0 >= n) continue;  // uniform over the block
+        const int row0 = blockIdx.y * 16, col0 = blockIdx.x * 16;
+        if (row0 >= n || col0 >= n) continue;  // uniform over the wave
         const int64_t o = off[m];
-        gemm_tile<TA, TB>(n, n, n, alpha, A + o, n, B + o, n, beta, C + o, n, row0, col0);
+        gemm_tile_mfma<TA, TB>(n, n, n, alpha, A + o, n, B + o, n, beta, C + o, n, row0, col0);
     }
 }
 
@@ -159,7 +108,7 @@ int gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, con
 int gemm_blocks(hipStream_t s, bool ta, bool tb, int nmol, int nmax, const int64_t *off, const int *nb,
                 double alpha, const double *A, const double *B, double beta, double *C) {
     if (nmol <= 0 || nmax <= 0) return MESS_OK;
-    dim3 grid((nmax + kTN - 1) / kTN, (nmax + kTM - 1) / kTM, (unsigned)(nmol < 65535 ? nmol : 65535)), blk(256);
+    dim3 grid((nmax + 15) / 16, (nmax + 15) / 16, (unsigned)(nmol < 65535 ? nmol : 65535)), blk(64);
     if (!ta && !tb)
         hipLaunchKernelGGL((k_gemm_blocks<false, false>), grid, blk, 0, s, nmol, off, nb, alpha, A, B, beta, C);
     else if (ta && !tb)
