@@ -49,6 +49,11 @@ PLANE_WAVES = {(5, 3): 2}
 # waves, (dd|dp) 2.60 -> 1.43 at two, (dp|pp) 0.55 -> 0.41, (dp|dp) 0.80 ->
 # 0.71, (dd|pp) 0.54 -> 0.47 at three)
 PLANE_WAVES_F32 = {(5, 3): 3, (5, 4): 2, (5, 2): 3, (4, 2): 3, (4, 4): 3}
+# kernels whose passes each evaluate the Boys function themselves instead of
+# sharing one evaluation through LDS (measured on the same box: sharing takes
+# FP64 (dd|ds) 5.07 -> 4.85 ms and FP32 (dd|ds) 3.19 -> 2.81, but FP32
+# (dd|dp) 1.44 -> 1.54)
+PLANE_NO_SHARE_F32 = {(5, 4)}
 # wave-per-primitive-quartet kernels (wave.hip)
 WAVE_CLASSES = [(5, 5), (5, 4), (5, 3)]
 
@@ -73,7 +78,9 @@ def _units():
                     units.append((src, os.path.join(OBJ, f"plane_{cb}{ck}_{real}.o"),
                                   [f"-DMESS_PCB={cb}", f"-DMESS_PCK={ck}", f"-DMESS_PREAL={real}",
                                    f"-DMESS_PLANE_PASSES={PLANE_PASSES.get((cb, ck), 1)}"] +
-                                  ([f"-DMESS_PLANE_WAVES={waves[(cb, ck)]}"] if (cb, ck) in waves else [])))
+                                  ([f"-DMESS_PLANE_WAVES={waves[(cb, ck)]}"] if (cb, ck) in waves else []) +
+                                  (["-DMESS_PLANE_SHARE=0"] if real == "float" and (cb, ck) in PLANE_NO_SHARE_F32
+                                   else [])))
         else:
             units.append((src, os.path.join(OBJ, name + ".o"), []))
     # heaviest classes first so the parallel build finishes sooner

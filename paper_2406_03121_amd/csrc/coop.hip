@@ -691,7 +691,8 @@ static int coop_launch(int mode, int cb, int ck, const ClassLaunch &L, int64_t t
         return MESS_OK;
     }
     if (plane_class(cb, ck, prec)) {
-        const size_t lds = sizeof(double) * (size_t)(P->nH + kNHCoef);
+        // H, the coefficients, and 64 lanes' base values (L + 1 each)
+        const size_t lds = sizeof(double) * ((size_t)P->nH + kNHCoef + 64 * (size_t)(P->L + 1));
         launch_plane(mode, cb, ck, prec, A, L, total, (unsigned)g, lds, D, out0, out1);
         MESS_LAUNCH_CHECK();
         return MESS_OK;

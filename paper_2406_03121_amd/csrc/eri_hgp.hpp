@@ -293,25 +293,48 @@ __host__ __device__ constexpr int ket_group_mask(const Cart c) {
 // intermediates are dead before the next starts (fewer live values for the
 // largest classes).  A component is emitted by the pass holding the lowest
 // group below it, so with passes in increasing group order the outputs keep
-// their depth-first order.
-template <class Dm, typename Real, int SUB = 63, class Out>
+// their depth-first order.  With PRE, the base values [00|00]^(m) come
+// from pre[64 m] (written by prim_base for the same primitive quartet, so
+// that passes share one Boys evaluation) instead of being evaluated here.
+//
+// prim_base: the base values [00|00]^(m) = 2 pi^{5/2} K_P K_Q /
+// (p q sqrt(p+q)) F_m(T), m = 0..L, of one primitive quartet.
+template <int L, typename Real>
+__device__ __forceinline__ void prim_base(const PrimPairT<Real> &P, const PrimPairT<Real> &Q, const Real (&AC)[3],
+                                          const BoysTabs &bt, Real (&V0)[L + 1]) {
+    const Real p = P.p, q = Q.p;
+    const Real spq = rsqrt_nr(p + q);
+    const Real rho = p * q * (spq * spq);
+    const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
+    const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    const Real pref = P.Kr * Q.Kr * spq;  // 2 pi^{5/2} K_P K_Q / (p q sqrt(p+q))
+    Real F[L + 1];
+    boys_eval<L, Real>(T, bt, F);
+    static_for<0, L + 1>([&](auto M) { V0[decltype(M)::value] = pref * F[decltype(M)::value]; });
+}
+
+template <class Dm, typename Real, int SUB = 63, bool PRE = false, class Out>
 __device__ __forceinline__ void prim_quartet(const PrimPairT<Real> &P, const PrimPairT<Real> &Q,
-                                                 const Real (&AC)[3], const BoysTabs &bt, Out &&out) {
+                                                 const Real (&AC)[3], const BoysTabs &bt, Out &&out,
+                                                 const Real *pre = nullptr) {
     constexpr int L = Dm::L, NE = Dm::NE, NF = Dm::NF, LA = Dm::LA, LC = Dm::LC, LCD = Dm::LCD;
     const Real p = P.p, q = Q.p;
     const Real pq = p + q;
     const Real spq = rsqrt_nr(pq);
     const Real rpq = spq * spq;
-    const Real rho = p * q * rpq;
     const Real PQx = AC[0] + (P.PAx - Q.PAx), PQy = AC[1] + (P.PAy - Q.PAy), PQz = AC[2] + (P.PAz - Q.PAz);
-    const Real T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
-    const Real pref = P.Kr * Q.Kr * spq;  // 2 pi^{5/2} K_P K_Q / (p q sqrt(p+q))
-
-    Real F[L + 1];
-    boys_eval<L, Real>(T, bt, F);
 
     Real V[NF][NE][L + 1];
-    static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pref * F[decltype(M)::value]; });
+    if constexpr (PRE) {
+        // volatile: each pass reads its own copy, so the compiler does not
+        // merge the passes' recursions into one long-lived set of values
+        const volatile Real *pv = pre;
+        static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = pv[64 * decltype(M)::value]; });
+    } else {
+        Real V0[L + 1];
+        prim_base<L, Real>(P, Q, AC, bt, V0);
+        static_for<0, L + 1>([&](auto M) { V[0][0][decltype(M)::value] = V0[decltype(M)::value]; });
+    }
 
     if constexpr (Dm::LAB > 0) {
         const Real PA[3] = {P.PAx, P.PAy, P.PAz};

@@ -68,6 +68,13 @@ inline constexpr int kPlaneBlockSize = 32;
 template <class Dm>
 inline constexpr int kPlanePasses = MESS_PLANE_PASSES;
 
+// with several passes, the base values [00|00]^(m) are evaluated once per
+// primitive quartet and read by every pass from LDS (MESS_PLANE_SHARE=0:
+// every pass evaluates them itself)
+#ifndef MESS_PLANE_SHARE
+#define MESS_PLANE_SHARE 1
+#endif
+
 // MESS_PLANE_WAVES=n asks for n waves per SIMD (register budget 512 / n)
 #if defined(MESS_PLANE_WAVES)
 #define MESS_PLANE_OCC __attribute__((amdgpu_waves_per_eu(MESS_PLANE_WAVES, MESS_PLANE_WAVES)))
@@ -96,6 +103,9 @@ __global__ void __launch_bounds__(64) MESS_PLANE_OCC k_plane(CoopArgs A, const P
     double *H = lds;
     double *hc = lds + A.nH;
     const int lane = threadIdx.x;
+    // base values [00|00]^(m) of this lane's primitive quartet, element m at
+    // bfl[64 m], shared by the recursion passes (one Boys evaluation)
+    Real *bfl = reinterpret_cast<Real *>(lds + A.nH + kNHCoef) + lane;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         int i, j;
         if (MODE == kModeSchwarz) {
@@ -150,12 +160,21 @@ __global__ void __launch_bounds__(64) MESS_PLANE_OCC k_plane(CoopArgs A, const P
             // classes whose recursion outgrows the registers run it in
             // passes over disjoint subtrees of the ket tree (outputs stay in
             // order, so the reduction blocks are unchanged)
+            constexpr bool PRE = MESS_PLANE_SHARE && kPlanePasses<Dm> > 1;
+            if constexpr (PRE) {
+                Real V0[Dr::L + 1];
+                if constexpr (SW)
+                    prim_base<Dr::L, Real>(Q, P, AC, bt, V0);
+                else
+                    prim_base<Dr::L, Real>(P, Q, AC, bt, V0);
+                static_for<0, Dr::L + 1>([&](auto M) { bfl[64 * decltype(M)::value] = V0[decltype(M)::value]; });
+            }
             auto run = [&](auto SUBC) {
                 constexpr int SUB = decltype(SUBC)::value;
                 if constexpr (SW)
-                    prim_quartet<Dr, Real, SUB>(Q, P, AC, bt, emit);
+                    prim_quartet<Dr, Real, SUB, PRE>(Q, P, AC, bt, emit, bfl);
                 else
-                    prim_quartet<Dr, Real, SUB>(P, Q, AC, bt, emit);
+                    prim_quartet<Dr, Real, SUB, PRE>(P, Q, AC, bt, emit, bfl);
             };
             // passes over second-level ket groups (xx xy xz | yy yz | zz)
             if constexpr (kPlanePasses<Dm> == 2) {
