@@ -60,12 +60,12 @@ int ClassOps<MESS_CB, MESS_CK>::jk(const ClassLaunch &L, const double *D, double
     if (plane_compiled(MESS_CB, MESS_CK) && class_form(MESS_CB, MESS_CK, prec) == kFormPlane)
         return coop_jk(MESS_CB, MESS_CK, L, D, Gj, Gk, prec);
     const BoysTabs bt{L.tab, L.etab, L.tabf, L.etabf, L.tabt};
-    if constexpr (MESS_CB != 2 && MESS_CK != 2 && (MESS_CB <= 3 || MESS_CK == 0)) {
+    if constexpr (!(MESS_CB == 4 && MESS_CK == 3) && !(MESS_CB == 3 && MESS_CK == 2)) {
         // one 256-thread block per bra segment, K rows of the bra functions
         // in LDS and J[a,b] in registers (one flush per segment), so only
-        // J[c,d] takes a global atomic per quartet (measured slower this way:
-        // classes with a pp pair, and dp or dd bras with a ps ket); the
-        // default form of these classes unless the form table says lane
+        // J[c,d] takes a global atomic per quartet (not built for (dp|ds)
+        // and (ds|pp), which spill and run 1.3-2.8x slower this way); the
+        // default form of the low classes unless the form table says lane
         const size_t lds = sizeof(double) * ((size_t)(Dm::NA + Dm::NB) * L.nmax + Dm::NA * Dm::NB);
         if (L.segs && L.nseg > 0 && lds <= 48 * 1024 && class_form(MESS_CB, MESS_CK, prec) == kFormRows) {
             const unsigned g = (unsigned)std::min(L.nseg, 1 << 20);
