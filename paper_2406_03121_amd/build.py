@@ -39,11 +39,15 @@ PLANE_CLASSES = [(5, 4), (5, 3), (5, 2), (5, 1), (4, 4), (4, 2), (2, 2)]
 # 3.27 ms (spill 1.6 KB -> 640 -> 152 B per lane), (dd|ds) at two waves
 # 7.07 -> 5.65 -> 5.20 (260 -> 148 B), (dp|dp) 1.56 -> 1.44 -> 1.43,
 # (dd|pp) 1.15 -> 1.06 (two passes) -> 1.05)
-PLANE_PASSES = {(5, 4): 6, (5, 3): 6, (5, 2): 6, (4, 4): 6}
+PLANE_PASSES = {(5, 4): 6, (5, 3): 6, (5, 2): 6, (4, 4): 6, (4, 2): 3}
 # waves per SIMD asked of the compiler (default: its own choice, one wave
-# with 512 registers here); (dd|ds) runs faster at two waves despite its
-# spill (six passes: 5.26 ms at one wave, 5.20 at two)
-PLANE_WAVES = {(5, 3): 2}
+# with 512 registers here); these run faster at two waves despite their
+# spill, with the passes sharing one Boys evaluation (measured on one box,
+# 60-atom build / 1024-molecule batch step: (dd|ds) 7.37 -> 4.81 ms;
+# (dp|pp) with three passes 1.06 -> 0.64 / 63 -> 37 ms, (dp|dp) 1.44 ->
+# 1.15 / 32 -> 23, (dd|pp) 1.02 -> 0.73 / 22 -> 15; (dd|ps) with passes at
+# three waves and (pp|pp) with passes were slower)
+PLANE_WAVES = {(5, 3): 2, (4, 2): 2, (4, 4): 2, (5, 2): 2}
 # the FP32 kernels need half the registers, so more of their waves fit a
 # SIMD (measured per 60-atom FP32 build: (dd|ds) 4.22 -> 3.27 ms at three
 # waves, (dd|dp) 2.60 -> 1.43 at two, (dp|pp) 0.55 -> 0.41, (dp|dp) 0.80 ->
